@@ -1,0 +1,299 @@
+"""Benchmark: injection + Jacobian evaluations per second at 100k buses.
+
+One step = one evaluation of S = P + jQ and all Jacobian values of a
+100,000-bus, 130,000-branch synthetic grid (one voltage state) by the
+element-wise method: one kernel launch.  To keep every step cold in the
+256 MB Infinity Cache, steps rotate over R independent replicas of the
+problem (grid data, state and outputs), R x 23 MB >= 512 MB.
+
+Printed (one JSON line): evals/s, the roofline of the dominant kernel
+(algorithmic bytes per launch / average launch time, HIP events on the
+launch stream), the CPU oracle's rate on the host, and side measurements:
+the Ybus method under the same protocol, warm-cache rates, 512 batched
+states on a 20k-bus grid, 64 uneven grids x 4 states, and the adjoint
+(32 states at 100k buses) against its forward pass.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+
+
+def algorithmic_bytes(nb, nl, nnz_y, nstate, with_j=True, method="ew", vjp=False):
+    """Bytes the method must move: state in/out, problem data once, outputs.
+
+    element-wise S+J: B (16 nb [vm, va] + 16 nb [P, Q] + 8 nnzJ) + 48 nl [from, to,
+    r, x, b, tap, shift] + 16 nb [shunts] + 4 (nb + 1) [row pointer];
+    Ybus S+J: B (32 nb + 8 nnzJ) + 20 nnzY [column + complex value] + 4 (nb + 1);
+    adjoint: B (32 nb in + 16 nb out) + grid data."""
+    nnz_j = 4 * nnz_y
+    per_state = 32 * nb + (8 * nnz_j if with_j else 0)
+    if vjp:
+        per_state = 48 * nb
+    if method == "ybus":
+        grid = 20 * nnz_y + 4 * (nb + 1)
+    else:
+        grid = 48 * nl + 16 * nb + 4 * (nb + 1)
+    return nstate * per_state + grid
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--replicas", type=int, default=24)
+    ap.add_argument("--no-extra", action="store_true", help="only the headline measurement")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--only", default="", help="comma list of side measurements to run")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the library runs on a single "
+              "MI355X and has no multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2302_10736_amd import gridgen, pf
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)
+
+    # ------------------------------------------------------------ workload
+    g = gridgen.config1()
+    vm, va = gridgen.states(g.nb, 1, cfg=1)
+    R = max(1, args.replicas)
+    reps = []
+    for r in range(R):
+        G = pf.Grid.from_grid(g)
+        reps.append(dict(
+            G=G,
+            vm=torch.as_tensor(vm, device=dev).clone(), va=torch.as_tensor(va, device=dev).clone(),
+            p=torch.empty(1, g.nb, dtype=torch.float64, device=dev),
+            q=torch.empty(1, g.nb, dtype=torch.float64, device=dev),
+            j=torch.empty(1, G.nnz_j, dtype=torch.float64, device=dev)))
+    G0 = reps[0]["G"]
+    nnz_y, nnz_j = G0.nnz_y, G0.nnz_j
+    tile, spb, ntiles = G0.schedule()
+    log(f"grid nb={g.nb} nl={g.nl} nnzY={nnz_y} nnzJ={nnz_j} tiles={ntiles} replicas={R}")
+
+    def timed(fn, steps, warmup):
+        for k in range(warmup):
+            fn(k)
+        torch.cuda.synchronize()
+        s = torch.cuda.current_stream()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(s)
+        for k in range(steps):
+            fn(k)
+        e1.record(s)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        return e0.elapsed_time(e1) / 1e3, wall
+
+    def ew_sj(k):
+        d = reps[k % R]
+        pf.pf_jacobian_values(d["G"], pf.PF_METHOD_ELEMENTWISE, d["vm"], d["va"], d["p"], d["q"], d["j"])
+
+    K, W = args.steps, args.warmup
+    ev_s, wall_s = timed(ew_sj, K, W)
+    value = K / wall_s
+    avg_launch = ev_s / K
+    abytes = algorithmic_bytes(g.nb, g.nl, nnz_y, 1)
+    achieved = abytes / avg_launch / 1e9
+    log(f"element-wise S+J: {avg_launch * 1e6:.2f} us/launch (events), {value:.0f} evals/s (wall)")
+
+    # traffic measured by rocprofv3 counters for this exact kernel source, if recorded
+    traffic = None
+    ksrc = os.path.join(ROOT, "paper_2302_10736_amd", "csrc", "pf_kernels.hip")
+    khash = hashlib.sha256(open(ksrc, "rb").read()).hexdigest()[:16]
+    tfile = os.path.join(ROOT, "profiles", "k_ew_cfg1_100k_traffic.json")
+    if os.path.exists(tfile):
+        t = json.load(open(tfile))
+        if t.get("kernel_sha256_16") == khash:
+            traffic = t.get("bytes_per_launch")
+
+    out = {
+        "metric": "S+Jacobian evals/s at 100k buses, % HBM peak; batched & adjoint vs plain",
+        "value": value,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": wall_s / K * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded generator standing in for the paper's MATPOWER cases)",
+        "config": {"workload": "100k-bus grid (nb=100000, nl=130000, 20% transformers), 1 voltage state, "
+                               "element-wise S + full polar Jacobian, one launch per step",
+                   "nb": g.nb, "nl": g.nl, "nnz_y": nnz_y, "nnz_j": nnz_j, "states": 1,
+                   "replicas_rotated": R, "tile_items": tile},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_ew<256,false,true>", "algorithmic_bytes_per_launch": abytes,
+                     "avg_launch_us": avg_launch * 1e6},
+    }
+
+    extra = {}
+    only = set(filter(None, args.only.split(",")))
+    want = (lambda name: not args.no_extra and (not only or name in only))
+
+    if want("ybus"):
+        for d in reps:
+            pf.pf_ybus(d["G"])
+        torch.cuda.synchronize()
+
+        def yb_sj(k):
+            d = reps[k % R]
+            pf.pf_jacobian_values(d["G"], pf.PF_METHOD_YBUS, d["vm"], d["va"], d["p"], d["q"], d["j"])
+        ev, wall = timed(yb_sj, K, W)
+        yb_bytes = algorithmic_bytes(g.nb, g.nl, nnz_y, 1, method="ybus")
+        extra["ybus_sj"] = {"evals_per_s": K / wall, "avg_launch_us": ev / K * 1e6,
+                            "achieved_GBs": yb_bytes / (ev / K) / 1e9, "algorithmic_bytes": yb_bytes,
+                            "ew_speedup_vs_ybus": (ev / K) / avg_launch}
+        log(f"Ybus S+J: {ev / K * 1e6:.2f} us/launch")
+
+    if want("warm"):
+        def ew_warm(k):
+            d = reps[0]
+            pf.pf_jacobian_values(d["G"], pf.PF_METHOD_ELEMENTWISE, d["vm"], d["va"], d["p"], d["q"], d["j"])
+        ev, wall = timed(ew_warm, K, W)
+        extra["ew_sj_warm_cache"] = {"evals_per_s": K / wall, "avg_launch_us": ev / K * 1e6}
+
+        def ew_s(k):
+            d = reps[k % R]
+            pf.pf_injections_elementwise(d["G"], d["vm"], d["va"], d["p"], d["q"])
+        ev, wall = timed(ew_s, K, W)
+        extra["ew_s_only"] = {"evals_per_s": K / wall, "avg_launch_us": ev / K * 1e6,
+                              "achieved_GBs": algorithmic_bytes(g.nb, g.nl, nnz_y, 1, with_j=False) / (ev / K) / 1e9}
+        if "ybus_sj" in extra:
+            def yb_s(k):
+                d = reps[k % R]
+                pf.pf_injections_ybus(d["G"], d["vm"], d["va"], d["p"], d["q"])
+            ev, wall = timed(yb_s, K, W)
+            extra["ybus_s_only"] = {"evals_per_s": K / wall, "avg_launch_us": ev / K * 1e6}
+        log("warm/S-only done")
+
+    del reps
+    torch.cuda.empty_cache()
+
+    if want("batched"):
+        g2 = gridgen.config2()
+        B = 512
+        vm2, va2 = gridgen.states(g2.nb, B, cfg=2, vlo=0.9, vhi=1.1, sigma=0.3)
+        G2 = pf.Grid.from_grid(g2)
+        vm2d, va2d = torch.as_tensor(vm2, device=dev), torch.as_tensor(va2, device=dev)
+        p2 = torch.empty(B, g2.nb, dtype=torch.float64, device=dev)
+        q2 = torch.empty_like(p2)
+        j2 = torch.empty(B, G2.nnz_j, dtype=torch.float64, device=dev)
+
+        def b_sj(k):
+            pf.pf_jacobian_values(G2, pf.PF_METHOD_ELEMENTWISE, vm2d, va2d, p2, q2, j2)
+        steps = max(20, K // 40)
+        ev, wall = timed(b_sj, steps, 5)
+        bb = algorithmic_bytes(g2.nb, g2.nl, G2.nnz_y, B)
+        extra["batched_20k_x512"] = {"state_evals_per_s": B * steps / wall, "avg_launch_us": ev / steps * 1e6,
+                                     "achieved_GBs": bb / (ev / steps) / 1e9,
+                                     "frac_hbm": bb / (ev / steps) / 1e9 / HBM_PEAK_GBS,
+                                     "algorithmic_bytes": bb, "schedule": G2.schedule()}
+        log(f"batched: {ev / steps * 1e6:.1f} us/launch")
+        del vm2d, va2d, p2, q2, j2, G2
+        torch.cuda.empty_cache()
+
+    if want("multigrid"):
+        grids = gridgen.config3()
+        big, bo, ro = gridgen.concat(grids)
+        G3 = pf.Grid.from_grid(big, bo, ro)
+        vm3 = np.concatenate([gridgen.states(gr.nb, 4, cfg=3, grid=k + 1)[0] for k, gr in enumerate(grids)], axis=1)
+        va3 = np.concatenate([gridgen.states(gr.nb, 4, cfg=3, grid=k + 1)[1] for k, gr in enumerate(grids)], axis=1)
+        vm3d, va3d = torch.as_tensor(vm3, device=dev), torch.as_tensor(va3, device=dev)
+        p3 = torch.empty(4, big.nb, dtype=torch.float64, device=dev)
+        q3 = torch.empty_like(p3)
+        j3 = torch.empty(4, G3.nnz_j, dtype=torch.float64, device=dev)
+
+        def m_sj(k):
+            pf.pf_jacobian_values(G3, pf.PF_METHOD_ELEMENTWISE, vm3d, va3d, p3, q3, j3)
+        steps = max(20, K // 40)
+        ev, wall = timed(m_sj, steps, 5)
+        mb = algorithmic_bytes(big.nb, big.nl, G3.nnz_y, 4)
+        extra["multigrid_64x4"] = {"grid_state_evals_per_s": 256 * steps / wall, "avg_launch_us": ev / steps * 1e6,
+                                   "achieved_GBs": mb / (ev / steps) / 1e9,
+                                   "frac_hbm": mb / (ev / steps) / 1e9 / HBM_PEAK_GBS, "algorithmic_bytes": mb,
+                                   "buses": big.nb, "branches": big.nl}
+        log(f"multigrid: {ev / steps * 1e6:.1f} us/launch")
+        del vm3d, va3d, p3, q3, j3, G3
+        torch.cuda.empty_cache()
+
+    if want("adjoint"):
+        B = 32
+        vm4, va4 = gridgen.states(g.nb, B, cfg=4)
+        lp4, lq4 = gridgen.adjoint_seeds(g.nb, B, cfg=4)
+        G4 = pf.Grid.from_grid(g)
+        t = lambda a: torch.as_tensor(a, device=dev)
+        vm4d, va4d, lp4d, lq4d = t(vm4), t(va4), t(lp4), t(lq4)
+        p4 = torch.empty_like(vm4d)
+        q4 = torch.empty_like(vm4d)
+        gv = torch.empty_like(vm4d)
+        ga = torch.empty_like(vm4d)
+        steps = max(50, K // 20)
+        ev_f, _ = timed(lambda k: pf.pf_injections_elementwise(G4, vm4d, va4d, p4, q4), steps, 5)
+        ev_b, _ = timed(lambda k: pf.pf_injections_vjp(G4, vm4d, va4d, lp4d, lq4d, gv, ga), steps, 5)
+        fb = algorithmic_bytes(g.nb, g.nl, G4.nnz_y, B, with_j=False)
+        bb = algorithmic_bytes(g.nb, g.nl, G4.nnz_y, B, vjp=True)
+        extra["adjoint_100k_x32"] = {"forward_us": ev_f / steps * 1e6, "vjp_us": ev_b / steps * 1e6,
+                                     "vjp_over_forward": ev_b / ev_f,
+                                     "forward_GBs": fb / (ev_f / steps) / 1e9, "vjp_GBs": bb / (ev_b / steps) / 1e9}
+        log(f"adjoint: fwd {ev_f / steps * 1e6:.1f} us, vjp {ev_b / steps * 1e6:.1f} us")
+
+    if extra:
+        out["extra"] = extra
+
+    if not args.no_cpu:
+        import oracle
+        yb = oracle.ybus(g)
+        pat = oracle.jac_pattern(yb)
+        n = 0
+        t0 = time.perf_counter()
+        while True:
+            oracle.inject_ew(g, vm[0], va[0])
+            oracle.jac_ew(g, vm[0], va[0], pat)
+            n += 1
+            el = time.perf_counter() - t0
+            if el >= args.cpu_seconds:
+                break
+        cpu_model = platform.processor() or ""
+        try:
+            for line in open("/proc/cpuinfo"):
+                if line.startswith("model name"):
+                    cpu_model = line.split(":", 1)[1].strip()
+                    break
+        except OSError:
+            pass
+        out["cpu_baseline"] = {"value": n / el, "unit": "evals/s", "cores": 1, "kind": "oracle",
+                               "sample": f"{n} full element-wise S+J evaluations of the same 100k-bus grid and state "
+                                         f"({el:.1f} s, one thread, {cpu_model}, nproc={os.cpu_count()})"}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,197 @@
+/*
+ * pf.h -- C ABI of the MI355X (gfx950) power-injection and Jacobian library.
+ *
+ * The library computes, for given bus voltage magnitudes v and angles theta,
+ * the complex nodal power injections S = P + jQ and the values of the sparse
+ * polar power-flow Jacobian
+ *     J = [ dP/dtheta  dP/dv ]
+ *         [ dQ/dtheta  dQ/dv ]
+ * by the two methods of "Bus Admittance Matrix Revisited: Is It Outdated on
+ * Modern Computers?" (arXiv 2302.10736):
+ *   - the element-wise method (Section II.B, eqs. (5)-(7); Section IV.C):
+ *     every branch end is evaluated on its own, then reduced onto buses and
+ *     into precomputed Jacobian slots;
+ *   - the Ybus method (Section II.A, eqs. (1)-(4); Section IV.B): a complex
+ *     CSR admittance matrix, S = V conj(Ybus V), and the two-pass Jacobian.
+ * It also offers the adjoint (vector-Jacobian product) of the injections.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Branch model (Section II.B): branch l runs from bus h = fbus[l] to bus
+ *   k = tbus[l]; series admittance y_hk = 1/(r + jx); line charging b is
+ *   split as y_h = y_k = j b/2; an off-nominal ratio m e^{j phi} (m = tap,
+ *   phi = shift in radians) sits on the h side; tap == 0 means m = 1.
+ *   Parallel branches between one bus pair are allowed.
+ * Bus shunts: g_i + j b_i adds v_i^2 (g_i - j b_i) to S_i (the paper's
+ *   eq. (7) has no shunt term; with it, the element-wise sum equals eq. (1)
+ *   with the shunt on the admittance diagonal).
+ * Sign: S_i is the complex power injected into the network at bus i.
+ * Ybus pattern: every diagonal (i, i), kept even when its value is zero,
+ *   plus (h, k) and (k, h) for each branch; parallel branches share an
+ *   entry; columns ascend within a row (Section IV.B.2 keeps such zeros).
+ * Jacobian pattern (eq. (2), size 2nb x 2nb): rows [P_0..P_{nb-1},
+ *   Q_0..Q_{nb-1}], columns [theta_0..theta_{nb-1}, v_0..v_{nb-1}], each of
+ *   the four blocks carrying the Ybus pattern, stored in CSR.  For Ybus
+ *   entry p (0-based position in the Ybus CSR) in row i:
+ *       J11 at yrow[i] + p,          J12 at yrow[i+1] + p,
+ *       J21 at 2 nnzY + yrow[i] + p,  J22 at 2 nnzY + yrow[i+1] + p,
+ *   which is the closed form of the index arrays of Algorithm 2.
+ * Multiple grids: one handle may hold G independent grids (block-diagonal
+ *   concatenation).  Bus-indexed arrays of all grids are concatenated
+ *   (grid g owns [bus_off[g], bus_off[g+1])); each grid keeps its own Ybus
+ *   and J patterns with grid-local rows and columns; grid g's Ybus values
+ *   start at y_off[g] and its J values at 4 y_off[g] (pf_grid_offsets).
+ * States: nstate >= 0 independent voltage states per call.  State arrays are
+ *   row-major [nstate][nb_total]; J values are [nstate][nnz_j_total].
+ * Memory: grid arrays given to pf_build_pattern are host memory, copied
+ *   during the call.  Every state, adjoint seed and output pointer of the
+ *   evaluation calls is a DEVICE pointer on the handle's device, owned by the
+ *   caller, 8-byte aligned (16-byte for jval); outputs must not overlap
+ *   inputs.  `stream` is a hipStream_t (NULL = default stream).
+ * Evaluation calls enqueue work on `stream` and return: they allocate
+ *   nothing, never synchronise and never read device data back, so they may
+ *   be captured in a HIP graph.  The handle holds only read-only data during
+ *   evaluation, so one handle may serve several streams at once.
+ * Results are deterministic: every sum runs in a fixed order set by the
+ *   pattern (bus, then neighbour, then branch), independent of launch shape.
+ * Errors: every call returns a pf_status.  On a validation error nothing is
+ *   written and nothing is launched; pf_last_error() describes it.  Faults of
+ *   earlier asynchronous work surface as PF_EHIP on a later call.  No call
+ *   aborts or throws.
+ */
+#ifndef PF_H
+#define PF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pf_grid pf_grid; /* opaque; owns host and device copies of the grid data */
+
+typedef enum pf_status {
+    PF_OK = 0,
+    PF_EINVAL = 1, /* invalid argument (index range, self loop, non-finite, tap < 0, r = x = 0, NULL) */
+    PF_ENOMEM = 2, /* host or device allocation failed */
+    PF_EHIP = 3,   /* HIP runtime error (including faults of earlier work) or no usable GPU */
+    PF_ESTATE = 4, /* call not valid in the handle's state (e.g. Ybus values not assembled) */
+    PF_EUNSUP = 5  /* valid but unsupported input (see pf_last_error) */
+} pf_status;
+
+typedef enum pf_method {
+    PF_METHOD_ELEMENTWISE = 0, /* eqs. (5)-(7): per branch end, then reduction */
+    PF_METHOD_YBUS = 1         /* eqs. (1), (3), (4): complex CSR SpMV, two-pass Jacobian */
+} pf_method;
+
+enum {
+    PF_BUILD_HOST_ONLY = 1u /* build and validate the pattern on the host only: no device
+                               memory, no GPU needed; evaluation calls return PF_ESTATE */
+};
+
+/* Build a handle: validate the grid, build the Ybus pattern, the Jacobian
+ * pattern (eq. (2)), the bus-sorted branch-end records and the launch
+ * schedule, copy everything to the current HIP device and compute the
+ * per-record branch constants there.  Setup work; not part of the timed
+ * evaluation (the paper pre-builds the pattern once, Section IV.B.2).
+ *   nb, nl        total buses (>= 1) and branches (>= 0) over all grids
+ *   fbus, tbus    int32[nl], 0-based, grid-local bus indices; fbus != tbus
+ *   r, x, b_charging, tap, shift   f64[nl]: p.u. series resistance and
+ *                 reactance (not both 0), total charging susceptance,
+ *                 off-nominal ratio (>= 0, 0 means 1), phase shift (rad)
+ *   gs, bs        f64[nb] bus shunt conductance / susceptance; NULL = 0
+ *   ngrids        >= 1; bus_off, br_off int32[ngrids+1] (NULL when 1):
+ *                 grid g owns buses [bus_off[g], bus_off[g+1]) and branches
+ *                 [br_off[g], br_off[g+1]); offsets start at 0, end at
+ *                 nb / nl, and every grid has at least one bus
+ *   flags         0 or PF_BUILD_HOST_ONLY
+ *   out           receives the handle (set to NULL on error)
+ * Errors: PF_EINVAL, PF_ENOMEM, PF_EHIP, PF_EUNSUP (more than 65535
+ * parallel branches on one bus pair, or more than 2^31 - 1 records). */
+int pf_build_pattern(int32_t nb, int32_t nl, const int32_t *fbus, const int32_t *tbus,
+                     const double *r, const double *x, const double *b_charging,
+                     const double *tap, const double *shift, const double *gs,
+                     const double *bs, int32_t ngrids, const int32_t *bus_off,
+                     const int32_t *br_off, uint32_t flags, pf_grid **out);
+
+/* Release a handle and its device memory.  NULL is allowed.  The caller
+ * must make sure no enqueued work still uses the handle. */
+void pf_grid_free(pf_grid *g);
+
+/* Totals over all grids: buses, Ybus nonzeros, Jacobian nonzeros (4 nnz_y),
+ * number of grids.  Any output pointer may be NULL. */
+int pf_grid_sizes(const pf_grid *g, int64_t *nb, int64_t *nnz_y, int64_t *nnz_j, int32_t *ngrids);
+int pf_pattern_sizes(const pf_grid *g, int64_t *nnz_y, int64_t *nnz_j);
+
+/* Per-grid offsets of the Ybus values (y_off) and of the J values
+ * (j_off = 4 y_off), int64[ngrids+1] host buffers. */
+int pf_grid_offsets(const pf_grid *g, int64_t *y_off, int64_t *j_off);
+
+/* Copy the patterns to caller-allocated HOST buffers, grid after grid, each
+ * with grid-local rows and columns:
+ *   y_rowptr int32[nb_total + ngrids], y_col int32[nnz_y],
+ *   j_rowptr int32[2 nb_total + ngrids], j_col int32[nnz_j].
+ * Any pointer may be NULL to skip that array.  Works on host-only handles. */
+int pf_pattern_export(const pf_grid *g, int32_t *y_rowptr, int32_t *y_col, int32_t *j_rowptr,
+                      int32_t *j_col);
+
+/* Assemble the Ybus values (Section II.A, with branch entries matching
+ * eqs. (5)-(6): Y_hh += (y_h + y_hk)/m^2, Y_hk += -y_hk e^{j phi}/m,
+ * Y_kh += -y_hk e^{-j phi}/m, Y_kk += y_k + y_hk, Y_ii += g_i + j b_i) into
+ * the handle; parallel branches are summed in pattern order.  Must precede
+ * pf_injections_ybus and pf_jacobian_values(PF_METHOD_YBUS).  When y_re /
+ * y_im are non-NULL the values are also copied to those DEVICE buffers
+ * (f64[nnz_y], grid g at y_off[g]).  Enqueued on `stream`. */
+int pf_ybus(pf_grid *g, double *y_re, double *y_im, void *stream);
+
+/* Injections by the element-wise method (eqs. (5)-(7) plus bus shunts).
+ * vm, va: f64[nstate][nb] device; p, q: f64[nstate][nb] device outputs. */
+int pf_injections_elementwise(const pf_grid *g, int32_t nstate, const double *vm,
+                              const double *va, double *p, double *q, void *stream);
+
+/* Injections by the Ybus method (Section IV.B.1: U = e^{j theta},
+ * V = v U, I = Ybus V, S = V conj(I)).  PF_ESTATE before pf_ybus. */
+int pf_injections_ybus(const pf_grid *g, int32_t nstate, const double *vm, const double *va,
+                       double *p, double *q, void *stream);
+
+/* Injections and Jacobian values in one pass.
+ *   method  PF_METHOD_ELEMENTWISE: the 16 partial derivatives per branch
+ *           (Section II.B), reduced into the J slots (Section IV.C.2);
+ *           PF_METHOD_YBUS: eqs. (3)-(4) by the row-wise two-pass scheme
+ *           (Section IV.B.2), written in place into J (PF_ESTATE before
+ *           pf_ybus).
+ *   p, q    f64[nstate][nb] device outputs, or NULL to skip
+ *   jval    f64[nstate][nnz_j] device output in the exported CSR order. */
+int pf_jacobian_values(const pf_grid *g, int32_t method, int32_t nstate, const double *vm,
+                       const double *va, double *p, double *q, double *jval, void *stream);
+
+/* Adjoint of the injections: for seeds lam_p, lam_q (f64[nstate][nb]),
+ *   g_va = J11^T lam_p + J21^T lam_q,   g_vm = J12^T lam_p + J22^T lam_q,
+ * i.e. the gradient of sum_i (lam_p_i P_i + lam_q_i Q_i) with respect to
+ * (va, vm), without forming J.  Outputs f64[nstate][nb] device. */
+int pf_injections_vjp(const pf_grid *g, int32_t nstate, const double *vm, const double *va,
+                      const double *lam_p, const double *lam_q, double *g_vm, double *g_va,
+                      void *stream);
+
+/* Launch schedule.  tile_items: records per work tile (64, 128, 256 or
+ * 512; also the workgroup size); states_per_block: voltage states one
+ * workgroup evaluates with the tile's constants held in registers
+ * (>= 1; 0 = automatic).  Changing the schedule never changes results.
+ * Rebuilds the tile list on the host and device; not for use while work
+ * on the handle is in flight. */
+int pf_set_schedule(pf_grid *g, int32_t tile_items, int32_t states_per_block);
+int pf_get_schedule(const pf_grid *g, int32_t *tile_items, int32_t *states_per_block,
+                    int32_t *ntiles);
+
+/* Description of the last error on the calling thread ("" if none).  The
+ * string stays valid until the next pf_* call on that thread. */
+const char *pf_last_error(void);
+
+/* Library version string. */
+const char *pf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PF_H */

@@ -1,0 +1,649 @@
+// Host side of the C ABI declared in include/pf.h: input validation, the
+// Ybus / Jacobian patterns, the bus-sorted branch-end records, the tile
+// schedule, device upload and the launch of the evaluation kernels.
+//
+// Setup follows the paper's advice to build the sparsity pattern once and
+// reuse it (Section IV.B.2, Algorithm 2; Section IV.C.2): nothing here runs
+// in the evaluation calls except argument checks and one kernel launch.
+
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/pf.h"
+#include "pf_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    return fail(PF_EHIP, std::string(what) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")");
+}
+
+// Device arrays are carved from one allocation; each array starts on a
+// 256-byte boundary.
+struct Arena {
+    size_t off = 0;
+    template <class T>
+    size_t take(size_t n) {
+        size_t o = (off + 255) & ~size_t(255);
+        off = o + n * sizeof(T);
+        return o;
+    }
+};
+
+}  // namespace
+
+struct pf_grid {
+    int32_t nb = 0, nl = 0, ngrids = 1;
+    int64_t nnz_y = 0, nitems = 0;
+    bool has_parallel = false;
+    bool host_only = false;
+    bool ybus_valid = false;
+    int device = -1;
+
+    std::vector<int32_t> bus_off, br_off;  // [G+1]
+    std::vector<int64_t> y_off;            // [G+1]
+    std::vector<int32_t> yrow, ycol;       // global numbering
+    std::vector<int32_t> irow, nbr, slot, item_br;
+    std::vector<int32_t> slot_row, slot_item;
+
+    int32_t tile_items = 256, states_per_block = 0;
+    std::vector<int32_t> tile_row, tile_grid;
+
+    void *dmem = nullptr;   // grid data
+    void *dtile = nullptr;  // schedule
+    pf::DevGrid dev{};
+    pf::DevSetup setup{};  // device view used by the setup kernels
+};
+
+namespace {
+
+bool finite_all(const double *a, int64_t n) {
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(a[i])) return false;
+    return true;
+}
+
+// Greedy row-aligned tiles inside each grid: a tile holds whole rows with at
+// most `cap` records in total; a row with more records than `cap` forms a
+// tile of its own, which the kernels walk in chunks.
+void build_tiles(pf_grid *g, int cap) {
+    g->tile_row.clear();
+    g->tile_grid.clear();
+    for (int32_t gi = 0; gi < g->ngrids; ++gi) {
+        int32_t r = g->bus_off[gi], end = g->bus_off[gi + 1];
+        int32_t start = r;
+        int64_t cnt = 0;
+        auto close = [&](int32_t upto) {
+            if (upto > start) {
+                g->tile_row.push_back(start);
+                g->tile_grid.push_back(gi);
+            }
+            start = upto;
+            cnt = 0;
+        };
+        for (; r < end; ++r) {
+            int64_t n = g->irow[r + 1] - g->irow[r];
+            if (n > cap) {
+                close(r);
+                close(r + 1);
+                continue;
+            }
+            if (cnt + n > cap) close(r);
+            cnt += n;
+        }
+        close(end);
+    }
+    g->tile_row.push_back(g->nb);
+}
+
+int upload_tiles(pf_grid *g) {
+    if (g->host_only) return PF_OK;
+    hipError_t e;
+    if (g->dtile) {
+        e = hipFree(g->dtile);
+        g->dtile = nullptr;
+        if (e != hipSuccess) return hip_fail(e, "hipFree(schedule)");
+    }
+    size_t nt = g->tile_grid.size();
+    size_t bytes = (2 * nt + 1) * sizeof(int32_t);
+    e = hipMalloc(&g->dtile, bytes);
+    if (e != hipSuccess) {
+        g->dtile = nullptr;
+        return e == hipErrorOutOfMemory ? fail(PF_ENOMEM, "device allocation of the schedule failed")
+                                        : hip_fail(e, "hipMalloc(schedule)");
+    }
+    auto *base = static_cast<int32_t *>(g->dtile);
+    e = hipMemcpy(base, g->tile_row.data(), (nt + 1) * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess && nt)
+        e = hipMemcpy(base + nt + 1, g->tile_grid.data(), nt * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(schedule)");
+    g->dev.tile_row = base;
+    g->dev.tile_grid = base + nt + 1;
+    g->dev.ntiles = (int32_t)nt;
+    return PF_OK;
+}
+
+int validate(int32_t nb, int32_t nl, const int32_t *fbus, const int32_t *tbus, const double *r,
+             const double *x, const double *b, const double *tap, const double *shift, const double *gs,
+             const double *bs, int32_t ngrids, const int32_t *bus_off, const int32_t *br_off,
+             uint32_t flags) {
+    if (flags & ~uint32_t(PF_BUILD_HOST_ONLY)) return fail(PF_EINVAL, "unknown flag bits");
+    if (nb <= 0) return fail(PF_EINVAL, "nb must be >= 1");
+    if (nl < 0) return fail(PF_EINVAL, "nl must be >= 0");
+    if (ngrids <= 0) return fail(PF_EINVAL, "ngrids must be >= 1");
+    if (ngrids > nb) return fail(PF_EINVAL, "every grid needs at least one bus (ngrids > nb)");
+    if (nl > 0 && (!fbus || !tbus || !r || !x || !b || !tap || !shift))
+        return fail(PF_EINVAL, "branch arrays must not be NULL when nl > 0");
+    if (ngrids > 1 && (!bus_off || !br_off)) return fail(PF_EINVAL, "bus_off and br_off are required when ngrids > 1");
+    if (ngrids > 1) {
+        if (bus_off[0] != 0 || bus_off[ngrids] != nb) return fail(PF_EINVAL, "bus_off must run from 0 to nb");
+        if (br_off[0] != 0 || br_off[ngrids] != nl) return fail(PF_EINVAL, "br_off must run from 0 to nl");
+        for (int32_t k = 0; k < ngrids; ++k) {
+            if (bus_off[k + 1] <= bus_off[k]) return fail(PF_EINVAL, "bus_off must be strictly increasing");
+            if (br_off[k + 1] < br_off[k]) return fail(PF_EINVAL, "br_off must be non-decreasing");
+        }
+    }
+    int32_t gk = 0;
+    for (int32_t l = 0; l < nl; ++l) {
+        if (ngrids > 1)
+            while (l >= br_off[gk + 1]) ++gk;
+        int32_t nbg = ngrids > 1 ? bus_off[gk + 1] - bus_off[gk] : nb;
+        if (fbus[l] < 0 || fbus[l] >= nbg || tbus[l] < 0 || tbus[l] >= nbg)
+            return fail(PF_EINVAL, "branch " + std::to_string(l) + ": bus index out of range");
+        if (fbus[l] == tbus[l]) return fail(PF_EINVAL, "branch " + std::to_string(l) + ": from == to");
+        if (!std::isfinite(r[l]) || !std::isfinite(x[l]) || !std::isfinite(b[l]) || !std::isfinite(tap[l]) ||
+            !std::isfinite(shift[l]))
+            return fail(PF_EINVAL, "branch " + std::to_string(l) + ": non-finite parameter");
+        if (tap[l] < 0) return fail(PF_EINVAL, "branch " + std::to_string(l) + ": tap < 0");
+        if (r[l] == 0.0 && x[l] == 0.0) return fail(PF_EINVAL, "branch " + std::to_string(l) + ": r = x = 0");
+    }
+    if (gs && !finite_all(gs, nb)) return fail(PF_EINVAL, "non-finite bus shunt conductance");
+    if (bs && !finite_all(bs, nb)) return fail(PF_EINVAL, "non-finite bus shunt susceptance");
+    if ((int64_t)nb + 2 * (int64_t)nl > INT32_MAX) return fail(PF_EUNSUP, "more than 2^31-1 records");
+    if (4 * ((int64_t)nb + 2 * (int64_t)nl) > INT32_MAX) return fail(PF_EUNSUP, "Jacobian larger than 2^31-1 entries");
+    return PF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *pf_last_error(void) { return g_err.c_str(); }
+
+const char *pf_version(void) { return "pf-mi355x 0.1 (gfx950, FP64)"; }
+
+int pf_build_pattern(int32_t nb, int32_t nl, const int32_t *fbus, const int32_t *tbus, const double *r,
+                     const double *x, const double *b, const double *tap, const double *shift, const double *gs,
+                     const double *bs, int32_t ngrids, const int32_t *bus_off, const int32_t *br_off,
+                     uint32_t flags, pf_grid **out) {
+    g_err.clear();
+    if (!out) return fail(PF_EINVAL, "out must not be NULL");
+    *out = nullptr;
+    int st = validate(nb, nl, fbus, tbus, r, x, b, tap, shift, gs, bs, ngrids, bus_off, br_off, flags);
+    if (st) return st;
+
+    pf_grid *g = new (std::nothrow) pf_grid;
+    if (!g) return fail(PF_ENOMEM, "host allocation failed");
+    try {
+        g->nb = nb;
+        g->nl = nl;
+        g->ngrids = ngrids;
+        g->host_only = (flags & PF_BUILD_HOST_ONLY) != 0;
+        g->bus_off.assign(ngrids + 1, 0);
+        g->br_off.assign(ngrids + 1, 0);
+        if (ngrids > 1) {
+            std::copy(bus_off, bus_off + ngrids + 1, g->bus_off.begin());
+            std::copy(br_off, br_off + ngrids + 1, g->br_off.begin());
+        } else {
+            g->bus_off[1] = nb;
+            g->br_off[1] = nl;
+        }
+        // Global bus numbers of both branch ends.
+        std::vector<int32_t> gf(nl), gt(nl);
+        for (int32_t k = 0; k < ngrids; ++k)
+            for (int32_t l = g->br_off[k]; l < g->br_off[k + 1]; ++l) {
+                gf[l] = fbus[l] + g->bus_off[k];
+                gt[l] = tbus[l] + g->bus_off[k];
+            }
+        // Records per bus: one shunt record + one per incident branch end.
+        const int64_t ni = (int64_t)nb + 2 * (int64_t)nl;
+        g->nitems = ni;
+        g->irow.assign(nb + 1, 0);
+        for (int32_t i = 0; i < nb; ++i) g->irow[i + 1] = 1;
+        for (int32_t l = 0; l < nl; ++l) {
+            g->irow[gf[l] + 1]++;
+            g->irow[gt[l] + 1]++;
+        }
+        for (int32_t i = 0; i < nb; ++i) g->irow[i + 1] += g->irow[i];
+        // Sort key inside a bus: (neighbour, branch, end); the shunt record
+        // has neighbour == own bus and sorts before nothing else with it.
+        std::vector<int64_t> key(ni);
+        std::vector<int32_t> fill(g->irow.begin(), g->irow.end() - 1);
+        g->nbr.assign(ni, 0);
+        g->item_br.assign(ni, 0);
+        for (int32_t i = 0; i < nb; ++i) {
+            int32_t e = fill[i]++;
+            key[e] = ((int64_t)i << 32) | 0;  // shunt record first among equal neighbours
+            g->nbr[e] = i;
+            g->item_br[e] = -1;
+        }
+        for (int32_t l = 0; l < nl; ++l) {
+            int32_t e = fill[gf[l]]++;
+            key[e] = ((int64_t)gt[l] << 32) | (uint32_t)(2 * l + 1);
+            g->nbr[e] = gt[l];
+            g->item_br[e] = 2 * l;  // from end
+            e = fill[gt[l]]++;
+            key[e] = ((int64_t)gf[l] << 32) | (uint32_t)(2 * l + 2);
+            g->nbr[e] = gf[l];
+            g->item_br[e] = 2 * l + 1;  // to end
+        }
+        std::vector<int32_t> perm;
+        for (int32_t i = 0; i < nb; ++i) {
+            int32_t a = g->irow[i], z = g->irow[i + 1];
+            perm.resize(z - a);
+            for (int32_t t = 0; t < z - a; ++t) perm[t] = a + t;
+            std::sort(perm.begin(), perm.end(), [&](int32_t u, int32_t v) { return key[u] < key[v]; });
+            std::vector<int32_t> nb2(z - a), br2(z - a);
+            for (int32_t t = 0; t < z - a; ++t) {
+                nb2[t] = g->nbr[perm[t]];
+                br2[t] = g->item_br[perm[t]];
+            }
+            std::copy(nb2.begin(), nb2.end(), g->nbr.begin() + a);
+            std::copy(br2.begin(), br2.end(), g->item_br.begin() + a);
+        }
+        // Slots: distinct neighbours of each bus (parallel branches merge).
+        g->slot.assign(ni, 0);
+        g->yrow.assign(nb + 1, 0);
+        g->ycol.clear();
+        g->ycol.reserve(ni);
+        g->slot_row.clear();
+        g->slot_item.clear();
+        for (int32_t i = 0; i < nb; ++i) {
+            for (int32_t e = g->irow[i]; e < g->irow[i + 1]; ++e) {
+                if (e == g->irow[i] || g->nbr[e] != g->nbr[e - 1]) {
+                    g->ycol.push_back(g->nbr[e]);
+                    g->slot_row.push_back(i);
+                    g->slot_item.push_back(e);
+                }
+                g->slot[e] = (int32_t)g->ycol.size() - 1;
+            }
+            g->yrow[i + 1] = (int32_t)g->ycol.size();
+        }
+        g->nnz_y = (int64_t)g->ycol.size();
+        g->slot_item.push_back((int32_t)ni);
+        g->has_parallel = g->nnz_y != ni;
+        g->y_off.assign(ngrids + 1, 0);
+        for (int32_t k = 0; k <= ngrids; ++k) g->y_off[k] = g->yrow[g->bus_off[k]];
+        build_tiles(g, g->tile_items);
+
+        if (g->host_only) {
+            *out = g;
+            return PF_OK;
+        }
+
+        // ---------------------------------------------------------- device
+        hipError_t e = hipGetDevice(&g->device);
+        if (e != hipSuccess) {
+            delete g;
+            return hip_fail(e, "hipGetDevice");
+        }
+        Arena ar;
+        size_t o_yrow = ar.take<int32_t>(nb + 1), o_irow = ar.take<int32_t>(nb + 1);
+        size_t o_ycol = ar.take<int32_t>(g->nnz_y), o_nbr = ar.take<int32_t>(ni), o_slot = ar.take<int32_t>(ni);
+        size_t o_A = ar.take<double>(ni), o_C = ar.take<double>(ni), o_G = ar.take<double>(ni),
+               o_B = ar.take<double>(ni), o_Gr = ar.take<double>(ni), o_Br = ar.take<double>(ni);
+        size_t o_yre = ar.take<double>(g->nnz_y), o_yim = ar.take<double>(g->nnz_y);
+        size_t o_yoff = ar.take<int64_t>(ngrids + 1);
+        // setup-only arrays
+        size_t o_ibr = ar.take<int32_t>(ni), o_srow = ar.take<int32_t>(g->nnz_y),
+               o_sitem = ar.take<int32_t>(g->nnz_y + 1);
+        size_t o_r = ar.take<double>(nl), o_x = ar.take<double>(nl), o_b = ar.take<double>(nl),
+               o_tap = ar.take<double>(nl), o_sh = ar.take<double>(nl);
+        size_t o_gs = ar.take<double>(nb), o_bs = ar.take<double>(nb);
+        e = hipMalloc(&g->dmem, ar.off);
+        if (e != hipSuccess) {
+            g->dmem = nullptr;
+            delete g;
+            return e == hipErrorOutOfMemory ? fail(PF_ENOMEM, "device allocation failed")
+                                            : hip_fail(e, "hipMalloc(grid)");
+        }
+        char *base = static_cast<char *>(g->dmem);
+        auto up = [&](size_t off, const void *src, size_t bytes) -> hipError_t {
+            if (!bytes) return hipSuccess;
+            return hipMemcpy(base + off, src, bytes, hipMemcpyHostToDevice);
+        };
+        std::vector<double> zeros;
+        const double *gsp = gs, *bsp = bs;
+        if (!gs || !bs) zeros.assign(nb, 0.0);
+        if (!gsp) gsp = zeros.data();
+        if (!bsp) bsp = zeros.data();
+        hipError_t ee = hipSuccess;
+        auto chk = [&](hipError_t x2) {
+            if (ee == hipSuccess) ee = x2;
+        };
+        chk(up(o_yrow, g->yrow.data(), (nb + 1) * 4));
+        chk(up(o_irow, g->irow.data(), (nb + 1) * 4));
+        chk(up(o_ycol, g->ycol.data(), g->nnz_y * 4));
+        chk(up(o_nbr, g->nbr.data(), ni * 4));
+        chk(up(o_slot, g->slot.data(), ni * 4));
+        chk(up(o_yoff, g->y_off.data(), (ngrids + 1) * 8));
+        chk(up(o_ibr, g->item_br.data(), ni * 4));
+        chk(up(o_srow, g->slot_row.data(), g->nnz_y * 4));
+        chk(up(o_sitem, g->slot_item.data(), (g->nnz_y + 1) * 4));
+        chk(up(o_r, r, nl * 8));
+        chk(up(o_x, x, nl * 8));
+        chk(up(o_b, b, nl * 8));
+        chk(up(o_tap, tap, nl * 8));
+        chk(up(o_sh, shift, nl * 8));
+        chk(up(o_gs, gsp, nb * 8));
+        chk(up(o_bs, bsp, nb * 8));
+        if (ee != hipSuccess) {
+            int rc = hip_fail(ee, "hipMemcpy(grid)");
+            pf_grid_free(g);
+            return rc;
+        }
+        auto I32 = [&](size_t o) { return reinterpret_cast<int32_t *>(base + o); };
+        auto F64 = [&](size_t o) { return reinterpret_cast<double *>(base + o); };
+        pf::DevGrid &d = g->dev;
+        d.nb = nb;
+        d.nnz_y = g->nnz_y;
+        d.nnz_j = 4 * g->nnz_y;
+        d.yrow = I32(o_yrow);
+        d.irow = I32(o_irow);
+        d.ycol = I32(o_ycol);
+        d.nbr = I32(o_nbr);
+        d.slot = I32(o_slot);
+        d.A = F64(o_A);
+        d.C = F64(o_C);
+        d.G = F64(o_G);
+        d.B = F64(o_B);
+        d.Gr = F64(o_Gr);
+        d.Br = F64(o_Br);
+        d.yre = F64(o_yre);
+        d.yim = F64(o_yim);
+        d.yoff = reinterpret_cast<const int64_t *>(base + o_yoff);
+
+        pf::DevSetup s{};
+        s.nitems = ni;
+        s.nnz_y = g->nnz_y;
+        s.item_br = I32(o_ibr);
+        s.nbr = I32(o_nbr);
+        s.slot_row = I32(o_srow);
+        s.slot_item = I32(o_sitem);
+        s.irow = I32(o_irow);
+        s.ycol = I32(o_ycol);
+        s.r = F64(o_r);
+        s.x = F64(o_x);
+        s.b = F64(o_b);
+        s.tap = F64(o_tap);
+        s.shift = F64(o_sh);
+        s.gs = F64(o_gs);
+        s.bs = F64(o_bs);
+        s.A = F64(o_A);
+        s.C = F64(o_C);
+        s.G = F64(o_G);
+        s.B = F64(o_B);
+        s.Gr = F64(o_Gr);
+        s.Br = F64(o_Br);
+        s.yre = F64(o_yre);
+        s.yim = F64(o_yim);
+        g->setup = s;
+        e = pf::launch_setup_items(s, nullptr);
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        if (e != hipSuccess) {
+            int rc = hip_fail(e, "record constants kernel");
+            pf_grid_free(g);
+            return rc;
+        }
+        st = upload_tiles(g);
+        if (st) {
+            pf_grid_free(g);
+            return st;
+        }
+        *out = g;
+        return PF_OK;
+    } catch (const std::bad_alloc &) {
+        delete g;
+        return fail(PF_ENOMEM, "host allocation failed");
+    }
+}
+
+void pf_grid_free(pf_grid *g) {
+    if (!g) return;
+    if (g->dmem) (void)hipFree(g->dmem);
+    if (g->dtile) (void)hipFree(g->dtile);
+    delete g;
+}
+
+int pf_grid_sizes(const pf_grid *g, int64_t *nb, int64_t *nnz_y, int64_t *nnz_j, int32_t *ngrids) {
+    g_err.clear();
+    if (!g) return fail(PF_EINVAL, "NULL handle");
+    if (nb) *nb = g->nb;
+    if (nnz_y) *nnz_y = g->nnz_y;
+    if (nnz_j) *nnz_j = 4 * g->nnz_y;
+    if (ngrids) *ngrids = g->ngrids;
+    return PF_OK;
+}
+
+int pf_pattern_sizes(const pf_grid *g, int64_t *nnz_y, int64_t *nnz_j) {
+    return pf_grid_sizes(g, nullptr, nnz_y, nnz_j, nullptr);
+}
+
+int pf_grid_offsets(const pf_grid *g, int64_t *y_off, int64_t *j_off) {
+    g_err.clear();
+    if (!g) return fail(PF_EINVAL, "NULL handle");
+    for (int32_t k = 0; k <= g->ngrids; ++k) {
+        if (y_off) y_off[k] = g->y_off[k];
+        if (j_off) j_off[k] = 4 * g->y_off[k];
+    }
+    return PF_OK;
+}
+
+int pf_pattern_export(const pf_grid *g, int32_t *y_rowptr, int32_t *y_col, int32_t *j_rowptr, int32_t *j_col) {
+    g_err.clear();
+    if (!g) return fail(PF_EINVAL, "NULL handle");
+    int64_t yr = 0, yc = 0, jr = 0, jc = 0;
+    for (int32_t k = 0; k < g->ngrids; ++k) {
+        const int32_t b0 = g->bus_off[k], b1 = g->bus_off[k + 1], nbg = b1 - b0;
+        const int32_t s0 = g->yrow[b0];
+        const int32_t nnzg = g->yrow[b1] - s0;
+        for (int32_t i = b0; i <= b1; ++i) {
+            if (y_rowptr) y_rowptr[yr] = g->yrow[i] - s0;
+            ++yr;
+        }
+        for (int32_t p = s0; p < g->yrow[b1]; ++p) {
+            if (y_col) y_col[yc] = g->ycol[p] - b0;
+            ++yc;
+        }
+        // J rows: P rows then Q rows; row i holds theta columns then v columns.
+        for (int32_t half = 0; half < 2; ++half) {
+            for (int32_t i = b0; i < b1; ++i) {
+                int32_t a = g->yrow[i] - s0, z = g->yrow[i + 1] - s0;
+                if (j_rowptr) j_rowptr[jr] = half * 2 * nnzg + 2 * a;
+                ++jr;
+                if (j_col) {
+                    for (int32_t p = a; p < z; ++p) j_col[jc++] = g->ycol[p + s0] - b0;
+                    for (int32_t p = a; p < z; ++p) j_col[jc++] = g->ycol[p + s0] - b0 + nbg;
+                }
+            }
+        }
+        if (j_rowptr) j_rowptr[jr] = 4 * nnzg;
+        ++jr;
+    }
+    return PF_OK;
+}
+
+int pf_set_schedule(pf_grid *g, int32_t tile_items, int32_t states_per_block) {
+    g_err.clear();
+    if (!g) return fail(PF_EINVAL, "NULL handle");
+    if (tile_items != 64 && tile_items != 128 && tile_items != 256 && tile_items != 512)
+        return fail(PF_EINVAL, "tile_items must be 64, 128, 256 or 512");
+    if (states_per_block < 0) return fail(PF_EINVAL, "states_per_block must be >= 0");
+    g->states_per_block = states_per_block;
+    if (tile_items != g->tile_items) {
+        g->tile_items = tile_items;
+        build_tiles(g, tile_items);
+        return upload_tiles(g);
+    }
+    return PF_OK;
+}
+
+int pf_get_schedule(const pf_grid *g, int32_t *tile_items, int32_t *states_per_block, int32_t *ntiles) {
+    g_err.clear();
+    if (!g) return fail(PF_EINVAL, "NULL handle");
+    if (tile_items) *tile_items = g->tile_items;
+    if (states_per_block) *states_per_block = g->states_per_block;
+    if (ntiles) *ntiles = (int32_t)g->tile_grid.size();
+    return PF_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+int check_eval(const pf_grid *g, int32_t nstate) {
+    if (!g) return fail(PF_EINVAL, "NULL handle");
+    if (g->host_only) return fail(PF_ESTATE, "handle was built with PF_BUILD_HOST_ONLY");
+    if (nstate < 0) return fail(PF_EINVAL, "nstate must be >= 0");
+    if ((int64_t)nstate * 4 * g->nnz_y > INT64_MAX / 16) return fail(PF_EUNSUP, "batch too large");
+    return PF_OK;
+}
+
+int auto_states_per_block(const pf_grid *g, int32_t nstate) {
+    if (g->states_per_block > 0) return std::min<int32_t>(g->states_per_block, std::max(nstate, 1));
+    // Enough workgroups to cover 256 CUs several times over; otherwise keep
+    // the tile constants in registers across as many states as possible.
+    const int64_t nt = std::max<int64_t>(1, (int64_t)g->tile_grid.size());
+    const int64_t want_blocks = 2048;
+    int64_t chunks = std::max<int64_t>(1, (want_blocks + nt - 1) / nt);
+    int64_t spb = std::max<int64_t>(1, (nstate + chunks - 1) / chunks);
+    return (int)std::min<int64_t>(spb, 64);
+}
+
+int run(const pf_grid *g, pf::Launch &L, void *stream) {
+    L.tile_items = g->tile_items;
+    L.has_parallel = g->has_parallel;
+    L.states_per_block = auto_states_per_block(g, L.nstate);
+    if (L.nstate == 0) return PF_OK;
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (cur != g->device) return fail(PF_EINVAL, "current HIP device differs from the handle's device");
+    e = pf::launch_eval(g->dev, L, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return PF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pf_ybus(pf_grid *g, double *y_re, double *y_im, void *stream) {
+    g_err.clear();
+    int st = check_eval(g, 1);
+    if (st) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const pf::DevSetup &d = g->setup;
+    hipError_t e = pf::launch_ybus_assemble(d, s);
+    if (e != hipSuccess) return hip_fail(e, "Ybus assembly launch");
+    if (y_re) {
+        e = hipMemcpyAsync(y_re, g->dev.yre, g->nnz_y * sizeof(double), hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return hip_fail(e, "copy of Ybus real parts");
+    }
+    if (y_im) {
+        e = hipMemcpyAsync(y_im, g->dev.yim, g->nnz_y * sizeof(double), hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return hip_fail(e, "copy of Ybus imaginary parts");
+    }
+    g->ybus_valid = true;
+    return PF_OK;
+}
+
+int pf_injections_elementwise(const pf_grid *g, int32_t nstate, const double *vm, const double *va, double *p,
+                              double *q, void *stream) {
+    g_err.clear();
+    int st = check_eval(g, nstate);
+    if (st) return st;
+    if (nstate > 0 && (!vm || !va || !p || !q)) return fail(PF_EINVAL, "NULL state or output pointer");
+    pf::Launch L{};
+    L.kind = pf::K_EW_S;
+    L.nstate = nstate;
+    L.vm = vm;
+    L.va = va;
+    L.p = p;
+    L.q = q;
+    return run(g, L, stream);
+}
+
+int pf_injections_ybus(const pf_grid *g, int32_t nstate, const double *vm, const double *va, double *p, double *q,
+                       void *stream) {
+    g_err.clear();
+    int st = check_eval(g, nstate);
+    if (st) return st;
+    if (!g->ybus_valid) return fail(PF_ESTATE, "pf_ybus has not been called on this handle");
+    if (nstate > 0 && (!vm || !va || !p || !q)) return fail(PF_EINVAL, "NULL state or output pointer");
+    pf::Launch L{};
+    L.kind = pf::K_YB_S;
+    L.nstate = nstate;
+    L.vm = vm;
+    L.va = va;
+    L.p = p;
+    L.q = q;
+    return run(g, L, stream);
+}
+
+int pf_jacobian_values(const pf_grid *g, int32_t method, int32_t nstate, const double *vm, const double *va,
+                       double *p, double *q, double *jval, void *stream) {
+    g_err.clear();
+    int st = check_eval(g, nstate);
+    if (st) return st;
+    if (method != PF_METHOD_ELEMENTWISE && method != PF_METHOD_YBUS) return fail(PF_EINVAL, "unknown method");
+    if (method == PF_METHOD_YBUS && !g->ybus_valid)
+        return fail(PF_ESTATE, "pf_ybus has not been called on this handle");
+    if (nstate > 0 && (!vm || !va || !jval)) return fail(PF_EINVAL, "NULL state or Jacobian pointer");
+    if ((p == nullptr) != (q == nullptr)) return fail(PF_EINVAL, "p and q must both be given or both be NULL");
+    if (reinterpret_cast<uintptr_t>(jval) % 16) return fail(PF_EINVAL, "jval must be 16-byte aligned");
+    pf::Launch L{};
+    L.kind = method == PF_METHOD_ELEMENTWISE ? pf::K_EW_SJ : pf::K_YB_SJ;
+    L.nstate = nstate;
+    L.vm = vm;
+    L.va = va;
+    L.p = p;
+    L.q = q;
+    L.jval = jval;
+    return run(g, L, stream);
+}
+
+int pf_injections_vjp(const pf_grid *g, int32_t nstate, const double *vm, const double *va, const double *lam_p,
+                      const double *lam_q, double *g_vm, double *g_va, void *stream) {
+    g_err.clear();
+    int st = check_eval(g, nstate);
+    if (st) return st;
+    if (nstate > 0 && (!vm || !va || !lam_p || !lam_q || !g_vm || !g_va))
+        return fail(PF_EINVAL, "NULL state, seed or output pointer");
+    pf::Launch L{};
+    L.kind = pf::K_EW_VJP;
+    L.nstate = nstate;
+    L.vm = vm;
+    L.va = va;
+    L.lp = lam_p;
+    L.lq = lam_q;
+    L.gvm = g_vm;
+    L.gva = g_va;
+    return run(g, L, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,225 @@
+"""Thin Python binding of ``libpf.so`` (argument marshalling only).
+
+Every function mirrors the C entry point of the same name in
+``include/pf.h``; all computation happens in the library's HIP kernels.
+Device arrays are ``torch`` float64 CUDA tensors (PyTorch provides device
+memory and streams only); ``stream=None`` means torch's current stream.
+The library must be built (``python -m paper_2302_10736_amd.build``):
+importing this module without it raises, there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpf.so")
+
+PF_OK, PF_EINVAL, PF_ENOMEM, PF_EHIP, PF_ESTATE, PF_EUNSUP = range(6)
+PF_METHOD_ELEMENTWISE, PF_METHOD_YBUS = 0, 1
+PF_BUILD_HOST_ONLY = 1
+
+EXPORTS = (
+    "pf_build_pattern", "pf_grid_free", "pf_grid_sizes", "pf_pattern_sizes", "pf_grid_offsets",
+    "pf_pattern_export", "pf_ybus", "pf_injections_elementwise", "pf_injections_ybus", "pf_jacobian_values",
+    "pf_injections_vjp", "pf_set_schedule", "pf_get_schedule", "pf_last_error", "pf_version",
+)
+
+
+class PFError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"pf error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing; build it with `python -m paper_2302_10736_amd.build`")
+        # torch bundles its own HIP runtime with the same soname; loading it
+        # first makes libpf.so bind to it, so the process holds one runtime.
+        import torch  # noqa: F401
+        L = C.CDLL(LIB_PATH)
+        P, i32, i64, u32 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32
+        L.pf_build_pattern.argtypes = [i32, i32] + [P] * 9 + [i32, P, P, u32, C.POINTER(P)]
+        L.pf_grid_free.argtypes = [P]
+        L.pf_grid_free.restype = None
+        L.pf_grid_sizes.argtypes = [P, P, P, P, P]
+        L.pf_pattern_sizes.argtypes = [P, P, P]
+        L.pf_grid_offsets.argtypes = [P, P, P]
+        L.pf_pattern_export.argtypes = [P, P, P, P, P]
+        L.pf_ybus.argtypes = [P, P, P, P]
+        L.pf_injections_elementwise.argtypes = [P, i32, P, P, P, P, P]
+        L.pf_injections_ybus.argtypes = [P, i32, P, P, P, P, P]
+        L.pf_jacobian_values.argtypes = [P, i32, i32, P, P, P, P, P, P]
+        L.pf_injections_vjp.argtypes = [P, i32, P, P, P, P, P, P, P]
+        L.pf_set_schedule.argtypes = [P, i32, i32]
+        L.pf_get_schedule.argtypes = [P, P, P, P]
+        L.pf_last_error.restype = C.c_char_p
+        L.pf_last_error.argtypes = []
+        L.pf_version.restype = C.c_char_p
+        L.pf_version.argtypes = []
+        for name in EXPORTS:
+            if name not in ("pf_grid_free", "pf_last_error", "pf_version"):
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def check(rc: int) -> None:
+    if rc != PF_OK:
+        raise PFError(rc, lib().pf_last_error().decode())
+
+
+def _host(a, dtype):
+    return None if a is None else np.ascontiguousarray(a, dtype=dtype)
+
+
+def _hp(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _dev(t, shape=None, name="array"):
+    """Device pointer of a float64 CUDA tensor (or None)."""
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous float64 CUDA tensor")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return C.c_void_p(t.data_ptr())
+
+
+class Grid:
+    """Owner of a ``pf_grid`` handle (pf_build_pattern / pf_grid_free)."""
+
+    def __init__(self, nb, nl, fbus, tbus, r, x, b, tap, shift, gs=None, bs=None, bus_off=None, br_off=None,
+                 host_only=False):
+        self._h = C.c_void_p()
+        arrs = [_host(fbus, np.int32), _host(tbus, np.int32)] + [_host(a, np.float64) for a in (r, x, b, tap, shift)]
+        gsa, bsa = _host(gs, np.float64), _host(bs, np.float64)
+        bo, ro = _host(bus_off, np.int32), _host(br_off, np.int32)
+        ngrids = 1 if bo is None else len(bo) - 1
+        self._keep = (arrs, gsa, bsa, bo, ro)
+        check(lib().pf_build_pattern(int(nb), int(nl), *[_hp(a) for a in arrs], _hp(gsa), _hp(bsa), ngrids,
+                                     _hp(bo), _hp(ro), PF_BUILD_HOST_ONLY if host_only else 0, C.byref(self._h)))
+        self._keep = None
+        n_b, n_y, n_j, n_g = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int32()
+        check(lib().pf_grid_sizes(self._h, C.byref(n_b), C.byref(n_y), C.byref(n_j), C.byref(n_g)))
+        self.nb, self.nnz_y, self.nnz_j, self.ngrids = n_b.value, n_y.value, n_j.value, n_g.value
+
+    @classmethod
+    def from_grid(cls, g, bus_off=None, br_off=None, host_only=False):
+        """From any object with nb, nl, fbus, tbus, r, x, b, tap, shift, gs, bs."""
+        return cls(g.nb, g.nl, g.fbus, g.tbus, g.r, g.x, g.b, g.tap, g.shift, g.gs, g.bs, bus_off, br_off,
+                   host_only)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h and self._h.value:
+            lib().pf_grid_free(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def offsets(self):
+        y = np.zeros(self.ngrids + 1, np.int64)
+        j = np.zeros(self.ngrids + 1, np.int64)
+        check(lib().pf_grid_offsets(self._h, _hp(y), _hp(j)))
+        return y, j
+
+    def pattern(self):
+        """(y_rowptr, y_col, j_rowptr, j_col), grid after grid, grid-local indices."""
+        yr = np.zeros(self.nb + self.ngrids, np.int32)
+        yc = np.zeros(max(self.nnz_y, 1), np.int32)
+        jr = np.zeros(2 * self.nb + self.ngrids, np.int32)
+        jc = np.zeros(max(self.nnz_j, 1), np.int32)
+        check(lib().pf_pattern_export(self._h, _hp(yr), _hp(yc), _hp(jr), _hp(jc)))
+        return yr, yc[: self.nnz_y], jr, jc[: self.nnz_j]
+
+    def set_schedule(self, tile_items=256, states_per_block=0):
+        check(lib().pf_set_schedule(self._h, int(tile_items), int(states_per_block)))
+
+    def schedule(self):
+        a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
+        check(lib().pf_get_schedule(self._h, C.byref(a), C.byref(b), C.byref(c)))
+        return a.value, b.value, c.value
+
+
+def _nstate(vm, nb):
+    if vm.dim() == 1:
+        if vm.shape[0] != nb:
+            raise ValueError("state length differs from nb")
+        return 1
+    if vm.dim() != 2 or vm.shape[1] != nb:
+        raise ValueError("states must be [nstate, nb]")
+    return vm.shape[0]
+
+
+def pf_build_pattern(nb, nl, fbus, tbus, r, x, b, tap, shift, gs=None, bs=None, bus_off=None, br_off=None,
+                     host_only=False) -> Grid:
+    return Grid(nb, nl, fbus, tbus, r, x, b, tap, shift, gs, bs, bus_off, br_off, host_only)
+
+
+def pf_ybus(grid: Grid, y_re=None, y_im=None, stream=None):
+    check(lib().pf_ybus(grid.handle, _dev(y_re, (grid.nnz_y,), "y_re"), _dev(y_im, (grid.nnz_y,), "y_im"),
+                        _stream(stream)))
+
+
+def pf_injections_elementwise(grid: Grid, vm, va, p, q, stream=None):
+    ns = _nstate(vm, grid.nb)
+    shp = tuple(vm.shape)
+    check(lib().pf_injections_elementwise(grid.handle, ns, _dev(vm, shp, "vm"), _dev(va, shp, "va"),
+                                          _dev(p, shp, "p"), _dev(q, shp, "q"), _stream(stream)))
+
+
+def pf_injections_ybus(grid: Grid, vm, va, p, q, stream=None):
+    ns = _nstate(vm, grid.nb)
+    shp = tuple(vm.shape)
+    check(lib().pf_injections_ybus(grid.handle, ns, _dev(vm, shp, "vm"), _dev(va, shp, "va"), _dev(p, shp, "p"),
+                                   _dev(q, shp, "q"), _stream(stream)))
+
+
+def pf_jacobian_values(grid: Grid, method: int, vm, va, p, q, jval, stream=None):
+    ns = _nstate(vm, grid.nb)
+    shp = tuple(vm.shape)
+    jshp = (grid.nnz_j,) if vm.dim() == 1 else (ns, grid.nnz_j)
+    check(lib().pf_jacobian_values(grid.handle, int(method), ns, _dev(vm, shp, "vm"), _dev(va, shp, "va"),
+                                   _dev(p, shp, "p"), _dev(q, shp, "q"), _dev(jval, jshp, "jval"), _stream(stream)))
+
+
+def pf_injections_vjp(grid: Grid, vm, va, lam_p, lam_q, g_vm, g_va, stream=None):
+    ns = _nstate(vm, grid.nb)
+    shp = tuple(vm.shape)
+    check(lib().pf_injections_vjp(grid.handle, ns, _dev(vm, shp, "vm"), _dev(va, shp, "va"),
+                                  _dev(lam_p, shp, "lam_p"), _dev(lam_q, shp, "lam_q"), _dev(g_vm, shp, "g_vm"),
+                                  _dev(g_va, shp, "g_va"), _stream(stream)))
+
+
+def pf_version() -> str:
+    return lib().pf_version().decode()

@@ -1,0 +1,306 @@
+"""GPU parity: every C-ABI call against the CPU oracle, element by element.
+
+Gate: for each output array (P, Q, J values, Ybus values, g_vm, g_va) and
+each state, max|gpu - oracle| <= 1e-12 max|oracle|.  Tiny hand-made grids
+whose sums cancel almost completely (many parallel branches on one bus
+pair) are gated against the largest term instead of the result.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2302_10736_amd import gridgen, pf
+from tests import _grids
+from tests._gpu import TOL, compare_grid, gpu_all, oracle_all, rel_err, require_gpu, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def check_single(g, vm, va, tile=256, spb=0, use_scale=False, lam=True):
+    """Build a handle, run every call on states [ns, nb], compare each state."""
+    G = pf.Grid.from_grid(g)
+    G.set_schedule(tile, spb)
+    ns = vm.shape[0]
+    rng = np.random.default_rng(5)
+    lp = rng.normal(size=vm.shape) if lam else None
+    lq = rng.normal(size=vm.shape) if lam else None
+    gres = gpu_all(G, vm, va, lp, lq)
+    for s in range(ns):
+        ores = oracle_all(g, vm[s], va[s], None if lp is None else lp[s], None if lq is None else lq[s])
+        compare_grid(gres, ores, s, slice(None), slice(None), slice(None), use_scale=use_scale)
+    return gres
+
+
+def test_config0_every_call():
+    g = gridgen.config0()
+    vm, va = gridgen.states(g.nb, 1, cfg=0)
+    check_single(g, vm, va)
+
+
+def star_grid(n_leaf, seed=0, parallel=0):
+    """A hub bus with n_leaf branches (long row) plus a ring among the leaves."""
+    rng = np.random.default_rng(seed)
+    nb = n_leaf + 1
+    f = [0] * n_leaf + list(range(1, nb - 1))
+    t = list(range(1, nb)) + list(range(2, nb))
+    for _ in range(parallel):
+        k = int(rng.integers(0, n_leaf))
+        f.append(0); t.append(k + 1)
+    n = len(f)
+    flip = rng.random(n) < 0.5
+    fb = np.where(flip, t, f).astype(np.int32)
+    tb = np.where(flip, f, t).astype(np.int32)
+    tap = np.where(rng.random(n) < 0.3, rng.uniform(0.9, 1.1, n), 1.0)
+    shift = np.where(tap != 1.0, rng.uniform(-0.1, 0.1, n), 0.0)
+    return gridgen.Grid(nb, n, fb, tb, rng.uniform(0.001, 0.05, n), rng.uniform(0.01, 0.3, n),
+                        rng.uniform(0, 0.1, n), tap, shift, rng.uniform(0, 0.02, nb), rng.uniform(-0.1, 0.1, nb))
+
+
+EDGE_GRIDS = {
+    "parallel_isolated": lambda: _grids.random_small(80, 150, 21, parallel=9, isolated=4),
+    "two_bus": lambda: _grids.two_bus(0.01, 0.1, 0.02, 1.03, 0.04),
+    "two_bus_flip": lambda: _grids.two_bus(0.01, 0.1, 0.02, 1.03, 0.04, flip=True),
+    "many_parallel_pair": lambda: _grids.random_small(2, 30, 2, parallel=10),
+    "hub_700": lambda: star_grid(700, seed=1),
+    "hub_600_parallel": lambda: star_grid(600, seed=2, parallel=40),
+    "ragged_tiles": lambda: _grids.random_small(333, 700, 8, parallel=3, isolated=7),
+}
+
+
+@pytest.mark.parametrize("tile", [64, 128, 256, 512])
+@pytest.mark.parametrize("name", sorted(EDGE_GRIDS))
+def test_edge_grids(name, tile):
+    g = EDGE_GRIDS[name]()
+    vm, va = _grids.random_state(g.nb, 3)
+    use_scale = name == "many_parallel_pair"
+    check_single(g, vm[None, :], va[None, :], tile=tile, use_scale=use_scale)
+
+
+def test_shunt_only_buses():
+    nb = 7
+    gs = np.linspace(0, 0.02, nb)
+    bs = np.linspace(-0.1, 0.1, nb)
+    e = np.zeros(0)
+    g = gridgen.Grid(nb, 0, np.zeros(0, np.int32), np.zeros(0, np.int32), e, e, e, e, e, gs, bs)
+    vm, va = _grids.random_state(nb, 4)
+    gres = check_single(g, vm[None], va[None], lam=True)
+    assert np.allclose(gres["p_ew"][0], vm ** 2 * gs, rtol=1e-15, atol=0)
+    assert np.allclose(gres["q_ew"][0], -(vm ** 2) * bs, rtol=1e-15, atol=0)
+
+
+@pytest.mark.parametrize("spb", [0, 1, 3, 8, 64])
+def test_batched_states_ragged(spb):
+    g = gridgen.config0()
+    vm, va = gridgen.states(g.nb, 37, cfg=0)
+    check_single(g, vm, va, tile=128, spb=spb)
+
+
+def test_zero_states_is_a_no_op():
+    import torch
+    G = pf.Grid.from_grid(gridgen.config0())
+    e = torch.empty(0, G.nb, dtype=torch.float64, device="cuda:0")
+    ej = torch.empty(0, G.nnz_j, dtype=torch.float64, device="cuda:0")
+    pf.pf_injections_elementwise(G, e, e, e, e)
+    pf.pf_jacobian_values(G, pf.PF_METHOD_ELEMENTWISE, e, e, e, e, ej)
+    pf.pf_injections_vjp(G, e, e, e, e, e, e)
+
+
+def test_multigrid_every_call():
+    grids = [_grids.random_small(n, int(n * 1.4), 70 + n, parallel=n % 4, isolated=n % 3) for n in (5, 40, 300, 17, 2)]
+    grids.append(star_grid(530, seed=9))
+    big, bo, ro = gridgen.concat(grids)
+    G = pf.Grid.from_grid(big, bo, ro)
+    assert G.ngrids == len(grids)
+    ns = 3
+    rng = np.random.default_rng(1)
+    vm = rng.uniform(0.9, 1.1, (ns, big.nb))
+    va = rng.normal(0, 0.2, (ns, big.nb))
+    lp = rng.normal(size=vm.shape)
+    lq = rng.normal(size=vm.shape)
+    gres = gpu_all(G, vm, va, lp, lq)
+    y_off, j_off = G.offsets()
+    for k, g in enumerate(grids):
+        bsl = slice(bo[k], bo[k + 1])
+        for s in range(ns):
+            ores = oracle_all(g, vm[s, bsl], va[s, bsl], lp[s, bsl], lq[s, bsl])
+            compare_grid(gres, ores, s, bsl, slice(j_off[k], j_off[k + 1]), slice(y_off[k], y_off[k + 1]),
+                         use_scale=g.nb == 2)
+
+
+def test_determinism_across_runs_and_schedules():
+    g = _grids.random_small(900, 1600, 33, parallel=12, isolated=5)
+    vm, va = _grids.random_state(g.nb, 6)
+    rng = np.random.default_rng(2)
+    vm = np.stack([vm, rng.uniform(0.9, 1.1, g.nb), rng.uniform(0.9, 1.1, g.nb)])
+    va = np.stack([va, rng.normal(0, 0.3, g.nb), rng.normal(0, 0.3, g.nb)])
+    lp, lq = rng.normal(size=vm.shape), rng.normal(size=vm.shape)
+    G = pf.Grid.from_grid(g)
+    ref = gpu_all(G, vm, va, lp, lq)
+    for _ in range(3):
+        again = gpu_all(G, vm, va, lp, lq)
+        for k in ref:
+            assert np.array_equal(ref[k], again[k]), k
+    for tile in (64, 128, 512):
+        for spb in (1, 2):
+            G.set_schedule(tile, spb)
+            other = gpu_all(G, vm, va, lp, lq)
+            for k in ref:
+                assert np.array_equal(ref[k], other[k]), (k, tile, spb)
+
+
+def test_ybus_required_before_ybus_calls():
+    import torch
+    G = pf.Grid.from_grid(gridgen.config0())
+    z = torch.zeros(1, G.nb, dtype=torch.float64, device="cuda:0")
+    with pytest.raises(pf.PFError) as e:
+        pf.pf_injections_ybus(G, z, z, z.clone(), z.clone())
+    assert e.value.code == pf.PF_ESTATE
+    j = torch.zeros(1, G.nnz_j, dtype=torch.float64, device="cuda:0")
+    with pytest.raises(pf.PFError) as e:
+        pf.pf_jacobian_values(G, pf.PF_METHOD_YBUS, z, z, None, None, j)
+    assert e.value.code == pf.PF_ESTATE
+
+
+def test_jval_alignment_checked():
+    import torch
+    G = pf.Grid.from_grid(gridgen.config0())
+    z = torch.zeros(1, G.nb, dtype=torch.float64, device="cuda:0")
+    jbig = torch.zeros(G.nnz_j + 1, dtype=torch.float64, device="cuda:0")
+    rc = pf.lib().pf_jacobian_values(G.handle, 0, 1, z.data_ptr(), z.data_ptr(), None, None,
+                                     jbig.data_ptr() + 8, None)
+    assert rc == pf.PF_EINVAL
+
+
+# ------------------------------------------------------------------ full sizes
+
+def test_config1_full_size():
+    """100k buses, one state, in the benchmark's launch configuration."""
+    g = gridgen.config1()
+    vm, va = gridgen.states(g.nb, 1, cfg=1)
+    G = pf.Grid.from_grid(g)
+    rng = np.random.default_rng(11)
+    lp, lq = rng.normal(size=vm.shape), rng.normal(size=vm.shape)
+    gres = gpu_all(G, vm, va, lp, lq)
+    ores = oracle_all(g, vm[0], va[0], lp[0], lq[0])
+    errs = compare_grid(gres, ores, 0, slice(None), slice(None), slice(None))
+    print(dict(errs))
+
+
+def test_config2_batched_sampled_states():
+    """20k buses x 512 states in one launch; six sampled states compared in full."""
+    import torch
+    g = gridgen.config2()
+    B = 512
+    vm, va = gridgen.states(g.nb, B, cfg=2, vlo=0.9, vhi=1.1, sigma=0.3)
+    G = pf.Grid.from_grid(g)
+    vm_d, va_d = to_dev(vm), to_dev(va)
+    p = torch.empty(B, G.nb, dtype=torch.float64, device="cuda:0")
+    q = torch.empty_like(p)
+    j = torch.empty(B, G.nnz_j, dtype=torch.float64, device="cuda:0")
+    pf.pf_jacobian_values(G, pf.PF_METHOD_ELEMENTWISE, vm_d, va_d, p, q, j)
+    torch.cuda.synchronize()
+    for s in (0, 1, 255, 256, 400, 511):
+        ores = oracle_all(g, vm[s], va[s])
+        assert rel_err(p[s].cpu().numpy(), ores["p_ew"]) <= TOL
+        assert rel_err(q[s].cpu().numpy(), ores["q_ew"]) <= TOL
+        assert rel_err(j[s].cpu().numpy(), ores["j_ew"]) <= TOL
+
+
+def test_config3_uneven_grids():
+    """64 grids (1k-80k buses), 4 states each, one launch; every grid and state compared."""
+    grids = gridgen.config3()
+    big, bo, ro = gridgen.concat(grids)
+    G = pf.Grid.from_grid(big, bo, ro)
+    vm = np.concatenate([gridgen.states(gr.nb, 4, cfg=3, grid=k + 1)[0] for k, gr in enumerate(grids)], axis=1)
+    va = np.concatenate([gridgen.states(gr.nb, 4, cfg=3, grid=k + 1)[1] for k, gr in enumerate(grids)], axis=1)
+    gres = gpu_all(G, vm, va, with_ybus=False)
+    y_off, j_off = G.offsets()
+    for k, gr in enumerate(grids):
+        bsl = slice(bo[k], bo[k + 1])
+        yb = oracle.ybus(gr)
+        pat = oracle.jac_pattern(yb)
+        for s in range(4):
+            p, q = oracle.inject_ew(gr, vm[s, bsl], va[s, bsl])
+            jv = oracle.jac_ew(gr, vm[s, bsl], va[s, bsl], pat)
+            assert rel_err(gres["p_ew"][s, bsl], p) <= TOL
+            assert rel_err(gres["q_ew"][s, bsl], q) <= TOL
+            assert rel_err(gres["j_ew"][s, j_off[k]:j_off[k + 1]], jv) <= TOL
+
+
+def test_config4_vjp_against_oracle_and_fd():
+    """100k buses x 32 states: VJP vs J^T lambda from the oracle Jacobian (sampled
+    states) and vs central differences (h = 1e-7) on 1000 sampled coordinates."""
+    import torch
+    g = gridgen.config1()
+    B = 32
+    vm, va = gridgen.states(g.nb, B, cfg=4)
+    lp, lq = gridgen.adjoint_seeds(g.nb, B, cfg=4)
+    G = pf.Grid.from_grid(g)
+    vm_d, va_d, lp_d, lq_d = map(to_dev, (vm, va, lp, lq))
+    gvm = torch.empty_like(vm_d)
+    gva = torch.empty_like(vm_d)
+    pf.pf_injections_vjp(G, vm_d, va_d, lp_d, lq_d, gvm, gva)
+    torch.cuda.synchronize()
+    gvm_h, gva_h = gvm.cpu().numpy(), gva.cpu().numpy()
+    yb = oracle.ybus(g)
+    pat = oracle.jac_pattern(yb)
+    for s in (0, 13, 31):
+        jv = oracle.jac_ybus(yb, vm[s], va[s], pat)
+        ovm, ova = oracle.vjp(g.nb, pat, jv, lp[s], lq[s])
+        assert rel_err(gvm_h[s], ovm) <= TOL
+        assert rel_err(gva_h[s], ova) <= TOL
+    # central differences of the local objective sum_{i in N(k)} lP_i P_i + lQ_i Q_i
+    coords = gridgen.sample_coords(B, g.nb, 1000, cfg=4)
+    nbrs = [[] for _ in range(g.nb)]
+    for a, c in zip(g.fbus.tolist(), g.tbus.tolist()):
+        nbrs[a].append(c)
+        nbrs[c].append(a)
+    h = 1e-7
+    chunk = 250
+    worst = 0.0
+    for c0 in range(0, len(coords), chunk):
+        cs = coords[c0:c0 + chunk]
+        n = len(cs)
+        vmp = np.repeat(vm[cs[:, 0]], 2, axis=0)
+        vap = np.repeat(va[cs[:, 0]], 2, axis=0)
+        for r, (s, var, k) in enumerate(cs):
+            arr = vmp if var == 0 else vap
+            arr[2 * r, k] += h
+            arr[2 * r + 1, k] -= h
+        vmd, vad = to_dev(vmp), to_dev(vap)
+        p = torch.empty_like(vmd)
+        q = torch.empty_like(vmd)
+        pf.pf_injections_elementwise(G, vmd, vad, p, q)
+        torch.cuda.synchronize()
+        for r, (s, var, k) in enumerate(cs):
+            loc = np.array([k] + nbrs[k])
+            pp = p[2 * r, loc].cpu().numpy() - p[2 * r + 1, loc].cpu().numpy()
+            qq = q[2 * r, loc].cpu().numpy() - q[2 * r + 1, loc].cpu().numpy()
+            fd = (lp[s, loc] @ pp + lq[s, loc] @ qq) / (2 * h)
+            gv = gvm_h[s, k] if var == 0 else gva_h[s, k]
+            err = abs(fd - gv) / (1 + abs(gv))
+            worst = max(worst, err)
+            assert err <= 1e-6, (s, var, k, fd, gv)
+    print("worst FD error", worst)
+
+
+def test_autograd_function():
+    import torch
+    from paper_2302_10736_amd.autograd import injections
+    g = _grids.random_small(12, 20, 4, parallel=2, isolated=1)
+    G = pf.Grid.from_grid(g)
+    vm, va = _grids.random_state(g.nb, 9)
+    vm_t = to_dev(vm[None]).requires_grad_(True)
+    va_t = to_dev(va[None]).requires_grad_(True)
+    assert torch.autograd.gradcheck(lambda a, b: injections(G, a, b), (vm_t, va_t), eps=1e-7, atol=1e-6)
+    P, Q = injections(G, vm_t, va_t)
+    w = torch.linspace(-1, 1, g.nb, dtype=torch.float64, device="cuda:0")
+    (P * w).sum().backward()
+    assert vm_t.grad is not None and va_t.grad is not None
