@@ -90,7 +90,7 @@ def main():
             j=torch.empty(1, G.nnz_j, dtype=torch.float64, device=dev)))
     G0 = reps[0]["G"]
     nnz_y, nnz_j = G0.nnz_y, G0.nnz_j
-    tile, spb, ntiles = G0.schedule()
+    tile, spb, order, ntiles = G0.schedule()
     log(f"grid nb={g.nb} nl={g.nl} nnzY={nnz_y} nnzJ={nnz_j} tiles={ntiles} replicas={R}")
 
     def timed(fn, steps, warmup):

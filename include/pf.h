@@ -106,8 +106,8 @@ enum {
  *                 nb / nl, and every grid has at least one bus
  *   flags         0 or PF_BUILD_HOST_ONLY
  *   out           receives the handle (set to NULL on error)
- * Errors: PF_EINVAL, PF_ENOMEM, PF_EHIP, PF_EUNSUP (more than 65535
- * parallel branches on one bus pair, or more than 2^31 - 1 records). */
+ * Errors: PF_EINVAL, PF_ENOMEM, PF_EHIP, PF_EUNSUP (more than 2^31 - 1
+ * records or Jacobian entries). */
 int pf_build_pattern(int32_t nb, int32_t nl, const int32_t *fbus, const int32_t *tbus,
                      const double *r, const double *x, const double *b_charging,
                      const double *tap, const double *shift, const double *gs,
@@ -173,14 +173,23 @@ int pf_injections_vjp(const pf_grid *g, int32_t nstate, const double *vm, const 
                       const double *lam_p, const double *lam_q, double *g_vm, double *g_va,
                       void *stream);
 
-/* Launch schedule.  tile_items: records per work tile (64, 128, 256 or
- * 512; also the workgroup size); states_per_block: voltage states one
- * workgroup evaluates with the tile's constants held in registers
- * (>= 1; 0 = automatic).  Changing the schedule never changes results.
- * Rebuilds the tile list on the host and device; not for use while work
- * on the handle is in flight. */
-int pf_set_schedule(pf_grid *g, int32_t tile_items, int32_t states_per_block);
-int pf_get_schedule(const pf_grid *g, int32_t *tile_items, int32_t *states_per_block,
+/* Launch schedule.
+ *   tile_items        records per work tile (64, 128, 256 or 512); a
+ *                     workgroup has that many threads
+ *   states_per_block  voltage states one workgroup evaluates in turn, with
+ *                     the tile's constants held in registers (>= 1; 0 =
+ *                     automatic)
+ *   order             order of the (tile, state chunk) work items over the
+ *                     workgroups: PF_ORDER_AUTO, PF_ORDER_TILE_MAJOR (the
+ *                     state chunks of one tile are adjacent) or
+ *                     PF_ORDER_STATE_MAJOR (the tiles of one state chunk are
+ *                     adjacent, so concurrent workgroups write neighbouring
+ *                     parts of J)
+ * Changing the schedule never changes results.  Rebuilds the tile list on
+ * the host and device; not for use while work on the handle is in flight. */
+enum { PF_ORDER_AUTO = 0, PF_ORDER_TILE_MAJOR = 1, PF_ORDER_STATE_MAJOR = 2 };
+int pf_set_schedule(pf_grid *g, int32_t tile_items, int32_t states_per_block, int32_t order);
+int pf_get_schedule(const pf_grid *g, int32_t *tile_items, int32_t *states_per_block, int32_t *order,
                     int32_t *ntiles);
 
 /* Description of the last error on the calling thread ("" if none).  The

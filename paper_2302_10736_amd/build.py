@@ -24,6 +24,10 @@ HIPCC_FLAGS = [
     "-Wall",
     # gfx950 packed FP32 instructions stay off: FP64 code never needs them.
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # No implicit contraction: every fused multiply-add is written out, so
+    # all kernel instantiations (tile sizes, batched or not) round alike and
+    # results are bitwise independent of the schedule.
+    "-ffp-contract=off",
 ]
 
 

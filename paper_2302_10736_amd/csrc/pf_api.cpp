@@ -60,8 +60,9 @@ struct pf_grid {
     std::vector<int32_t> irow, nbr, slot, item_br;
     std::vector<int32_t> slot_row, slot_item;
 
-    int32_t tile_items = 256, states_per_block = 0;
-    std::vector<int32_t> tile_row, tile_grid;
+    int32_t tile_items = 256, states_per_block = 0, order = PF_ORDER_AUTO;
+    std::vector<pf::TileDesc> tiles;
+    int32_t num_cus = 0;
 
     void *dmem = nullptr;   // grid data
     void *dtile = nullptr;  // schedule
@@ -81,16 +82,26 @@ bool finite_all(const double *a, int64_t n) {
 // most `cap` records in total; a row with more records than `cap` forms a
 // tile of its own, which the kernels walk in chunks.
 void build_tiles(pf_grid *g, int cap) {
-    g->tile_row.clear();
-    g->tile_grid.clear();
+    g->tiles.clear();
     for (int32_t gi = 0; gi < g->ngrids; ++gi) {
         int32_t r = g->bus_off[gi], end = g->bus_off[gi + 1];
         int32_t start = r;
         int64_t cnt = 0;
         auto close = [&](int32_t upto) {
             if (upto > start) {
-                g->tile_row.push_back(start);
-                g->tile_grid.push_back(gi);
+                pf::TileDesc d;
+                d.r0 = start;
+                d.nrows = upto - start;
+                d.i0 = g->irow[start];
+                d.n = g->irow[upto] - d.i0;
+                d.s0 = g->yrow[start];
+                d.ns = g->yrow[upto] - d.s0;
+                // Grid gi's J values start at 4 y_off[gi]; its P rows hold
+                // 2 nnz_y(gi) values, so row i's P part starts at
+                // 2 y_off[gi] + 2 yrow[i] and its Q part at 2 y_off[gi+1] + 2 yrow[i].
+                d.jp = 2 * g->y_off[gi] + 2 * (int64_t)d.s0;
+                d.jq = 2 * g->y_off[gi + 1] + 2 * (int64_t)d.s0;
+                g->tiles.push_back(d);
             }
             start = upto;
             cnt = 0;
@@ -107,7 +118,6 @@ void build_tiles(pf_grid *g, int cap) {
         }
         close(end);
     }
-    g->tile_row.push_back(g->nb);
 }
 
 int upload_tiles(pf_grid *g) {
@@ -118,21 +128,17 @@ int upload_tiles(pf_grid *g) {
         g->dtile = nullptr;
         if (e != hipSuccess) return hip_fail(e, "hipFree(schedule)");
     }
-    size_t nt = g->tile_grid.size();
-    size_t bytes = (2 * nt + 1) * sizeof(int32_t);
+    size_t nt = g->tiles.size();
+    size_t bytes = nt * sizeof(pf::TileDesc);
     e = hipMalloc(&g->dtile, bytes);
     if (e != hipSuccess) {
         g->dtile = nullptr;
         return e == hipErrorOutOfMemory ? fail(PF_ENOMEM, "device allocation of the schedule failed")
                                         : hip_fail(e, "hipMalloc(schedule)");
     }
-    auto *base = static_cast<int32_t *>(g->dtile);
-    e = hipMemcpy(base, g->tile_row.data(), (nt + 1) * sizeof(int32_t), hipMemcpyHostToDevice);
-    if (e == hipSuccess && nt)
-        e = hipMemcpy(base + nt + 1, g->tile_grid.data(), nt * sizeof(int32_t), hipMemcpyHostToDevice);
+    e = hipMemcpy(g->dtile, g->tiles.data(), bytes, hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpy(schedule)");
-    g->dev.tile_row = base;
-    g->dev.tile_grid = base + nt + 1;
+    g->dev.tiles = static_cast<const pf::TileDesc *>(g->dtile);
     g->dev.ntiles = (int32_t)nt;
     return PF_OK;
 }
@@ -288,6 +294,10 @@ int pf_build_pattern(int32_t nb, int32_t nl, const int32_t *fbus, const int32_t 
         g->has_parallel = g->nnz_y != ni;
         g->y_off.assign(ngrids + 1, 0);
         for (int32_t k = 0; k <= ngrids; ++k) g->y_off[k] = g->yrow[g->bus_off[k]];
+        if ((int64_t)g->nnz_y * 4 > INT32_MAX) {
+            delete g;
+            return fail(PF_EUNSUP, "Jacobian larger than 2^31-1 entries");
+        }
         build_tiles(g, g->tile_items);
 
         if (g->host_only) {
@@ -297,6 +307,7 @@ int pf_build_pattern(int32_t nb, int32_t nl, const int32_t *fbus, const int32_t 
 
         // ---------------------------------------------------------- device
         hipError_t e = hipGetDevice(&g->device);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&g->num_cus, hipDeviceAttributeMultiprocessorCount, g->device);
         if (e != hipSuccess) {
             delete g;
             return hip_fail(e, "hipGetDevice");
@@ -304,10 +315,9 @@ int pf_build_pattern(int32_t nb, int32_t nl, const int32_t *fbus, const int32_t 
         Arena ar;
         size_t o_yrow = ar.take<int32_t>(nb + 1), o_irow = ar.take<int32_t>(nb + 1);
         size_t o_ycol = ar.take<int32_t>(g->nnz_y), o_nbr = ar.take<int32_t>(ni), o_slot = ar.take<int32_t>(ni);
-        size_t o_A = ar.take<double>(ni), o_C = ar.take<double>(ni), o_G = ar.take<double>(ni),
-               o_B = ar.take<double>(ni), o_Gr = ar.take<double>(ni), o_Br = ar.take<double>(ni);
+        size_t o_G = ar.take<double>(ni), o_B = ar.take<double>(ni), o_Gr = ar.take<double>(ni),
+               o_Br = ar.take<double>(ni), o_dA = ar.take<double>(nb), o_dC = ar.take<double>(nb);
         size_t o_yre = ar.take<double>(g->nnz_y), o_yim = ar.take<double>(g->nnz_y);
-        size_t o_yoff = ar.take<int64_t>(ngrids + 1);
         // setup-only arrays
         size_t o_ibr = ar.take<int32_t>(ni), o_srow = ar.take<int32_t>(g->nnz_y),
                o_sitem = ar.take<int32_t>(g->nnz_y + 1);
@@ -340,7 +350,6 @@ int pf_build_pattern(int32_t nb, int32_t nl, const int32_t *fbus, const int32_t 
         chk(up(o_ycol, g->ycol.data(), g->nnz_y * 4));
         chk(up(o_nbr, g->nbr.data(), ni * 4));
         chk(up(o_slot, g->slot.data(), ni * 4));
-        chk(up(o_yoff, g->y_off.data(), (ngrids + 1) * 8));
         chk(up(o_ibr, g->item_br.data(), ni * 4));
         chk(up(o_srow, g->slot_row.data(), g->nnz_y * 4));
         chk(up(o_sitem, g->slot_item.data(), (g->nnz_y + 1) * 4));
@@ -367,15 +376,14 @@ int pf_build_pattern(int32_t nb, int32_t nl, const int32_t *fbus, const int32_t 
         d.ycol = I32(o_ycol);
         d.nbr = I32(o_nbr);
         d.slot = I32(o_slot);
-        d.A = F64(o_A);
-        d.C = F64(o_C);
+        d.dA = F64(o_dA);
+        d.dC = F64(o_dC);
         d.G = F64(o_G);
         d.B = F64(o_B);
         d.Gr = F64(o_Gr);
         d.Br = F64(o_Br);
         d.yre = F64(o_yre);
         d.yim = F64(o_yim);
-        d.yoff = reinterpret_cast<const int64_t *>(base + o_yoff);
 
         pf::DevSetup s{};
         s.nitems = ni;
@@ -393,8 +401,9 @@ int pf_build_pattern(int32_t nb, int32_t nl, const int32_t *fbus, const int32_t 
         s.shift = F64(o_sh);
         s.gs = F64(o_gs);
         s.bs = F64(o_bs);
-        s.A = F64(o_A);
-        s.C = F64(o_C);
+        s.nb = nb;
+        s.dA = F64(o_dA);
+        s.dC = F64(o_dC);
         s.G = F64(o_G);
         s.B = F64(o_B);
         s.Gr = F64(o_Gr);
@@ -487,13 +496,16 @@ int pf_pattern_export(const pf_grid *g, int32_t *y_rowptr, int32_t *y_col, int32
     return PF_OK;
 }
 
-int pf_set_schedule(pf_grid *g, int32_t tile_items, int32_t states_per_block) {
+int pf_set_schedule(pf_grid *g, int32_t tile_items, int32_t states_per_block, int32_t order) {
     g_err.clear();
     if (!g) return fail(PF_EINVAL, "NULL handle");
     if (tile_items != 64 && tile_items != 128 && tile_items != 256 && tile_items != 512)
         return fail(PF_EINVAL, "tile_items must be 64, 128, 256 or 512");
     if (states_per_block < 0) return fail(PF_EINVAL, "states_per_block must be >= 0");
+    if (order != PF_ORDER_AUTO && order != PF_ORDER_TILE_MAJOR && order != PF_ORDER_STATE_MAJOR)
+        return fail(PF_EINVAL, "unknown order");
     g->states_per_block = states_per_block;
+    g->order = order;
     if (tile_items != g->tile_items) {
         g->tile_items = tile_items;
         build_tiles(g, tile_items);
@@ -502,12 +514,14 @@ int pf_set_schedule(pf_grid *g, int32_t tile_items, int32_t states_per_block) {
     return PF_OK;
 }
 
-int pf_get_schedule(const pf_grid *g, int32_t *tile_items, int32_t *states_per_block, int32_t *ntiles) {
+int pf_get_schedule(const pf_grid *g, int32_t *tile_items, int32_t *states_per_block, int32_t *order,
+                    int32_t *ntiles) {
     g_err.clear();
     if (!g) return fail(PF_EINVAL, "NULL handle");
     if (tile_items) *tile_items = g->tile_items;
     if (states_per_block) *states_per_block = g->states_per_block;
-    if (ntiles) *ntiles = (int32_t)g->tile_grid.size();
+    if (order) *order = g->order;
+    if (ntiles) *ntiles = (int32_t)g->tiles.size();
     return PF_OK;
 }
 
@@ -523,21 +537,29 @@ int check_eval(const pf_grid *g, int32_t nstate) {
     return PF_OK;
 }
 
-int auto_states_per_block(const pf_grid *g, int32_t nstate) {
+// States per workgroup.  A workgroup keeps its tile's record constants in
+// registers and walks its states one after another, so fewer, longer
+// workgroups read the constants fewer times.  The automatic choice fills the
+// GPU with exactly one round of resident workgroups (no tail), i.e. it
+// splits the states of each tile into about (resident capacity / tiles)
+// chunks.
+int auto_states_per_block(const pf_grid *g, int kind, int32_t nstate) {
     if (g->states_per_block > 0) return std::min<int32_t>(g->states_per_block, std::max(nstate, 1));
-    // Enough workgroups to cover 256 CUs several times over; otherwise keep
-    // the tile constants in registers across as many states as possible.
-    const int64_t nt = std::max<int64_t>(1, (int64_t)g->tile_grid.size());
-    const int64_t want_blocks = 2048;
-    int64_t chunks = std::max<int64_t>(1, (want_blocks + nt - 1) / nt);
-    int64_t spb = std::max<int64_t>(1, (nstate + chunks - 1) / chunks);
-    return (int)std::min<int64_t>(spb, 64);
+    if (nstate <= 1) return 1;
+    const int64_t nt = std::max<int64_t>(1, (int64_t)g->tiles.size());
+    int per_cu = pf::resident_blocks_per_cu(kind, g->tile_items, g->has_parallel);
+    if (per_cu <= 0) per_cu = 4;
+    const int64_t capacity = (int64_t)std::max(g->num_cus, 1) * per_cu;
+    int64_t chunks = std::max<int64_t>(1, capacity / nt);
+    chunks = std::min<int64_t>(chunks, nstate);
+    return (int)((nstate + chunks - 1) / chunks);
 }
 
 int run(const pf_grid *g, pf::Launch &L, void *stream) {
     L.tile_items = g->tile_items;
     L.has_parallel = g->has_parallel;
-    L.states_per_block = auto_states_per_block(g, L.nstate);
+    L.states_per_block = auto_states_per_block(g, L.kind, L.nstate);
+    L.state_major = g->order == PF_ORDER_STATE_MAJOR;
     if (L.nstate == 0) return PF_OK;
     int cur = -1;
     hipError_t e = hipGetDevice(&cur);

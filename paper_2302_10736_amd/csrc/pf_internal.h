@@ -10,12 +10,23 @@
 
 namespace pf {
 
+// One work tile: consecutive whole bus rows of one grid (see pf_kernels.hip).
+struct TileDesc {
+    int32_t r0, nrows;  // first row (global bus), number of rows
+    int32_t i0, n;      // first record, number of records
+    int32_t s0, ns;     // first Ybus slot, number of slots
+    int64_t jp, jq;     // offsets of the tile's P rows and Q rows in one state's J values
+};
+
 // Device view of a handle, passed to kernels by value.
 //
 // Records ("items") are the unit of the element-wise method: one per branch
 // end (at bus i, pointing to the remote bus j) and one per bus for its shunt
 // (j == i), sorted by (bus, neighbour, branch).  Slots are Ybus nonzeros;
-// without parallel branches item e and slot e coincide.
+// without parallel branches item e and slot e coincide.  A record keeps the
+// coupling admittance of its branch end; the own-end admittances of all
+// records of a bus (and its shunt) share the factor v_i^2 in every
+// evaluation and are summed once per bus (dA + j dC).
 struct DevGrid {
     int32_t nb;           // buses over all grids
     int64_t nnz_y;        // Ybus nonzeros over all grids
@@ -26,13 +37,11 @@ struct DevGrid {
     const int32_t *ycol;  // [nnz_y] global bus index of the column
     const int32_t *nbr;   // [nitems] remote bus (== own bus for the shunt record)
     const int32_t *slot;  // [nitems] global slot of the item
-    const double *A, *C;  // [nitems] own-end admittance Re / Im (shunt: g, b)
-    const double *G, *B;  // [nitems] coupling admittance Re / Im of this end
+    const double *G, *B;  // [nitems] coupling admittance Re / Im of this end (0 for the shunt record)
     const double *Gr, *Br;  // [nitems] coupling admittance of the other end (adjoint)
+    const double *dA, *dC;    // [nb] sum of own-end admittances + shunt (Re / Im)
     const double *yre, *yim;  // [nnz_y] Ybus values
-    const int64_t *yoff;      // [ngrids+1] first slot of each grid
-    const int32_t *tile_row;  // [ntiles+1] first row of each tile
-    const int32_t *tile_grid;  // [ntiles] grid of each tile
+    const TileDesc *tiles;    // [ntiles]
 };
 
 // Setup data, only read by the setup kernels.
@@ -47,7 +56,9 @@ struct DevSetup {
     const int32_t *ycol;       // [nnz_y]
     const double *r, *x, *b, *tap, *shift;  // [nl]
     const double *gs, *bs;                  // [nb]
-    double *A, *C, *G, *B, *Gr, *Br;        // [nitems] outputs
+    int32_t nb;
+    double *G, *B, *Gr, *Br;                // [nitems] outputs
+    double *dA, *dC;                        // [nb] outputs
     double *yre, *yim;                      // [nnz_y] outputs
 };
 
@@ -57,6 +68,7 @@ struct Launch {
     int kind;
     int tile_items;        // workgroup size = records per tile
     int states_per_block;
+    bool state_major;  // work items ordered state chunk first
     int nstate;
     bool has_parallel;
     const double *vm, *va, *lp, *lq;
@@ -64,6 +76,9 @@ struct Launch {
 };
 
 hipError_t launch_eval(const DevGrid &g, const Launch &L, hipStream_t stream);
+// Workgroups of the evaluation kernel for (kind, tile_items, has_parallel)
+// that one compute unit holds at once (0 if unknown).
+int resident_blocks_per_cu(int kind, int tile_items, bool has_parallel);
 hipError_t launch_setup_items(const DevSetup &s, hipStream_t stream);
 hipError_t launch_ybus_assemble(const DevSetup &s, hipStream_t stream);
 

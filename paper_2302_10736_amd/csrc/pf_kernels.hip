@@ -6,45 +6,68 @@
 // Work decomposition (both methods)
 // ---------------------------------
 // Records are sorted by (bus, neighbour, branch).  A tile is a run of whole
-// bus rows holding at most NT records (NT = workgroup size); one thread
-// owns one record.  Per voltage state a workgroup
-//   1. evaluates every record of the tile (one branch end, or the bus shunt,
-//      for the element-wise method; one Ybus nonzero for the Ybus method),
-//   2. reduces the records of each row in LDS, sequentially in record order,
-//      by the thread that owns the row's diagonal record,
-//   3. assembles the tile's Jacobian rows in LDS and writes them out with
-//      contiguous 16-byte stores: a tile's rows are contiguous in the CSR
-//      value array, once for the P rows and once for the Q rows.
-// There are no atomics; every sum has a fixed order set by the pattern, so
-// results do not depend on the tile size or the number of states per
-// workgroup.  A row with more than NT records forms a tile of its own,
-// walked in chunks with the same sequential order.
+// bus rows holding at most NT records (NT = workgroup size); one thread owns
+// one record, and thread r < rows also owns row r of the tile.  Per voltage
+// state a workgroup
+//   1. evaluates every record of the tile (one branch end or one bus shunt
+//      for the element-wise method, one Ybus nonzero for the Ybus method),
+//      writing the off-diagonal Jacobian entries into an LDS copy of the
+//      tile's Jacobian rows;
+//   2. reduces each row sequentially, in record order, by its row thread,
+//      which writes P_i, Q_i and the four diagonal Jacobian entries;
+//   3. writes the tile's Jacobian rows with contiguous 16-byte stores: a
+//      tile's rows are two contiguous ranges of the CSR value array (the P
+//      rows and the Q rows).
+// No atomics; every sum has a fixed order set by the pattern, so results do
+// not depend on the tile size or on the states per workgroup.  LDS buffers
+// alternate between consecutive states (two barriers per state), and the
+// gathers of the next state are issued before the current one is reduced.
+// A row with more than NT records is a tile of its own, walked in chunks by
+// one thread's sequential sums in the same order.
 //
-// Record constants (from the branch data, computed once at setup):
-//   A + jC  own-end admittance: Re/Im of (y_h + y_hk)/m^2 at the from end,
-//           of (y_k + y_hk) at the to end, of (g + jb) for a bus shunt;
-//   G + jB  coupling admittance of this end: -y_hk e^{j phi}/m at the from
-//           end, -y_hk e^{-j phi}/m at the to end, 0 for a bus shunt;
-//   Gr, Br  coupling admittance of the other end of the same branch.
-// With t = theta_i - theta_j, w = v_i v_j, alpha = G cos t + B sin t,
-// beta = G sin t - B cos t, one record contributes
-//   P = v_i^2 A + w alpha,   Q = -v_i^2 C + w beta,
-// i.e. eq. (5) (from end) or eq. (6) (to end) split into real and imaginary
-// parts, and its eight partial derivatives
-//   dP/dtheta_i = -w beta    dP/dtheta_j =  w beta
-//   dP/dv_i = 2 v_i A + v_j alpha    dP/dv_j = v_i alpha
-//   dQ/dtheta_i =  w alpha   dQ/dtheta_j = -w alpha
-//   dQ/dv_i = -2 v_i C + v_j beta    dQ/dv_j = v_i beta
-// (the 16 partials of one branch are the 8 + 8 of its two ends).
+// Element-wise records
+// --------------------
+// A branch-end record at bus i (remote bus j) holds the coupling admittance
+// G + jB of its end: -y_hk e^{j phi}/m at the from end, -y_hk e^{-j phi}/m at
+// the to end (the phase shift folded in), zero for the bus-shunt record.
+// With t = theta_i - theta_j, alpha = G cos t + B sin t and
+// beta = G sin t - B cos t, eqs. (5) and (6) split into real and imaginary
+// parts read, for every record,
+//   P_e = v_i^2 A_e + v_i v_j alpha,   Q_e = -v_i^2 C_e + v_i v_j beta,
+// where A_e + jC_e is the record's own-end admittance ((y_h + y_hk)/m^2 at
+// the from end, y_k + y_hk at the to end, g + jb for the shunt).  The own-end
+// term of every record at bus i carries the same factor v_i^2, so the bus sum
+// of eq. (7) is
+//   P_i = v_i^2 dA_i + v_i a_i,   Q_i = -v_i^2 dC_i + v_i b_i,
+// with the state-free bus constants dA + j dC = sum of A_e + jC_e (setup) and
+// the per-state row sums a_i = sum_e v_j alpha_e, b_i = sum_e v_j beta_e.
+// The 16 partials of a branch (Section II.B) are its two ends' remote partials
+//   dP_e/dtheta_j =  v_i v_j beta,   dP_e/dv_j = v_i alpha,
+//   dQ_e/dtheta_j = -v_i v_j alpha,  dQ_e/dv_j = v_i beta,
+// written straight into J (one record per off-diagonal slot, or a fixed-order
+// slot sum with parallel branches), and its own partials, whose bus sums are
+//   dP_i/dtheta_i = -v_i b_i,          dP_i/dv_i = 2 v_i dA_i + a_i,
+//   dQ_i/dtheta_i =  v_i a_i,          dQ_i/dv_i = b_i - 2 v_i dC_i.
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+
 #include "pf_internal.h"
+#include "pf_math.h"
 
 namespace pf {
+
+// Series coefficients in constant memory: with external linkage the compiler
+// reads them with scalar loads instead of folding them into vector-register
+// immediates, so each polynomial step is one FMA with a scalar operand.
+__constant__ SinCosCoef g_sincos = kSinCosTaylor;
+
 namespace {
 
 constexpr int kXcds = 8;
+
+__device__ __forceinline__ void sincos_dev(double x, double *s, double *c) { sincos_rad(x, s, c, g_sincos); }
 
 // Workgroups are dispatched round-robin over the 8 XCDs.  Give each XCD a
 // contiguous range of work items so that neighbouring tiles, and all state
@@ -55,30 +78,17 @@ __device__ __forceinline__ int work_index(int nblocks) {
     return (b % kXcds) * per + b / kXcds;
 }
 
-struct Tile {
-    int r0, nrows;  // first row, number of rows
-    int i0, n;      // first record, number of records
-    int s0, ns;     // first slot, number of slots
-    int64_t jp, jq;  // offsets of the tile's P rows and Q rows in one state's J values
-};
-
-__device__ __forceinline__ Tile tile_of(const DevGrid &g, int t) {
-    Tile c;
-    c.r0 = g.tile_row[t];
-    const int r1 = g.tile_row[t + 1];
-    c.nrows = r1 - c.r0;
-    c.i0 = g.irow[c.r0];
-    c.n = g.irow[r1] - c.i0;
-    c.s0 = g.yrow[c.r0];
-    c.ns = g.yrow[r1] - c.s0;
-    const int gi = g.tile_grid[t];
-    // Grid gi's J values start at 4 yoff[gi]; its P rows hold 2 nnz_y(gi)
-    // values, so row i's P part starts at 2 yoff[gi] + 2 yrow[i] and its Q
-    // part at 2 yoff[gi+1] + 2 yrow[i].
-    c.jp = 2 * g.yoff[gi] + 2 * (int64_t)c.s0;
-    c.jq = 2 * g.yoff[gi + 1] + 2 * (int64_t)c.s0;
-    return c;
+// LDS-only workgroup barrier: orders LDS accesses across the barrier without
+// waiting for outstanding global loads (prefetches) or stores.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
+
+using Tile = TileDesc;
+
+__device__ __forceinline__ Tile tile_of(const DevGrid &g, int t) { return g.tiles[t]; }
 
 // Local row pointers of a packed tile (records and slots) into LDS.
 template <int NT>
@@ -105,10 +115,12 @@ __device__ __forceinline__ int row_of(int k, const int *rowptr, int nrows) {
 struct Cx {
     double re, im;
 };
-__device__ __forceinline__ Cx cmul(Cx a, Cx b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+// Complex product with one rounding per product term and one fused step.
+__device__ __forceinline__ Cx cmul(Cx a, Cx b) {
+    return {fma(a.re, b.re, -(a.im * b.im)), fma(a.re, b.im, a.im * b.re)};
+}
 __device__ __forceinline__ Cx cconj(Cx a) { return {a.re, -a.im}; }
 __device__ __forceinline__ Cx cadd(Cx a, Cx b) { return {a.re + b.re, a.im + b.im}; }
-__device__ __forceinline__ Cx csub(Cx a, Cx b) { return {a.re - b.re, a.im - b.im}; }
 
 // Copy a staged tile of J rows (LDS) to global memory with 16-byte stores.
 template <int NT>
@@ -122,111 +134,152 @@ __device__ __forceinline__ void write_jrows(const Tile &c, const double *s_J, do
     }
 }
 
-// One element-wise record: power and the eight partials (see file header).
-struct EwOut {
-    double p, q;               // record's contribution to P_i, Q_i
-    double dpt, dpv, dqt, dqv;  // own-bus partials (diagonal slot)
-    double rpt, rpv, rqt, rqv;  // remote-bus partials (slot (i, j))
+// Walk states [sb, se) with the per-state inputs of each state loaded one
+// state ahead.  Two register sets alternate (states are taken in pairs), so
+// the loop never copies registers that are still being loaded: a copy would
+// make the wave wait for every outstanding memory operation, including the
+// previous state's stores.  `proc(s, parity, in)` gets parity = (s - sb) & 1
+// for the double-buffered LDS.
+template <class In, class Load, class Proc>
+__device__ __forceinline__ void pipelined_states(int sb, int se, Load &&load, Proc &&proc) {
+    In ra{}, rb{};
+    if (sb < se) load(sb, ra);
+    for (int s = sb; s < se; s += 2) {
+        if (s + 1 < se) load(s + 1, rb);
+        proc(s, 0, ra);
+        if (s + 2 < se) load(s + 2, ra);
+        if (s + 1 < se) proc(s + 1, 1, rb);
+    }
+}
+
+// Row sums of two LDS arrays over records [a, z), strictly left to right.
+// Records are read four at a time so one LDS round trip serves four terms;
+// reads past the row end use a clamped index and contribute +0.0, which
+// leaves every partial sum unchanged.
+__device__ __forceinline__ void row_sum2(const double *x, const double *y, int a, int z, double &sx, double &sy) {
+    double u = 0.0, v = 0.0;
+    for (int q = a; q < z; q += 4) {
+        const int q1 = min(q + 1, z - 1), q2 = min(q + 2, z - 1), q3 = min(q + 3, z - 1);
+        const double x0 = x[q], x1 = x[q1], x2 = x[q2], x3 = x[q3];
+        const double y0 = y[q], y1 = y[q1], y2 = y[q2], y3 = y[q3];
+        u += x0;
+        v += y0;
+        u += q + 1 < z ? x1 : 0.0;
+        v += q + 1 < z ? y1 : 0.0;
+        u += q + 2 < z ? x2 : 0.0;
+        v += q + 2 < z ? y2 : 0.0;
+        u += q + 3 < z ? x3 : 0.0;
+        v += q + 3 < z ? y3 : 0.0;
+    }
+    sx = u;
+    sy = v;
+}
+
+// One element-wise record (see the file header).
+struct EwRec {
+    double a, b;                // v_j alpha, v_j beta (row sums)
+    double rpt, rpv, rqt, rqv;  // remote partials: dP/dtheta_j, dP/dv_j, dQ/dtheta_j, dQ/dv_j
 };
 
-__device__ __forceinline__ EwOut ew_record(double vi, double ti, double vj, double tj, double A, double C, double G,
-                                           double B) {
+__device__ __forceinline__ EwRec ew_record(double vi, double ti, double vj, double tj, double G, double B) {
     double sn, cs;
-    sincos(ti - tj, &sn, &cs);
-    const double w = vi * vj;
-    const double al = G * cs + B * sn;
-    const double be = G * sn - B * cs;
-    EwOut o;
-    o.p = vi * vi * A + w * al;
-    o.q = w * be - vi * vi * C;
-    o.dpt = -(w * be);
-    o.dpv = 2.0 * vi * A + vj * al;
-    o.dqt = w * al;
-    o.dqv = vj * be - 2.0 * vi * C;
-    o.rpt = w * be;
-    o.rpv = vi * al;
-    o.rqt = -(w * al);
-    o.rqv = vi * be;
+    sincos_dev(ti - tj, &sn, &cs);
+    const double al = fma(G, cs, B * sn);
+    const double be = fma(G, sn, -(B * cs));
+    EwRec r;
+    r.a = vj * al;
+    r.b = vj * be;
+    r.rpt = vi * r.b;
+    r.rpv = vi * al;
+    r.rqt = -(vi * r.a);
+    r.rqv = vi * be;
+    return r;
+}
+
+struct EwRow {
+    double p, q, j11, j12, j21, j22;
+};
+
+__device__ __forceinline__ EwRow ew_row(double vi, double dA, double dC, double as, double bs) {
+    EwRow o;
+    o.p = vi * fma(vi, dA, as);
+    o.q = vi * fma(-vi, dC, bs);
+    o.j11 = -(vi * bs);
+    o.j12 = fma(2.0 * vi, dA, as);
+    o.j21 = vi * as;
+    o.j22 = fma(-2.0 * vi, dC, bs);
     return o;
 }
 
 // ===================================================================
-// Element-wise injections and Jacobian values.
+// Element-wise injections (WITH_J = false) and injections + Jacobian values.
 template <int NT, bool PAR, bool WITH_J>
 __global__ void __launch_bounds__(NT)
-    k_ew(DevGrid g, int nstate, int spb, int nchunk, const double *__restrict__ vm, const double *__restrict__ va,
+    k_ew(DevGrid g, int nstate, int spb, int nchunk, bool state_major, const double *__restrict__ vm, const double *__restrict__ va,
          double *__restrict__ P, double *__restrict__ Q, double *__restrict__ J) {
+    constexpr int NR = (WITH_J && PAR) ? NT : 1;  // remote partials kept for slot sums
     __shared__ int s_irow[NT + 1];
     __shared__ int s_yrow[NT + 1];
-    constexpr int NV = WITH_J ? 6 : 2;        // values per record kept for the row sums
-    constexpr int NR = (WITH_J && PAR) ? NT : 1;  // remote partials kept for slot sums
-    __shared__ double s_val[NV][NT];
-    __shared__ double s_pq[2][NT];
-    __shared__ __align__(16) double s_J[WITH_J ? 4 * NT : 2];
-    __shared__ double s_rem[4][NR];
+    __shared__ int s_dslot[NT];
+    __shared__ double s_ab[2][2][NT];
+    // J stage: P rows in [0, 2 NT), Q rows in [2 NT, 4 NT), two pad slots
+    // (4 NT, 4 NT + 1) that absorb the writes of lanes with nothing to write
+    __shared__ __align__(16) double s_J[2][WITH_J ? 4 * NT + 2 : 2];
+    __shared__ double s_rem[2][4][NR];
     __shared__ int s_slot[NR];
-    __shared__ int s_diag;
 
     const int W = g.ntiles * nchunk;
     const int w = work_index(gridDim.x);
     if (w >= W) return;
-    const int t = w / nchunk;
-    const int sb = (w - t * nchunk) * spb;
+    const int t = state_major ? w % g.ntiles : w / nchunk;
+    const int sb = (state_major ? w / g.ntiles : w - t * nchunk) * spb;
     const int se = min(nstate, sb + spb);
     const Tile c = tile_of(g, t);
     const int k = threadIdx.x;
     const size_t nb = (size_t)g.nb;
 
     if (c.n > NT) {
-        // ---- one long row, walked in chunks of NT records by thread 0's sequential sums
+        // ---- one row with more than NT records, walked in chunks
         const int i = c.r0;
         const int d = c.ns;  // slots in the row
-        if (k == 0) s_diag = -1;  // set by the shunt record's thread below; same in every state
-        __syncthreads();
+        const double dA = g.dA[i], dC = g.dC[i];
         for (int s = sb; s < se; ++s) {
-            const size_t so = (size_t)s * nb;
+            const double *vms = vm + (size_t)s * nb;
+            const double *vas = va + (size_t)s * nb;
             double *Js = WITH_J ? J + (size_t)s * (size_t)g.nnz_j : nullptr;
-            double acc[6] = {0, 0, 0, 0, 0, 0};
-            double racc[4] = {0, 0, 0, 0};
+            const double vi = vms[i], ti = vas[i];
+            double as = 0.0, bs = 0.0;
+            double racc[4] = {0.0, 0.0, 0.0, 0.0};
             int cur = -1;
             for (int base = 0; base < c.n; base += NT) {
-                const bool live = base + k < c.n;
-                if (live) {
+                if (base + k < c.n) {
                     const int e = c.i0 + base + k;
                     const int j = g.nbr[e];
-                    const EwOut o = ew_record(vm[so + i], va[so + i], vm[so + j], va[so + j], g.A[e], g.C[e],
-                                              g.G[e], g.B[e]);
-                    s_val[0][k] = o.p;
-                    s_val[1][k] = o.q;
+                    const EwRec r = ew_record(vi, ti, vms[j], vas[j], g.G[e], g.B[e]);
+                    s_ab[0][0][k] = r.a;
+                    s_ab[0][1][k] = r.b;
                     if constexpr (WITH_J) {
-                        s_val[2][k] = o.dpt;
-                        s_val[3][k] = o.dpv;
-                        s_val[4][k] = o.dqt;
-                        s_val[5][k] = o.dqv;
-                        // long rows reuse the J stage as remote-partial storage
-                        s_J[0 * NT + k] = o.rpt;
-                        s_J[1 * NT + k] = o.rpv;
-                        s_J[2 * NT + k] = o.rqt;
-                        s_J[3 * NT + k] = o.rqv;
+                        // the J stage holds the remote partials of the chunk
+                        s_J[0][0 * NT + k] = r.rpt;
+                        s_J[0][1 * NT + k] = r.rpv;
+                        s_J[0][2 * NT + k] = r.rqt;
+                        s_J[0][3 * NT + k] = r.rqv;
                         const int ls = (PAR ? g.slot[e] : e) - c.s0;
                         s_irow[k] = ls;
-                        if (j == i) s_diag = ls;
+                        if (j == i) s_dslot[0] = ls;
                     }
                 }
                 __syncthreads();
                 if (k == 0) {
                     const int m = min(NT, c.n - base);
                     for (int q = 0; q < m; ++q) {
-                        acc[0] += s_val[0][q];
-                        acc[1] += s_val[1][q];
+                        as += s_ab[0][0][q];
+                        bs += s_ab[0][1][q];
                         if constexpr (WITH_J) {
-                            acc[2] += s_val[2][q];
-                            acc[3] += s_val[3][q];
-                            acc[4] += s_val[4][q];
-                            acc[5] += s_val[5][q];
                             const int ls = s_irow[q];
                             if (ls != cur) {
-                                if (cur >= 0 && cur != s_diag) {
+                                // a finished slot; the diagonal slot's zeros are overwritten below
+                                if (cur >= 0) {
                                     Js[c.jp + cur] = racc[0];
                                     Js[c.jp + d + cur] = racc[1];
                                     Js[c.jq + cur] = racc[2];
@@ -235,32 +288,33 @@ __global__ void __launch_bounds__(NT)
                                 cur = ls;
                                 racc[0] = racc[1] = racc[2] = racc[3] = 0.0;
                             }
-                            racc[0] += s_J[0 * NT + q];
-                            racc[1] += s_J[1 * NT + q];
-                            racc[2] += s_J[2 * NT + q];
-                            racc[3] += s_J[3 * NT + q];
+                            racc[0] += s_J[0][0 * NT + q];
+                            racc[1] += s_J[0][1 * NT + q];
+                            racc[2] += s_J[0][2 * NT + q];
+                            racc[3] += s_J[0][3 * NT + q];
                         }
                     }
                 }
                 __syncthreads();
             }
             if (k == 0) {
+                const EwRow o = ew_row(vi, dA, dC, as, bs);
                 if (P) {
-                    P[so + i] = acc[0];
-                    Q[so + i] = acc[1];
+                    P[(size_t)s * nb + i] = o.p;
+                    Q[(size_t)s * nb + i] = o.q;
                 }
                 if constexpr (WITH_J) {
-                    if (cur >= 0 && cur != s_diag) {
+                    if (cur >= 0) {
                         Js[c.jp + cur] = racc[0];
                         Js[c.jp + d + cur] = racc[1];
                         Js[c.jq + cur] = racc[2];
                         Js[c.jq + d + cur] = racc[3];
                     }
-                    const int ld = s_diag;
-                    Js[c.jp + ld] = acc[2];
-                    Js[c.jp + d + ld] = acc[3];
-                    Js[c.jq + ld] = acc[4];
-                    Js[c.jq + d + ld] = acc[5];
+                    const int ld = s_dslot[0];
+                    Js[c.jp + ld] = o.j11;
+                    Js[c.jp + d + ld] = o.j12;
+                    Js[c.jq + ld] = o.j21;
+                    Js[c.jq + d + ld] = o.j22;
                 }
             }
             __syncthreads();
@@ -272,124 +326,145 @@ __global__ void __launch_bounds__(NT)
     stage_rows<NT>(g, c, s_irow, s_yrow);
     const bool live = k < c.n;
     int j = 0, ls = 0;
-    double A = 0.0, C = 0.0, G = 0.0, B = 0.0;
+    double G = 0.0, B = 0.0;
     if (live) {
         const int e = c.i0 + k;
         j = g.nbr[e];
-        A = g.A[e];
-        C = g.C[e];
         G = g.G[e];
         B = g.B[e];
         ls = (PAR ? g.slot[e] : e) - c.s0;  // without parallel branches, slot == record
+    }
+    const bool rowt = k < c.nrows;  // thread k also owns row k of the tile
+    const int ir = c.r0 + k;
+    double dA = 0.0, dC = 0.0;
+    if (rowt) {
+        dA = g.dA[ir];
+        dC = g.dC[ir];
     }
     __syncthreads();
     const int row = live ? row_of(k, s_irow, c.nrows) : 0;
     const int i = c.r0 + row;
     const bool diag = live && j == i;
-    const int o11 = s_yrow[row] + ls;      // J11 / J21 position inside the staged P / Q rows
-    const int o12 = s_yrow[row + 1] + ls;  // J12 / J22
+    if (diag) s_dslot[row] = ls;
     if constexpr (WITH_J && PAR)
         if (live) s_slot[k] = ls;
+    const int o11 = s_yrow[row] + ls;      // J11 / J21 position inside the staged P / Q rows
+    const int o12 = s_yrow[row + 1] + ls;  // J12 / J22
+    __syncthreads();
+    int ra = 0, rz = 0, d11 = 0, d12 = 0;
+    if (rowt) {
+        ra = s_irow[k];
+        rz = s_irow[k + 1];
+        d11 = s_yrow[k] + s_dslot[k];
+        d12 = s_yrow[k + 1] + s_dslot[k];
+    }
 
-    for (int s = sb; s < se; ++s) {
-        const size_t so = (size_t)s * nb;
-        if (live) {
-            const EwOut o = ew_record(vm[so + i], va[so + i], vm[so + j], va[so + j], A, C, G, B);
-            s_val[0][k] = o.p;
-            s_val[1][k] = o.q;
-            if constexpr (WITH_J) {
-                s_val[2][k] = o.dpt;
-                s_val[3][k] = o.dpv;
-                s_val[4][k] = o.dqt;
-                s_val[5][k] = o.dqv;
-                if constexpr (PAR) {
-                    s_rem[0][k] = o.rpt;
-                    s_rem[1][k] = o.rpv;
-                    s_rem[2][k] = o.rqt;
-                    s_rem[3][k] = o.rqv;
-                } else if (!diag) {
-                    s_J[o11] = o.rpt;
-                    s_J[o12] = o.rpv;
-                    s_J[2 * NT + o11] = o.rqt;
-                    s_J[2 * NT + o12] = o.rqv;
-                }
+    // State loads are unconditional (idle lanes read a valid bus of the
+    // tile), which keeps the memory-counter waits exact.
+    const int li = live ? i : c.r0, lj = live ? j : c.r0, lr = rowt ? ir : c.r0;
+    struct In {
+        double vi, ti, vj, tj, vr;
+    };
+    auto load = [&](int s, In &x) {
+        const double *vms = vm + (size_t)s * nb;
+        const double *vas = va + (size_t)s * nb;
+        x.vi = vms[li];
+        x.ti = vas[li];
+        x.vj = vms[lj];
+        x.tj = vas[lj];
+        x.vr = vms[lr];
+    };
+    // LDS targets of the record's remote partials and of the row's diagonal
+    // entries; lanes with nothing to write use the pad slots.
+    const bool wrem = live && !diag && !PAR;
+    const int t11 = wrem ? o11 : 4 * NT, t12 = wrem ? o12 : 4 * NT;
+    const int t21 = wrem ? 2 * NT + o11 : 4 * NT + 1, t22 = wrem ? 2 * NT + o12 : 4 * NT + 1;
+    const int u11 = rowt ? d11 : 4 * NT, u12 = rowt ? d12 : 4 * NT;
+    const int u21 = rowt ? 2 * NT + d11 : 4 * NT + 1, u22 = rowt ? 2 * NT + d12 : 4 * NT + 1;
+    // Every lane evaluates a record and a row (idle lanes with zero
+    // admittances and valid indices), so each loaded value is consumed on the
+    // straight-line path and the loads of the next state stay in flight; only
+    // LDS writes and stores depend on the lane's role.  Record slots k >= n
+    // and row slots k >= rows are never read.
+    auto proc = [&](int s, int p, const In &x) {
+        const EwRec r = ew_record(x.vi, x.ti, x.vj, x.tj, G, B);
+        s_ab[p][0][k] = r.a;
+        s_ab[p][1][k] = r.b;
+        if constexpr (WITH_J) {
+            if constexpr (PAR) {
+                s_rem[p][0][k] = r.rpt;
+                s_rem[p][1][k] = r.rpv;
+                s_rem[p][2][k] = r.rqt;
+                s_rem[p][3][k] = r.rqv;
+            } else {
+                s_J[p][t11] = r.rpt;
+                s_J[p][t12] = r.rpv;
+                s_J[p][t21] = r.rqt;
+                s_J[p][t22] = r.rqv;
             }
         }
-        __syncthreads();
-        if (diag) {
-            const int a = s_irow[row], z = s_irow[row + 1];
-            double sp = 0.0, sq = 0.0, d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
-            for (int q = a; q < z; ++q) {
-                sp += s_val[0][q];
-                sq += s_val[1][q];
-                if constexpr (WITH_J) {
-                    d0 += s_val[2][q];
-                    d1 += s_val[3][q];
-                    d2 += s_val[4][q];
-                    d3 += s_val[5][q];
-                }
-            }
-            s_pq[0][row] = sp;
-            s_pq[1][row] = sq;
-            if constexpr (WITH_J) {
-                s_J[o11] = d0;
-                s_J[o12] = d1;
-                s_J[2 * NT + o11] = d2;
-                s_J[2 * NT + o12] = d3;
-            }
-        } else if (live) {
-            if constexpr (WITH_J && PAR) {
-              if (k == 0 || s_slot[k - 1] != ls) {  // first record of its slot sums the slot
+        lds_barrier();
+        double as, bs;
+        row_sum2(s_ab[p][0], s_ab[p][1], ra, rz, as, bs);
+        const EwRow o = ew_row(x.vr, dA, dC, as, bs);
+        if (P && rowt) {
+            P[(size_t)s * nb + ir] = o.p;
+            Q[(size_t)s * nb + ir] = o.q;
+        }
+        if constexpr (WITH_J) {
+            s_J[p][u11] = o.j11;
+            s_J[p][u12] = o.j12;
+            s_J[p][u21] = o.j21;
+            s_J[p][u22] = o.j22;
+        }
+        if constexpr (WITH_J && PAR) {
+            if (live && !diag && (k == 0 || s_slot[k - 1] != ls)) {  // first record of its slot sums the slot
                 double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
                 for (int q = k; q < c.n && s_slot[q] == ls; ++q) {
-                    a0 += s_rem[0][q];
-                    a1 += s_rem[1][q];
-                    a2 += s_rem[2][q];
-                    a3 += s_rem[3][q];
+                    a0 += s_rem[p][0][q];
+                    a1 += s_rem[p][1][q];
+                    a2 += s_rem[p][2][q];
+                    a3 += s_rem[p][3][q];
                 }
-                s_J[o11] = a0;
-                s_J[o12] = a1;
-                s_J[2 * NT + o11] = a2;
-                s_J[2 * NT + o12] = a3;
-              }
+                s_J[p][o11] = a0;
+                s_J[p][o12] = a1;
+                s_J[p][2 * NT + o11] = a2;
+                s_J[p][2 * NT + o12] = a3;
             }
         }
-        __syncthreads();
-        if (WITH_J) write_jrows<NT>(c, s_J, J + (size_t)s * (size_t)g.nnz_j);
-        if (P) {
-            for (int q = k; q < c.nrows; q += NT) {
-                P[so + c.r0 + q] = s_pq[0][q];
-                Q[so + c.r0 + q] = s_pq[1][q];
-            }
+        if constexpr (WITH_J) {
+            lds_barrier();
+            write_jrows<NT>(c, s_J[p], J + (size_t)s * (size_t)g.nnz_j);
         }
-        __syncthreads();
-    }
+    };
+    pipelined_states<In>(sb, se, load, proc);
 }
 
 // ===================================================================
 // Ybus method: I = Ybus V, S = V conj(I) (eq. (1)) and, with WITH_J, the
 // two-pass Jacobian of eqs. (3)-(4) done row-wise on the CSR matrix:
-// pass 1 forms I_i, pass 2 turns each nonzero into
+// pass 1 forms Y_ij V_j and the row sums I_i, pass 2 turns each nonzero into
 //   dS_i/dtheta_j = j V_i (delta_ij conj(I_i) - conj(Y_ij V_j))
 //   dS_i/dv_j     = V_i conj(Y_ij U_j) + delta_ij conj(I_i) U_i
 // and writes the four real parts in place into J (Section IV.B.2).
-// U = e^{j theta} and V = v U are formed on the fly from (vm, va).
+// U = e^{j theta} and V = v U are formed on the fly from (vm, va); a row's
+// own V_i and U_i reach the other threads of the row through LDS.
 template <int NT, bool WITH_J>
 __global__ void __launch_bounds__(NT)
-    k_ybus(DevGrid g, int nstate, int spb, int nchunk, const double *__restrict__ vm, const double *__restrict__ va,
+    k_ybus(DevGrid g, int nstate, int spb, int nchunk, bool state_major, const double *__restrict__ vm, const double *__restrict__ va,
            double *__restrict__ P, double *__restrict__ Q, double *__restrict__ J) {
     __shared__ int s_irow[NT + 1];
     __shared__ int s_yrow[NT + 1];
-    __shared__ double s_yv[2][NT];
-    __shared__ double s_row[4][NT];  // per row: I_i (re, im), V_i (re, im)
-    __shared__ double s_u[2][NT];    // per row: U_i
-    __shared__ __align__(16) double s_J[WITH_J ? 4 * NT : 1];
+    __shared__ int s_dslot[NT];
+    __shared__ double s_yv[2][2][NT];  // Y_ij V_j
+    __shared__ double s_vu[2][4][NT];  // per row: V_i, U_i (re, im)
+    __shared__ __align__(16) double s_J[2][WITH_J ? 4 * NT + 2 : 2];  // + two pad slots (see k_ew)
 
     const int W = g.ntiles * nchunk;
     const int w = work_index(gridDim.x);
     if (w >= W) return;
-    const int t = w / nchunk;
-    const int sb = (w - t * nchunk) * spb;
+    const int t = state_major ? w % g.ntiles : w / nchunk;
+    const int sb = (state_major ? w / g.ntiles : w - t * nchunk) * spb;
     const int se = min(nstate, sb + spb);
     const Tile c = tile_of(g, t);
     const int k = threadIdx.x;
@@ -400,59 +475,57 @@ __global__ void __launch_bounds__(NT)
         const int i = c.r0;
         const int d = c.ns;
         for (int s = sb; s < se; ++s) {
-            const size_t so = (size_t)s * nb;
+            const double *vms = vm + (size_t)s * nb;
+            const double *vas = va + (size_t)s * nb;
             Cx I = {0.0, 0.0};
             for (int base = 0; base < d; base += NT) {
                 if (base + k < d) {
                     const int p = c.s0 + base + k;
                     const int j = g.ycol[p];
                     double sn, cs;
-                    sincos(va[so + j], &sn, &cs);
-                    const double v = vm[so + j];
+                    sincos_dev(vas[j], &sn, &cs);
+                    const double v = vms[j];
                     const Cx yv = cmul({g.yre[p], g.yim[p]}, {v * cs, v * sn});
-                    s_yv[0][k] = yv.re;
-                    s_yv[1][k] = yv.im;
+                    s_yv[0][0][k] = yv.re;
+                    s_yv[0][1][k] = yv.im;
                 }
                 __syncthreads();
                 if (k == 0) {
                     const int m = min(NT, d - base);
                     for (int q = 0; q < m; ++q) {
-                        I.re += s_yv[0][q];
-                        I.im += s_yv[1][q];
+                        I.re += s_yv[0][0][q];
+                        I.im += s_yv[0][1][q];
                     }
+                    s_vu[0][0][0] = I.re;
+                    s_vu[0][1][0] = I.im;
                 }
                 __syncthreads();
             }
             double sn, cs;
-            sincos(va[so + i], &sn, &cs);
+            sincos_dev(vas[i], &sn, &cs);
             const Cx Ui = {cs, sn};
-            const double vi = vm[so + i];
+            const double vi = vms[i];
             const Cx Vi = {vi * cs, vi * sn};
-            if (k == 0) {
-                s_row[0][0] = I.re;
-                s_row[1][0] = I.im;
-                if (P) {
-                    const Cx S = cmul(Vi, cconj(I));
-                    P[so + i] = S.re;
-                    Q[so + i] = S.im;
-                }
+            const Cx Ic = {s_vu[0][0][0], -s_vu[0][1][0]};  // conj(I_i)
+            if (k == 0 && P) {
+                const Cx S = cmul(Vi, Ic);
+                P[(size_t)s * nb + i] = S.re;
+                Q[(size_t)s * nb + i] = S.im;
             }
-            __syncthreads();
             if constexpr (WITH_J) {
-                const Cx Ic = {s_row[0][0], -s_row[1][0]};  // conj(I_i)
                 double *Js = J + (size_t)s * (size_t)g.nnz_j;
                 for (int lp = k; lp < d; lp += NT) {
                     const int p = c.s0 + lp;
                     const int j = g.ycol[p];
                     double snj, csj;
-                    sincos(va[so + j], &snj, &csj);
-                    const double v = vm[so + j];
+                    sincos_dev(vas[j], &snj, &csj);
+                    const double v = vms[j];
                     const Cx Y = {g.yre[p], g.yim[p]};
                     const Cx Uj = {csj, snj};
                     const Cx yv = cmul(Y, {v * csj, v * snj});
                     const bool dg = j == i;
-                    const Cx x = csub(dg ? Ic : Cx{0.0, 0.0}, cconj(yv));
-                    const Cx dst = cmul({-Vi.im, Vi.re}, x);  // j V_i x
+                    const Cx x = {(dg ? Ic.re : 0.0) - yv.re, (dg ? Ic.im : 0.0) + yv.im};  // delta conj(I) - conj(YV)
+                    const Cx dst = cmul({-Vi.im, Vi.re}, x);                                  // j V_i x
                     Cx dsv = cmul(Vi, cconj(cmul(Y, Uj)));
                     if (dg) dsv = cadd(dsv, cmul(Ic, Ui));
                     Js[c.jp + lp] = dst.re;
@@ -475,68 +548,89 @@ __global__ void __launch_bounds__(NT)
         j = g.ycol[p];
         Y = {g.yre[p], g.yim[p]};
     }
+    const bool rowt = k < c.nrows;
+    const int ir = c.r0 + k;
     __syncthreads();
     const int row = live ? row_of(k, s_yrow, c.nrows) : 0;
-    const int i = c.r0 + row;
-    const bool diag = live && j == i;
+    const bool diag = live && j == c.r0 + row;
+    if (diag) s_dslot[row] = k;
     const int o11 = s_yrow[row] + k;
     const int o12 = s_yrow[row + 1] + k;
+    __syncthreads();
+    int ra = 0, rz = 0, dl = 0;
+    Cx Yd = {0.0, 0.0};
+    if (rowt) {
+        ra = s_yrow[k];
+        rz = s_yrow[k + 1];
+        dl = s_dslot[k];
+        Yd = {g.yre[c.s0 + dl], g.yim[c.s0 + dl]};
+    }
 
-    for (int s = sb; s < se; ++s) {
-        const size_t so = (size_t)s * nb;
-        Cx Uj = {0.0, 0.0}, yv = {0.0, 0.0};
-        if (live) {
-            double sn, cs;
-            sincos(va[so + j], &sn, &cs);
-            const double v = vm[so + j];
-            Uj = {cs, sn};
-            yv = cmul(Y, {v * cs, v * sn});
-            s_yv[0][k] = yv.re;
-            s_yv[1][k] = yv.im;
-            if (diag) {  // the diagonal nonzero carries the row's own phasor
-                s_row[2][row] = v * cs;
-                s_row[3][row] = v * sn;
-                s_u[0][row] = cs;
-                s_u[1][row] = sn;
-            }
+    const int lj = live ? j : c.r0;  // idle lanes load a valid bus (unconditional loads)
+    struct In {
+        double v, th;
+    };
+    auto load = [&](int s, In &x) {
+        x.v = vm[(size_t)s * nb + lj];
+        x.th = va[(size_t)s * nb + lj];
+    };
+    const bool woff = live && !diag;
+    const int t11 = woff ? o11 : 4 * NT, t12 = woff ? o12 : 4 * NT;
+    const int t21 = woff ? 2 * NT + o11 : 4 * NT + 1, t22 = woff ? 2 * NT + o12 : 4 * NT + 1;
+    const int dd11 = s_yrow[rowt ? k : 0] + dl, dd12 = s_yrow[rowt ? k + 1 : 1] + dl;
+    const int u11 = rowt ? dd11 : 4 * NT, u12 = rowt ? dd12 : 4 * NT;
+    const int u21 = rowt ? 2 * NT + dd11 : 4 * NT + 1, u22 = rowt ? 2 * NT + dd12 : 4 * NT + 1;
+    // As in k_ew: every lane computes, only LDS writes and stores depend on
+    // the lane's role (idle lanes have Y = 0 and a valid bus).
+    auto proc = [&](int s, int p, const In &x) {
+        double sn, cs;
+        sincos_dev(x.th, &sn, &cs);
+        const Cx Uj = {cs, sn};
+        const Cx yv = cmul(Y, {x.v * cs, x.v * sn});
+        s_yv[p][0][k] = yv.re;
+        s_yv[p][1][k] = yv.im;
+        if (diag) {  // the diagonal nonzero carries the row's own phasor
+            s_vu[p][0][row] = x.v * cs;
+            s_vu[p][1][row] = x.v * sn;
+            s_vu[p][2][row] = cs;
+            s_vu[p][3][row] = sn;
         }
-        __syncthreads();
-        if (diag) {
-            const int a = s_yrow[row], z = s_yrow[row + 1];
-            Cx I = {0.0, 0.0};
-            for (int q = a; q < z; ++q) {
-                I.re += s_yv[0][q];
-                I.im += s_yv[1][q];
-            }
-            s_row[0][row] = I.re;
-            s_row[1][row] = I.im;
-        }
-        __syncthreads();
-        if (P) {
-            for (int q = k; q < c.nrows; q += NT) {
-                const Cx S = cmul({s_row[2][q], s_row[3][q]}, {s_row[0][q], -s_row[1][q]});
-                P[so + c.r0 + q] = S.re;
-                Q[so + c.r0 + q] = S.im;
-            }
+        lds_barrier();
+        Cx I;
+        row_sum2(s_yv[p][0], s_yv[p][1], ra, rz, I.re, I.im);
+        const int kr = rowt ? k : 0;
+        const Cx Vk = {s_vu[p][0][kr], s_vu[p][1][kr]};
+        const Cx Ic = {I.re, -I.im};
+        const Cx S = cmul(Vk, Ic);
+        if (P && rowt) {
+            P[(size_t)s * nb + ir] = S.re;
+            Q[(size_t)s * nb + ir] = S.im;
         }
         if constexpr (WITH_J) {
-            if (live) {
-                const Cx Vi = {s_row[2][row], s_row[3][row]};
-                const Cx Ic = {s_row[0][row], -s_row[1][row]};
-                const Cx x = csub(diag ? Ic : Cx{0.0, 0.0}, cconj(yv));
-                const Cx dst = cmul({-Vi.im, Vi.re}, x);
-                Cx dsv = cmul(Vi, cconj(cmul(Y, Uj)));
-                if (diag) dsv = cadd(dsv, cmul(Ic, {s_u[0][row], s_u[1][row]}));
-                s_J[o11] = dst.re;
-                s_J[o12] = dsv.re;
-                s_J[2 * NT + o11] = dst.im;
-                s_J[2 * NT + o12] = dsv.im;
-            }
-            __syncthreads();
-            write_jrows<NT>(c, s_J, J + (size_t)s * (size_t)g.nnz_j);
+            // diagonal entry of row k (Y_ii V_i recomputed from Y_ii and V_i)
+            const Cx Ui = {s_vu[p][2][kr], s_vu[p][3][kr]};
+            const Cx yu = cmul(Yd, Ui);
+            const Cx yvi = cmul(Yd, Vk);
+            const Cx x2 = {Ic.re - yvi.re, Ic.im + yvi.im};
+            const Cx dst = cmul({-Vk.im, Vk.re}, x2);
+            const Cx dsv = cadd(cmul(Vk, cconj(yu)), cmul(Ic, Ui));
+            s_J[p][u11] = dst.re;
+            s_J[p][u12] = dsv.re;
+            s_J[p][u21] = dst.im;
+            s_J[p][u22] = dsv.im;
+            // off-diagonal entry of this nonzero
+            const Cx Vi = {s_vu[p][0][row], s_vu[p][1][row]};
+            const Cx dso = cmul({-Vi.im, Vi.re}, {-yv.re, yv.im});  // j V_i (-conj(Y_ij V_j))
+            const Cx dvo = cmul(Vi, cconj(cmul(Y, Uj)));
+            s_J[p][t11] = dso.re;
+            s_J[p][t12] = dvo.re;
+            s_J[p][t21] = dso.im;
+            s_J[p][t22] = dvo.im;
+            lds_barrier();
+            write_jrows<NT>(c, s_J[p], J + (size_t)s * (size_t)g.nnz_j);
         }
-        __syncthreads();
-    }
+    };
+    pipelined_states<In>(sb, se, load, proc);
 }
 
 // ===================================================================
@@ -544,167 +638,226 @@ __global__ void __launch_bounds__(NT)
 // partials of every record at bus i (rows P_i, Q_i) and the remote partials
 // of the opposite end of each incident branch (rows P_j, Q_j).  Record e (at
 // i, towards j) therefore contributes to bus i
-//   g_va += lP_i (-w beta) + lQ_i (w alpha) + lP_j (w beta') - lQ_j (w alpha')
-//   g_vm += lP_i (2 v_i A + v_j alpha) + lQ_i (v_j beta - 2 v_i C)
-//         + lP_j (v_j alpha') + lQ_j (v_j beta')
+//   g_va += v_i v_j (lQ_i alpha - lP_i beta + lP_j beta' - lQ_j alpha')
+//   g_vm += v_j (lP_i alpha + lQ_i beta + lP_j alpha' + lQ_j beta')
 // where alpha', beta' use the other end's coupling (Gr, Br) at angle -t:
-//   alpha' = Gr cos t - Br sin t,  beta' = -Gr sin t - Br cos t.
-// Sums per bus run in record order; J is never formed.
+//   alpha' = Gr cos t - Br sin t,  beta' = -Gr sin t - Br cos t,
+// and the own-end terms add 2 v_i (lP_i dA_i - lQ_i dC_i) to g_vm once per
+// bus.  Sums per bus run in record order; J is never formed.
+struct VjpIn {
+    double vi, ti, vj, tj, lpi, lqi, lpj, lqj;
+};
+
+__device__ __forceinline__ void vjp_record(const VjpIn &x, double G, double B, double Gr, double Br, double &ga,
+                                           double &gv) {
+    double sn, cs;
+    sincos_dev(x.ti - x.tj, &sn, &cs);
+    const double al = fma(G, cs, B * sn), be = fma(G, sn, -(B * cs));
+    const double al2 = fma(Gr, cs, -(Br * sn)), be2 = fma(-Gr, sn, -(Br * cs));
+    const double ta = fma(-x.lqj, al2, fma(x.lpj, be2, fma(-x.lpi, be, x.lqi * al)));
+    const double tv = fma(x.lqj, be2, fma(x.lpj, al2, fma(x.lqi, be, x.lpi * al)));
+    ga = (x.vi * x.vj) * ta;
+    gv = x.vj * tv;
+}
+
+// g_vm of bus i: the record sum plus the own-end term 2 v_i (lP_i dA_i - lQ_i dC_i).
+__device__ __forceinline__ double vjp_own(double sum, double vi, double lpi, double lqi, double dA, double dC) {
+    return fma(2.0 * vi, fma(lpi, dA, -(lqi * dC)), sum);
+}
+
 template <int NT>
 __global__ void __launch_bounds__(NT)
-    k_ew_vjp(DevGrid g, int nstate, int spb, int nchunk, const double *__restrict__ vm,
+    k_ew_vjp(DevGrid g, int nstate, int spb, int nchunk, bool state_major, const double *__restrict__ vm,
              const double *__restrict__ va, const double *__restrict__ lp, const double *__restrict__ lq,
              double *__restrict__ gvm, double *__restrict__ gva) {
     __shared__ int s_irow[NT + 1];
     __shared__ int s_yrow[NT + 1];
-    __shared__ double s_val[2][NT];
-    __shared__ double s_out[2][NT];
+    __shared__ double s_val[2][2][NT];
 
     const int W = g.ntiles * nchunk;
     const int w = work_index(gridDim.x);
     if (w >= W) return;
-    const int t = w / nchunk;
-    const int sb = (w - t * nchunk) * spb;
+    const int t = state_major ? w % g.ntiles : w / nchunk;
+    const int sb = (state_major ? w / g.ntiles : w - t * nchunk) * spb;
     const int se = min(nstate, sb + spb);
     const Tile c = tile_of(g, t);
     const int k = threadIdx.x;
     const size_t nb = (size_t)g.nb;
 
-    auto record = [&](int e, int i, size_t so, double &ga, double &gv) {
-        const int j = g.nbr[e];
-        const double vi = vm[so + i], ti = va[so + i], vj = vm[so + j], tj = va[so + j];
-        const double lpi = lp[so + i], lqi = lq[so + i], lpj = lp[so + j], lqj = lq[so + j];
-        const double A = g.A[e], C = g.C[e], G = g.G[e], B = g.B[e], Gr = g.Gr[e], Br = g.Br[e];
-        double sn, cs;
-        sincos(ti - tj, &sn, &cs);
-        const double wv = vi * vj;
-        const double al = G * cs + B * sn, be = G * sn - B * cs;
-        const double al2 = Gr * cs - Br * sn, be2 = -(Gr * sn) - Br * cs;
-        ga = wv * (lqi * al - lpi * be + lpj * be2 - lqj * al2);
-        gv = lpi * (2.0 * vi * A + vj * al) + lqi * (vj * be - 2.0 * vi * C) + vj * (lpj * al2 + lqj * be2);
+    auto fetch = [&](size_t so, int i, int j) {
+        VjpIn x;
+        x.vi = vm[so + i];
+        x.ti = va[so + i];
+        x.vj = vm[so + j];
+        x.tj = va[so + j];
+        x.lpi = lp[so + i];
+        x.lqi = lq[so + i];
+        x.lpj = lp[so + j];
+        x.lqj = lq[so + j];
+        return x;
     };
 
     if (c.n > NT) {
         const int i = c.r0;
+        const double dA = g.dA[i], dC = g.dC[i];
         for (int s = sb; s < se; ++s) {
             const size_t so = (size_t)s * nb;
             double acc_a = 0.0, acc_v = 0.0;
             for (int base = 0; base < c.n; base += NT) {
                 if (base + k < c.n) {
+                    const int e = c.i0 + base + k;
                     double ga, gv;
-                    record(c.i0 + base + k, i, so, ga, gv);
-                    s_val[0][k] = ga;
-                    s_val[1][k] = gv;
+                    vjp_record(fetch(so, i, g.nbr[e]), g.G[e], g.B[e], g.Gr[e], g.Br[e], ga, gv);
+                    s_val[0][0][k] = ga;
+                    s_val[0][1][k] = gv;
                 }
                 __syncthreads();
                 if (k == 0) {
                     const int m = min(NT, c.n - base);
                     for (int q = 0; q < m; ++q) {
-                        acc_a += s_val[0][q];
-                        acc_v += s_val[1][q];
+                        acc_a += s_val[0][0][q];
+                        acc_v += s_val[0][1][q];
                     }
                 }
                 __syncthreads();
             }
             if (k == 0) {
+                const double vi = vm[so + i];
                 gva[so + i] = acc_a;
-                gvm[so + i] = acc_v;
+                gvm[so + i] = vjp_own(acc_v, vi, lp[so + i], lq[so + i], dA, dC);
             }
         }
         return;
     }
 
     stage_rows<NT>(g, c, s_irow, s_yrow);
-    __syncthreads();
     const bool live = k < c.n;
+    int j = 0;
+    double G = 0.0, B = 0.0, Gr = 0.0, Br = 0.0;
+    if (live) {
+        const int e = c.i0 + k;
+        j = g.nbr[e];
+        G = g.G[e];
+        B = g.B[e];
+        Gr = g.Gr[e];
+        Br = g.Br[e];
+    }
+    const bool rowt = k < c.nrows;
+    const int ir = c.r0 + k;
+    double dA = 0.0, dC = 0.0;
+    if (rowt) {
+        dA = g.dA[ir];
+        dC = g.dC[ir];
+    }
+    __syncthreads();
     const int row = live ? row_of(k, s_irow, c.nrows) : 0;
     const int i = c.r0 + row;
-    const bool head = live && s_irow[row] == k;  // first record of the row sums it
-    for (int s = sb; s < se; ++s) {
-        const size_t so = (size_t)s * nb;
-        if (live) {
-            double ga, gv;
-            record(c.i0 + k, i, so, ga, gv);
-            s_val[0][k] = ga;
-            s_val[1][k] = gv;
-        }
-        __syncthreads();
-        if (head) {
-            double a = 0.0, v = 0.0;
-            for (int q = s_irow[row]; q < s_irow[row + 1]; ++q) {
-                a += s_val[0][q];
-                v += s_val[1][q];
-            }
-            s_out[0][row] = a;
-            s_out[1][row] = v;
-        }
-        __syncthreads();
-        for (int q = k; q < c.nrows; q += NT) {
-            gva[so + c.r0 + q] = s_out[0][q];
-            gvm[so + c.r0 + q] = s_out[1][q];
-        }
-        __syncthreads();
+    int ra = 0, rz = 0;
+    if (rowt) {
+        ra = s_irow[k];
+        rz = s_irow[k + 1];
     }
+    const int li = live ? i : c.r0, lj = live ? j : c.r0, lr = rowt ? ir : c.r0;  // unconditional loads
+    struct In {
+        VjpIn x;
+        double vr, lpr, lqr;
+    };
+    auto load = [&](int s, In &in) {
+        const size_t so = (size_t)s * nb;
+        in.x = fetch(so, li, lj);
+        in.vr = vm[so + lr];
+        in.lpr = lp[so + lr];
+        in.lqr = lq[so + lr];
+    };
+    // As in k_ew: every lane computes; stores depend on the lane's role.
+    auto proc = [&](int s, int p, const In &in) {
+        double ga, gv;
+        vjp_record(in.x, G, B, Gr, Br, ga, gv);
+        s_val[p][0][k] = ga;
+        s_val[p][1][k] = gv;
+        lds_barrier();
+        double a, v;
+        row_sum2(s_val[p][0], s_val[p][1], ra, rz, a, v);
+        const double gm = vjp_own(v, in.vr, in.lpr, in.lqr, dA, dC);
+        if (rowt) {
+            const size_t so = (size_t)s * nb;
+            gva[so + ir] = a;
+            gvm[so + ir] = gm;
+        }
+    };
+    pipelined_states<In>(sb, se, load, proc);
 }
 
 // ===================================================================
-// Setup: record constants from the branch parameters.
+// Setup: record coupling admittances from the branch parameters.
+__device__ __forceinline__ void branch_admittances(const DevSetup &s, int l, double &gsr, double &bsr, double &m,
+                                                   double &bh, double &sp, double &cp) {
+    const double r = s.r[l], x = s.x[l];
+    const double den = r * r + x * x;
+    gsr = r / den;  // y_hk = 1/(r + jx)
+    bsr = -x / den;
+    m = s.tap[l] == 0.0 ? 1.0 : s.tap[l];
+    bh = 0.5 * s.b[l];
+    sincos_dev(s.shift[l], &sp, &cp);
+}
+
 __global__ void k_items_init(DevSetup s) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= s.nitems) return;
     const int br = s.item_br[e];
-    if (br < 0) {  // bus shunt record
-        const int i = s.nbr[e];
-        s.A[e] = s.gs[i];
-        s.C[e] = s.bs[i];
+    if (br < 0) {  // bus shunt record: no coupling
         s.G[e] = 0.0;
         s.B[e] = 0.0;
         s.Gr[e] = 0.0;
         s.Br[e] = 0.0;
         return;
     }
-    const int l = br >> 1;
-    const bool to_end = (br & 1) != 0;
-    const double r = s.r[l], x = s.x[l];
-    const double den = r * r + x * x;
-    const double gsr = r / den, bsr = -x / den;  // y_hk = 1/(r + jx)
-    const double m = s.tap[l] == 0.0 ? 1.0 : s.tap[l];
-    const double bh = 0.5 * s.b[l];
-    double sp, cp;
-    sincos(s.shift[l], &sp, &cp);
+    double gsr, bsr, m, bh, sp, cp;
+    branch_admittances(s, br >> 1, gsr, bsr, m, bh, sp, cp);
     // -y_hk e^{+j phi}/m (from end) and -y_hk e^{-j phi}/m (to end)
     const double gf = -(gsr * cp - bsr * sp) / m, bf = -(gsr * sp + bsr * cp) / m;
     const double gt = -(gsr * cp + bsr * sp) / m, bt = -(bsr * cp - gsr * sp) / m;
-    if (!to_end) {
-        s.A[e] = gsr / (m * m);
-        s.C[e] = (bsr + bh) / (m * m);
-        s.G[e] = gf;
-        s.B[e] = bf;
-        s.Gr[e] = gt;
-        s.Br[e] = bt;
-    } else {
-        s.A[e] = gsr;
-        s.C[e] = bsr + bh;
-        s.G[e] = gt;
-        s.B[e] = bt;
-        s.Gr[e] = gf;
-        s.Br[e] = bf;
-    }
+    const bool to_end = (br & 1) != 0;
+    s.G[e] = to_end ? gt : gf;
+    s.B[e] = to_end ? bt : bf;
+    s.Gr[e] = to_end ? gf : gt;
+    s.Br[e] = to_end ? bf : bt;
 }
 
-// Setup: Ybus values.  The diagonal sums the own-end admittances of all
-// records of the row (shunt included); an off-diagonal slot sums the
-// coupling admittances of its records (more than one for parallel branches).
+// Setup: per bus, the sum in record order of the own-end admittances
+// ((y_h + y_hk)/m^2 at a from end, y_k + y_hk at a to end) and the shunt.
+__global__ void k_bus_diag(DevSetup s) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= s.nb) return;
+    double re = 0.0, im = 0.0;
+    for (int e = s.irow[i]; e < s.irow[i + 1]; ++e) {
+        const int br = s.item_br[e];
+        if (br < 0) {
+            re += s.gs[i];
+            im += s.bs[i];
+            continue;
+        }
+        double gsr, bsr, m, bh, sp, cp;
+        branch_admittances(s, br >> 1, gsr, bsr, m, bh, sp, cp);
+        const double f = (br & 1) ? 1.0 : 1.0 / (m * m);
+        re += gsr * f;
+        im += (bsr + bh) * f;
+    }
+    s.dA[i] = re;
+    s.dC[i] = im;
+}
+
+// Setup: Ybus values.  The diagonal is the bus constant above; an
+// off-diagonal slot sums the coupling admittances of its records (more than
+// one for parallel branches) in record order.
 __global__ void k_ybus_assemble(DevSetup s) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= s.nnz_y) return;
     const int i = s.slot_row[p];
     double re = 0.0, im = 0.0;
     if (s.ycol[p] == i) {
-        for (int e = s.irow[i]; e < s.irow[i + 1]; ++e) {
-            re += s.A[e];
-            im += s.C[e];
-        }
+        re = s.dA[i];
+        im = s.dC[i];
     } else {
         for (int e = s.slot_item[p]; e < s.slot_item[p + 1]; ++e) {
             re += s.G[e];
@@ -726,36 +879,65 @@ hipError_t launch_nt(const DevGrid &g, const Launch &L, hipStream_t st) {
     switch (L.kind) {
         case K_EW_S:
             if (L.has_parallel)
-                hipLaunchKernelGGL((k_ew<NT, true, false>), grid, block, 0, st, g, L.nstate, spb, nchunk, L.vm, L.va,
+                hipLaunchKernelGGL((k_ew<NT, true, false>), grid, block, 0, st, g, L.nstate, spb, nchunk, L.state_major, L.vm, L.va,
                                    L.p, L.q, nullptr);
             else
-                hipLaunchKernelGGL((k_ew<NT, false, false>), grid, block, 0, st, g, L.nstate, spb, nchunk, L.vm, L.va,
+                hipLaunchKernelGGL((k_ew<NT, false, false>), grid, block, 0, st, g, L.nstate, spb, nchunk, L.state_major, L.vm, L.va,
                                    L.p, L.q, nullptr);
             break;
         case K_EW_SJ:
             if (L.has_parallel)
-                hipLaunchKernelGGL((k_ew<NT, true, true>), grid, block, 0, st, g, L.nstate, spb, nchunk, L.vm, L.va,
+                hipLaunchKernelGGL((k_ew<NT, true, true>), grid, block, 0, st, g, L.nstate, spb, nchunk, L.state_major, L.vm, L.va,
                                    L.p, L.q, L.jval);
             else
-                hipLaunchKernelGGL((k_ew<NT, false, true>), grid, block, 0, st, g, L.nstate, spb, nchunk, L.vm, L.va,
+                hipLaunchKernelGGL((k_ew<NT, false, true>), grid, block, 0, st, g, L.nstate, spb, nchunk, L.state_major, L.vm, L.va,
                                    L.p, L.q, L.jval);
             break;
         case K_YB_S:
-            hipLaunchKernelGGL((k_ybus<NT, false>), grid, block, 0, st, g, L.nstate, spb, nchunk, L.vm, L.va, L.p, L.q,
+            hipLaunchKernelGGL((k_ybus<NT, false>), grid, block, 0, st, g, L.nstate, spb, nchunk, L.state_major, L.vm, L.va, L.p, L.q,
                                nullptr);
             break;
         case K_YB_SJ:
-            hipLaunchKernelGGL((k_ybus<NT, true>), grid, block, 0, st, g, L.nstate, spb, nchunk, L.vm, L.va, L.p, L.q,
+            hipLaunchKernelGGL((k_ybus<NT, true>), grid, block, 0, st, g, L.nstate, spb, nchunk, L.state_major, L.vm, L.va, L.p, L.q,
                                L.jval);
             break;
         case K_EW_VJP:
-            hipLaunchKernelGGL((k_ew_vjp<NT>), grid, block, 0, st, g, L.nstate, spb, nchunk, L.vm, L.va, L.lp, L.lq,
+            hipLaunchKernelGGL((k_ew_vjp<NT>), grid, block, 0, st, g, L.nstate, spb, nchunk, L.state_major, L.vm, L.va, L.lp, L.lq,
                                L.gvm, L.gva);
             break;
         default:
             return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+template <int NT>
+int occupancy_nt(int kind, bool par) {
+    int n = 0;
+    hipError_t e = hipErrorInvalidValue;
+    auto q = [&](const void *f) { e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, NT, 0); };
+    switch (kind) {
+        case K_EW_S:
+            q(par ? reinterpret_cast<const void *>(&k_ew<NT, true, false>)
+                  : reinterpret_cast<const void *>(&k_ew<NT, false, false>));
+            break;
+        case K_EW_SJ:
+            q(par ? reinterpret_cast<const void *>(&k_ew<NT, true, true>)
+                  : reinterpret_cast<const void *>(&k_ew<NT, false, true>));
+            break;
+        case K_YB_S:
+            q(reinterpret_cast<const void *>(&k_ybus<NT, false>));
+            break;
+        case K_YB_SJ:
+            q(reinterpret_cast<const void *>(&k_ybus<NT, true>));
+            break;
+        case K_EW_VJP:
+            q(reinterpret_cast<const void *>(&k_ew_vjp<NT>));
+            break;
+        default:
+            break;
+    }
+    return e == hipSuccess ? n : 0;
 }
 
 }  // namespace
@@ -775,10 +957,45 @@ hipError_t launch_eval(const DevGrid &g, const Launch &L, hipStream_t stream) {
     }
 }
 
+int resident_blocks_per_cu(int kind, int tile_items, bool has_parallel) {
+    // One value per (kind, tile size, parallel flag): a property of the
+    // compiled kernel and the device, so concurrent first calls agree.
+    static std::atomic<int> cache[5][4][2] = {};
+    if (kind < 0 || kind > 4) return 0;
+    const int ti = tile_items == 64 ? 0 : tile_items == 128 ? 1 : tile_items == 256 ? 2 : tile_items == 512 ? 3 : -1;
+    if (ti < 0) return 0;
+    std::atomic<int> &slot = cache[kind][ti][has_parallel ? 1 : 0];
+    int v = slot.load();
+    if (v > 0) return v;
+    switch (tile_items) {
+        case 64:
+            v = occupancy_nt<64>(kind, has_parallel);
+            break;
+        case 128:
+            v = occupancy_nt<128>(kind, has_parallel);
+            break;
+        case 256:
+            v = occupancy_nt<256>(kind, has_parallel);
+            break;
+        default:
+            v = occupancy_nt<512>(kind, has_parallel);
+            break;
+    }
+    slot.store(v);
+    return v;
+}
+
 hipError_t launch_setup_items(const DevSetup &s, hipStream_t stream) {
-    if (s.nitems == 0) return hipSuccess;
-    const int64_t blocks = (s.nitems + 255) / 256;
-    hipLaunchKernelGGL(k_items_init, dim3((unsigned)blocks), dim3(256), 0, stream, s);
+    if (s.nitems > 0) {
+        const int64_t blocks = (s.nitems + 255) / 256;
+        hipLaunchKernelGGL(k_items_init, dim3((unsigned)blocks), dim3(256), 0, stream, s);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (s.nb > 0) {
+        const int64_t blocks = (s.nb + 255) / 256;
+        hipLaunchKernelGGL(k_bus_diag, dim3((unsigned)blocks), dim3(256), 0, stream, s);
+    }
     return hipGetLastError();
 }
 

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(HERE, "libpf.so")
 PF_OK, PF_EINVAL, PF_ENOMEM, PF_EHIP, PF_ESTATE, PF_EUNSUP = range(6)
 PF_METHOD_ELEMENTWISE, PF_METHOD_YBUS = 0, 1
 PF_BUILD_HOST_ONLY = 1
+PF_ORDER_AUTO, PF_ORDER_TILE_MAJOR, PF_ORDER_STATE_MAJOR = 0, 1, 2
 
 EXPORTS = (
     "pf_build_pattern", "pf_grid_free", "pf_grid_sizes", "pf_pattern_sizes", "pf_grid_offsets",
@@ -59,8 +60,8 @@ def lib() -> C.CDLL:
         L.pf_injections_ybus.argtypes = [P, i32, P, P, P, P, P]
         L.pf_jacobian_values.argtypes = [P, i32, i32, P, P, P, P, P, P]
         L.pf_injections_vjp.argtypes = [P, i32, P, P, P, P, P, P, P]
-        L.pf_set_schedule.argtypes = [P, i32, i32]
-        L.pf_get_schedule.argtypes = [P, P, P, P]
+        L.pf_set_schedule.argtypes = [P, i32, i32, i32]
+        L.pf_get_schedule.argtypes = [P, P, P, P, P]
         L.pf_last_error.restype = C.c_char_p
         L.pf_last_error.argtypes = []
         L.pf_version.restype = C.c_char_p
@@ -162,13 +163,14 @@ class Grid:
         check(lib().pf_pattern_export(self._h, _hp(yr), _hp(yc), _hp(jr), _hp(jc)))
         return yr, yc[: self.nnz_y], jr, jc[: self.nnz_j]
 
-    def set_schedule(self, tile_items=256, states_per_block=0):
-        check(lib().pf_set_schedule(self._h, int(tile_items), int(states_per_block)))
+    def set_schedule(self, tile_items=256, states_per_block=0, order=PF_ORDER_AUTO):
+        check(lib().pf_set_schedule(self._h, int(tile_items), int(states_per_block), int(order)))
 
     def schedule(self):
-        a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
-        check(lib().pf_get_schedule(self._h, C.byref(a), C.byref(b), C.byref(c)))
-        return a.value, b.value, c.value
+        """(tile_items, states_per_block, order, ntiles)."""
+        a, b, c, d = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        check(lib().pf_get_schedule(self._h, C.byref(a), C.byref(b), C.byref(c), C.byref(d)))
+        return a.value, b.value, c.value, d.value
 
 
 def _nstate(vm, nb):

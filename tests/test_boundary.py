@@ -195,13 +195,17 @@ def test_schedule_choices():
     G = pf.Grid.from_grid(gridgen.config0(), host_only=True)
     for cap in (64, 128, 256, 512):
         G.set_schedule(cap, 0)
-        t, spb, nt = G.schedule()
+        t, spb, order, nt = G.schedule()
         assert t == cap and nt >= (500 + 1900) // cap // 2
     with pytest.raises(pf.PFError) as e:
         G.set_schedule(100, 0)
     assert e.value.code == pf.PF_EINVAL
     with pytest.raises(pf.PFError):
         G.set_schedule(256, -1)
+    with pytest.raises(pf.PFError):
+        G.set_schedule(256, 0, 7)
+    G.set_schedule(128, 3, pf.PF_ORDER_STATE_MAJOR)
+    assert G.schedule()[:3] == (128, 3, pf.PF_ORDER_STATE_MAJOR)
 
 
 def test_binding_refuses_host_arrays():

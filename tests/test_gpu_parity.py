@@ -23,10 +23,10 @@ def _gpu():
     require_gpu()
 
 
-def check_single(g, vm, va, tile=256, spb=0, use_scale=False, lam=True):
+def check_single(g, vm, va, tile=256, spb=0, use_scale=False, lam=True, order=pf.PF_ORDER_AUTO):
     """Build a handle, run every call on states [ns, nb], compare each state."""
     G = pf.Grid.from_grid(g)
-    G.set_schedule(tile, spb)
+    G.set_schedule(tile, spb, order)
     ns = vm.shape[0]
     rng = np.random.default_rng(5)
     lp = rng.normal(size=vm.shape) if lam else None
@@ -95,11 +95,12 @@ def test_shunt_only_buses():
     assert np.allclose(gres["q_ew"][0], -(vm ** 2) * bs, rtol=1e-15, atol=0)
 
 
+@pytest.mark.parametrize("order", [pf.PF_ORDER_TILE_MAJOR, pf.PF_ORDER_STATE_MAJOR])
 @pytest.mark.parametrize("spb", [0, 1, 3, 8, 64])
-def test_batched_states_ragged(spb):
+def test_batched_states_ragged(spb, order):
     g = gridgen.config0()
     vm, va = gridgen.states(g.nb, 37, cfg=0)
-    check_single(g, vm, va, tile=128, spb=spb)
+    check_single(g, vm, va, tile=128, spb=spb, order=order)
 
 
 def test_zero_states_is_a_no_op():
@@ -150,10 +151,11 @@ def test_determinism_across_runs_and_schedules():
             assert np.array_equal(ref[k], again[k]), k
     for tile in (64, 128, 512):
         for spb in (1, 2):
-            G.set_schedule(tile, spb)
-            other = gpu_all(G, vm, va, lp, lq)
-            for k in ref:
-                assert np.array_equal(ref[k], other[k]), (k, tile, spb)
+            for order in (pf.PF_ORDER_TILE_MAJOR, pf.PF_ORDER_STATE_MAJOR):
+                G.set_schedule(tile, spb, order)
+                other = gpu_all(G, vm, va, lp, lq)
+                for k in ref:
+                    assert np.array_equal(ref[k], other[k]), (k, tile, spb, order)
 
 
 def test_ybus_required_before_ybus_calls():
