@@ -63,6 +63,7 @@ struct pf_grid {
     int32_t tile_items = 256, states_per_block = 0, order = PF_ORDER_AUTO;
     std::vector<pf::TileDesc> tiles;
     int32_t num_cus = 0;
+    pf::DevLaneFill lanes{};  // gather sources and targets of the lane values
 
     void *dmem = nullptr;   // grid data
     void *dtile = nullptr;  // schedule
@@ -120,6 +121,80 @@ void build_tiles(pf_grid *g, int cap) {
     }
 }
 
+// Lane tables of the packed tiles (tile size NT).  Positions inside the LDS
+// copy of a tile's J rows: the P rows take [0, 2 NT), the Q rows start at
+// 2 NT + 2, and position 2 NT (Q: 4 NT + 2) is a pad that absorbs the
+// writes of lanes with nothing to write.  For row r of a tile with local
+// slot range [ya, yz) and local slot ls, dP/dtheta sits at ya + ls and
+// dP/dv at yz + ls (Section IV.B.2: J11 and J12 entries of one row are
+// adjacent, as are J21 and J22).
+struct HostLanes {
+    std::vector<int32_t> lane_j, lane_rec, ylane_j, ylane_slot;
+    std::vector<int32_t> lane_pk, ylane_pk;  // pairs
+    std::vector<int32_t> row_ew, row_yb;     // pairs per bus
+};
+
+HostLanes build_lanes(const pf_grid *g) {
+    const int NT = g->tile_items;
+    const int32_t pad = 2 * NT;
+    const size_t nl = g->tiles.size() * (size_t)NT;
+    HostLanes h;
+    h.lane_j.assign(nl, 0);
+    h.lane_rec.assign(nl, -1);
+    h.ylane_j.assign(nl, 0);
+    h.ylane_slot.assign(nl, -1);
+    h.lane_pk.assign(2 * nl, 0);
+    h.ylane_pk.assign(2 * nl, 0);
+    h.row_ew.assign(2 * (size_t)g->nb, 0);
+    h.row_yb.assign(2 * (size_t)g->nb, 0);
+    const int32_t padpair = pad | (pad << 16);
+    for (size_t t = 0; t < g->tiles.size(); ++t) {
+        const pf::TileDesc &c = g->tiles[t];
+        const size_t base = t * NT;
+        for (int k = 0; k < NT; ++k) {
+            h.lane_j[base + k] = c.r0;
+            h.ylane_j[base + k] = c.r0;
+            h.lane_pk[2 * (base + k)] = padpair;
+            h.ylane_pk[2 * (base + k)] = padpair;
+        }
+        if (c.n > NT) continue;  // long row: walked without lane tables
+        for (int32_t row = 0; row < c.nrows; ++row) {
+            const int32_t i = c.r0 + row;
+            const int32_t ya = g->yrow[i] - c.s0, yz = g->yrow[i + 1] - c.s0;
+            const int32_t ra = g->irow[i] - c.i0, rz = g->irow[i + 1] - c.i0;
+            int32_t dls = ya;
+            for (int32_t q = g->yrow[i]; q < g->yrow[i + 1]; ++q)
+                if (g->ycol[q] == i) dls = q - c.s0;
+            h.row_ew[2 * i] = ra | (rz << 16);
+            h.row_ew[2 * i + 1] = (ya + dls) | ((yz + dls) << 16);
+            h.row_yb[2 * i] = ya | (yz << 16);
+            h.row_yb[2 * i + 1] = dls;
+            for (int32_t e = g->irow[i]; e < g->irow[i + 1]; ++e) {
+                const size_t L = base + (e - c.i0);
+                const int32_t j = g->nbr[e], ls = g->slot[e] - c.s0;
+                const bool head = j != i && (e == g->irow[i] || g->slot[e - 1] != g->slot[e]);
+                int32_t run = 0;
+                if (head)
+                    while (e + run < g->irow[i + 1] && g->slot[e + run] == g->slot[e]) ++run;
+                h.lane_j[L] = j;
+                h.lane_rec[L] = e;
+                h.lane_pk[2 * L] = head ? ((ya + ls) | ((yz + ls) << 16)) : padpair;
+                h.lane_pk[2 * L + 1] = row | (run << 16);
+            }
+            for (int32_t q = g->yrow[i]; q < g->yrow[i + 1]; ++q) {
+                const size_t L = base + (q - c.s0);
+                const int32_t ls = q - c.s0;
+                const bool dg = g->ycol[q] == i;
+                h.ylane_j[L] = g->ycol[q];
+                h.ylane_slot[L] = q;
+                h.ylane_pk[2 * L] = dg ? padpair : ((ya + ls) | ((yz + ls) << 16));
+                h.ylane_pk[2 * L + 1] = row | ((dg ? 1 : 0) << 16);
+            }
+        }
+    }
+    return h;
+}
+
 int upload_tiles(pf_grid *g) {
     if (g->host_only) return PF_OK;
     hipError_t e;
@@ -128,18 +203,68 @@ int upload_tiles(pf_grid *g) {
         g->dtile = nullptr;
         if (e != hipSuccess) return hip_fail(e, "hipFree(schedule)");
     }
-    size_t nt = g->tiles.size();
-    size_t bytes = nt * sizeof(pf::TileDesc);
-    e = hipMalloc(&g->dtile, bytes);
+    const HostLanes h = build_lanes(g);
+    const size_t nt = g->tiles.size();
+    const size_t nl = nt * (size_t)g->tile_items;
+    Arena ar;
+    const size_t o_t = ar.take<pf::TileDesc>(nt);
+    const size_t o_lj = ar.take<int32_t>(nl), o_lrec = ar.take<int32_t>(nl), o_lpk = ar.take<int2>(nl);
+    const size_t o_lgb = ar.take<double2>(nl), o_lgr = ar.take<double2>(nl), o_rew = ar.take<int2>(g->nb);
+    const size_t o_yj = ar.take<int32_t>(nl), o_yslot = ar.take<int32_t>(nl), o_ypk = ar.take<int2>(nl);
+    const size_t o_yy = ar.take<double2>(nl), o_ryb = ar.take<int2>(g->nb);
+    e = hipMalloc(&g->dtile, ar.off);
     if (e != hipSuccess) {
         g->dtile = nullptr;
         return e == hipErrorOutOfMemory ? fail(PF_ENOMEM, "device allocation of the schedule failed")
                                         : hip_fail(e, "hipMalloc(schedule)");
     }
-    e = hipMemcpy(g->dtile, g->tiles.data(), bytes, hipMemcpyHostToDevice);
-    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(schedule)");
-    g->dev.tiles = static_cast<const pf::TileDesc *>(g->dtile);
-    g->dev.ntiles = (int32_t)nt;
+    char *base = static_cast<char *>(g->dtile);
+    hipError_t ee = hipSuccess;
+    auto up = [&](size_t off, const void *src, size_t bytes) {
+        if (ee == hipSuccess && bytes) ee = hipMemcpy(base + off, src, bytes, hipMemcpyHostToDevice);
+    };
+    up(o_t, g->tiles.data(), nt * sizeof(pf::TileDesc));
+    up(o_lj, h.lane_j.data(), nl * 4);
+    up(o_lrec, h.lane_rec.data(), nl * 4);
+    up(o_lpk, h.lane_pk.data(), nl * 8);
+    up(o_rew, h.row_ew.data(), (size_t)g->nb * 8);
+    up(o_yj, h.ylane_j.data(), nl * 4);
+    up(o_yslot, h.ylane_slot.data(), nl * 4);
+    up(o_ypk, h.ylane_pk.data(), nl * 8);
+    up(o_ryb, h.row_yb.data(), (size_t)g->nb * 8);
+    if (ee != hipSuccess) return hip_fail(ee, "hipMemcpy(schedule)");
+    pf::DevGrid &d = g->dev;
+    d.tiles = reinterpret_cast<const pf::TileDesc *>(base + o_t);
+    d.ntiles = (int32_t)nt;
+    d.lane_j = reinterpret_cast<const int32_t *>(base + o_lj);
+    d.lane_pk = reinterpret_cast<const int2 *>(base + o_lpk);
+    d.lane_gb = reinterpret_cast<const double2 *>(base + o_lgb);
+    d.lane_grbr = reinterpret_cast<const double2 *>(base + o_lgr);
+    d.row_ew = reinterpret_cast<const int2 *>(base + o_rew);
+    d.ylane_j = reinterpret_cast<const int32_t *>(base + o_yj);
+    d.ylane_pk = reinterpret_cast<const int2 *>(base + o_ypk);
+    d.ylane_y = reinterpret_cast<const double2 *>(base + o_yy);
+    d.row_yb = reinterpret_cast<const int2 *>(base + o_ryb);
+    pf::DevLaneFill &f = g->lanes;
+    f.nlanes = (int64_t)nl;
+    f.lane_rec = reinterpret_cast<const int32_t *>(base + o_lrec);
+    f.ylane_slot = reinterpret_cast<const int32_t *>(base + o_yslot);
+    f.G = d.G;
+    f.B = d.B;
+    f.Gr = d.Gr;
+    f.Br = d.Br;
+    f.yre = d.yre;
+    f.yim = d.yim;
+    f.lane_gb = reinterpret_cast<double2 *>(base + o_lgb);
+    f.lane_grbr = reinterpret_cast<double2 *>(base + o_lgr);
+    f.ylane_y = reinterpret_cast<double2 *>(base + o_yy);
+    // Record constants exist once the setup kernels ran; Ybus values once
+    // pf_ybus ran.  Until then the Ybus lanes stay unfilled and the Ybus
+    // evaluation calls refuse to run.
+    e = pf::launch_lane_fill(f, true, nullptr);
+    if (e == hipSuccess && g->ybus_valid) e = pf::launch_lane_fill(f, false, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "lane table kernel");
     return PF_OK;
 }
 
@@ -581,6 +706,7 @@ int pf_ybus(pf_grid *g, double *y_re, double *y_im, void *stream) {
     hipStream_t s = static_cast<hipStream_t>(stream);
     const pf::DevSetup &d = g->setup;
     hipError_t e = pf::launch_ybus_assemble(d, s);
+    if (e == hipSuccess) e = pf::launch_lane_fill(g->lanes, false, s);
     if (e != hipSuccess) return hip_fail(e, "Ybus assembly launch");
     if (y_re) {
         e = hipMemcpyAsync(y_re, g->dev.yre, g->nnz_y * sizeof(double), hipMemcpyDeviceToDevice, s);

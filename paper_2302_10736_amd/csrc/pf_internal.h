@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime_api.h>
+#include <hip/hip_vector_types.h>
 #include <stdint.h>
 
 #include <string>
@@ -42,6 +43,28 @@ struct DevGrid {
     const double *dA, *dC;    // [nb] sum of own-end admittances + shunt (Re / Im)
     const double *yre, *yim;  // [nnz_y] Ybus values
     const TileDesc *tiles;    // [ntiles]
+
+    // Lane tables of the packed tiles, [ntiles * tile_items], entry
+    // t * tile_items + k for thread k of tile t (see pf_kernels.hip for the
+    // encodings).  Entries of idle lanes and of long-row tiles are inert.
+    const int32_t *lane_j;      // element-wise record: remote bus
+    const int2 *lane_pk;        // {o11 | o12 << 16, row | run << 16}
+    const double2 *lane_gb;     // {G, B}
+    const double2 *lane_grbr;   // {Gr, Br}
+    const int2 *row_ew;         // [nb] {ra | rz << 16, d11 | d12 << 16}
+    const int32_t *ylane_j;     // Ybus nonzero: column bus
+    const int2 *ylane_pk;       // {o11 | o12 << 16, row | diag << 16}
+    const double2 *ylane_y;     // {Re Y, Im Y}
+    const int2 *row_yb;         // [nb] {ya | yz << 16, dls}
+};
+
+// Gather sources of the lane tables: record (element-wise) and slot (Ybus)
+// of every lane, -1 for inert lanes.
+struct DevLaneFill {
+    int64_t nlanes;
+    const int32_t *lane_rec, *ylane_slot;
+    const double *G, *B, *Gr, *Br, *yre, *yim;
+    double2 *lane_gb, *lane_grbr, *ylane_y;
 };
 
 // Setup data, only read by the setup kernels.
@@ -80,6 +103,9 @@ hipError_t launch_eval(const DevGrid &g, const Launch &L, hipStream_t stream);
 // that one compute unit holds at once (0 if unknown).
 int resident_blocks_per_cu(int kind, int tile_items, bool has_parallel);
 hipError_t launch_setup_items(const DevSetup &s, hipStream_t stream);
+// Fill the element-wise (ew) or Ybus (!ew) lane values from the record /
+// slot arrays.
+hipError_t launch_lane_fill(const DevLaneFill &f, bool ew, hipStream_t stream);
 hipError_t launch_ybus_assemble(const DevSetup &s, hipStream_t stream);
 
 }  // namespace pf

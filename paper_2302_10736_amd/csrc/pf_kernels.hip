@@ -90,27 +90,20 @@ using Tile = TileDesc;
 
 __device__ __forceinline__ Tile tile_of(const DevGrid &g, int t) { return g.tiles[t]; }
 
-// Local row pointers of a packed tile (records and slots) into LDS.
+// LDS copy of one state's J rows of a packed tile: the P rows in [0, 2 NT),
+// the Q rows from kQ<NT> on, and one pad position (kPad<NT>, and
+// kQ<NT> + kPad<NT> on the Q side) that absorbs the writes of lanes with
+// nothing to write.  The Q offset keeps both halves 16-byte aligned.
 template <int NT>
-__device__ __forceinline__ void stage_rows(const DevGrid &g, const Tile &c, int *s_irow, int *s_yrow) {
-    for (int q = threadIdx.x; q <= c.nrows; q += NT) {
-        s_irow[q] = g.irow[c.r0 + q] - c.i0;
-        s_yrow[q] = g.yrow[c.r0 + q] - c.s0;
-    }
-}
+constexpr int kQ = 2 * NT + 2;
+template <int NT>
+constexpr int kPad = 2 * NT;
+template <int NT>
+constexpr int kJStage = 4 * NT + 4;
 
-// Largest q in [0, nrows) with rowptr[q] <= k.
-__device__ __forceinline__ int row_of(int k, const int *rowptr, int nrows) {
-    int lo = 0, hi = nrows - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (rowptr[mid] <= k)
-            lo = mid;
-        else
-            hi = mid - 1;
-    }
-    return lo;
-}
+// Two 16-bit fields of a lane-table word.
+__device__ __forceinline__ int lo16(int v) { return v & 0xffff; }
+__device__ __forceinline__ int hi16(int v) { return (int)((unsigned)v >> 16); }
 
 struct Cx {
     double re, im;
@@ -130,7 +123,7 @@ __device__ __forceinline__ void write_jrows(const Tile &c, const double *s_J, do
     double2 *dq = reinterpret_cast<double2 *>(Js + c.jq);
     for (int q = threadIdx.x; q < c.ns; q += NT) {
         dp[q] = src[q];
-        dq[q] = src[NT + q];
+        dq[q] = src[kQ<NT> / 2 + q];
     }
 }
 
@@ -140,8 +133,14 @@ __device__ __forceinline__ void write_jrows(const Tile &c, const double *s_J, do
 // make the wave wait for every outstanding memory operation, including the
 // previous state's stores.  `proc(s, parity, in)` gets parity = (s - sb) & 1
 // for the double-buffered LDS.
-template <class In, class Load, class Proc>
+template <class In, bool ONE, class Load, class Proc>
 __device__ __forceinline__ void pipelined_states(int sb, int se, Load &&load, Proc &&proc) {
+    if constexpr (ONE) {  // one state per workgroup: nothing to overlap, half the registers
+        In x{};
+        load(sb, x);
+        proc(sb, 0, x);
+        return;
+    }
     In ra{}, rb{};
     if (sb < se) load(sb, ra);
     for (int s = sb; s < se; s += 2) {
@@ -213,20 +212,17 @@ __device__ __forceinline__ EwRow ew_row(double vi, double dA, double dC, double 
 
 // ===================================================================
 // Element-wise injections (WITH_J = false) and injections + Jacobian values.
-template <int NT, bool PAR, bool WITH_J>
+template <int NT, bool PAR, bool WITH_J, bool ONE>
 __global__ void __launch_bounds__(NT)
     k_ew(DevGrid g, int nstate, int spb, int nchunk, bool state_major, const double *__restrict__ vm, const double *__restrict__ va,
          double *__restrict__ P, double *__restrict__ Q, double *__restrict__ J) {
     constexpr int NR = (WITH_J && PAR) ? NT : 1;  // remote partials kept for slot sums
-    __shared__ int s_irow[NT + 1];
-    __shared__ int s_yrow[NT + 1];
-    __shared__ int s_dslot[NT];
-    __shared__ double s_ab[2][2][NT];
-    // J stage: P rows in [0, 2 NT), Q rows in [2 NT, 4 NT), two pad slots
-    // (4 NT, 4 NT + 1) that absorb the writes of lanes with nothing to write
-    __shared__ __align__(16) double s_J[2][WITH_J ? 4 * NT + 2 : 2];
-    __shared__ double s_rem[2][4][NR];
-    __shared__ int s_slot[NR];
+    constexpr int NBUF = ONE ? 1 : 2;             // LDS buffers alternate between states
+    __shared__ int s_ls[NT];   // long rows: local slot of each record of a chunk
+    __shared__ int s_dslot[1];  // long rows: local diagonal slot
+    __shared__ double s_ab[NBUF][2][NT];
+    __shared__ __align__(16) double s_J[NBUF][WITH_J ? kJStage<NT> : 2];
+    __shared__ double s_rem[NBUF][4][NR];
 
     const int W = g.ntiles * nchunk;
     const int w = work_index(gridDim.x);
@@ -234,8 +230,13 @@ __global__ void __launch_bounds__(NT)
     const int t = state_major ? w % g.ntiles : w / nchunk;
     const int sb = (state_major ? w / g.ntiles : w - t * nchunk) * spb;
     const int se = min(nstate, sb + spb);
-    const Tile c = tile_of(g, t);
     const int k = threadIdx.x;
+    // lane table entries do not depend on the tile descriptor: both load at once
+    const size_t lane = (size_t)t * NT + k;
+    const int j = g.lane_j[lane];
+    const int2 pk = g.lane_pk[lane];
+    const double2 gb = g.lane_gb[lane];
+    const Tile c = tile_of(g, t);
     const size_t nb = (size_t)g.nb;
 
     if (c.n > NT) {
@@ -254,8 +255,8 @@ __global__ void __launch_bounds__(NT)
             for (int base = 0; base < c.n; base += NT) {
                 if (base + k < c.n) {
                     const int e = c.i0 + base + k;
-                    const int j = g.nbr[e];
-                    const EwRec r = ew_record(vi, ti, vms[j], vas[j], g.G[e], g.B[e]);
+                    const int je = g.nbr[e];
+                    const EwRec r = ew_record(vi, ti, vms[je], vas[je], g.G[e], g.B[e]);
                     s_ab[0][0][k] = r.a;
                     s_ab[0][1][k] = r.b;
                     if constexpr (WITH_J) {
@@ -265,8 +266,8 @@ __global__ void __launch_bounds__(NT)
                         s_J[0][2 * NT + k] = r.rqt;
                         s_J[0][3 * NT + k] = r.rqv;
                         const int ls = (PAR ? g.slot[e] : e) - c.s0;
-                        s_irow[k] = ls;
-                        if (j == i) s_dslot[0] = ls;
+                        s_ls[k] = ls;
+                        if (je == i) s_dslot[0] = ls;
                     }
                 }
                 __syncthreads();
@@ -276,7 +277,7 @@ __global__ void __launch_bounds__(NT)
                         as += s_ab[0][0][q];
                         bs += s_ab[0][1][q];
                         if constexpr (WITH_J) {
-                            const int ls = s_irow[q];
+                            const int ls = s_ls[q];
                             if (ls != cur) {
                                 // a finished slot; the diagonal slot's zeros are overwritten below
                                 if (cur >= 0) {
@@ -322,46 +323,25 @@ __global__ void __launch_bounds__(NT)
         return;
     }
 
-    // ---- packed tile: whole rows, at most NT records
-    stage_rows<NT>(g, c, s_irow, s_yrow);
-    const bool live = k < c.n;
-    int j = 0, ls = 0;
-    double G = 0.0, B = 0.0;
-    if (live) {
-        const int e = c.i0 + k;
-        j = g.nbr[e];
-        G = g.G[e];
-        B = g.B[e];
-        ls = (PAR ? g.slot[e] : e) - c.s0;  // without parallel branches, slot == record
-    }
-    const bool rowt = k < c.nrows;  // thread k also owns row k of the tile
-    const int ir = c.r0 + k;
+    // ---- packed tile: whole rows, at most NT records.  Lane k holds
+    // record c.i0 + k (inert past c.n); its table entry gives the remote bus,
+    // the tile row, the LDS targets (o11, o12) of its remote partials (the
+    // pad for the shunt record, idle lanes and, with parallel branches,
+    // every record but the first of its slot) and, for the first record of
+    // a slot, the slot's record count.  Thread k < rows also owns row k.
+    const int rowl = lo16(pk.y), run = hi16(pk.y);
+    const int o11 = lo16(pk.x), o12 = hi16(pk.x);
+    const bool rowt = k < c.nrows;
+    const int ir = c.r0 + (rowt ? k : 0);
+    int2 rw = make_int2(0, kPad<NT> | (kPad<NT> << 16));
     double dA = 0.0, dC = 0.0;
     if (rowt) {
+        rw = g.row_ew[ir];
         dA = g.dA[ir];
         dC = g.dC[ir];
     }
-    __syncthreads();
-    const int row = live ? row_of(k, s_irow, c.nrows) : 0;
-    const int i = c.r0 + row;
-    const bool diag = live && j == i;
-    if (diag) s_dslot[row] = ls;
-    if constexpr (WITH_J && PAR)
-        if (live) s_slot[k] = ls;
-    const int o11 = s_yrow[row] + ls;      // J11 / J21 position inside the staged P / Q rows
-    const int o12 = s_yrow[row + 1] + ls;  // J12 / J22
-    __syncthreads();
-    int ra = 0, rz = 0, d11 = 0, d12 = 0;
-    if (rowt) {
-        ra = s_irow[k];
-        rz = s_irow[k + 1];
-        d11 = s_yrow[k] + s_dslot[k];
-        d12 = s_yrow[k + 1] + s_dslot[k];
-    }
-
-    // State loads are unconditional (idle lanes read a valid bus of the
-    // tile), which keeps the memory-counter waits exact.
-    const int li = live ? i : c.r0, lj = live ? j : c.r0, lr = rowt ? ir : c.r0;
+    const int ra = lo16(rw.x), rz = hi16(rw.x), d11 = lo16(rw.y), d12 = hi16(rw.y);
+    const int li = c.r0 + rowl;
     struct In {
         double vi, ti, vj, tj, vr;
     };
@@ -370,24 +350,16 @@ __global__ void __launch_bounds__(NT)
         const double *vas = va + (size_t)s * nb;
         x.vi = vms[li];
         x.ti = vas[li];
-        x.vj = vms[lj];
-        x.tj = vas[lj];
-        x.vr = vms[lr];
+        x.vj = vms[j];
+        x.tj = vas[j];
+        x.vr = vms[ir];
     };
-    // LDS targets of the record's remote partials and of the row's diagonal
-    // entries; lanes with nothing to write use the pad slots.
-    const bool wrem = live && !diag && !PAR;
-    const int t11 = wrem ? o11 : 4 * NT, t12 = wrem ? o12 : 4 * NT;
-    const int t21 = wrem ? 2 * NT + o11 : 4 * NT + 1, t22 = wrem ? 2 * NT + o12 : 4 * NT + 1;
-    const int u11 = rowt ? d11 : 4 * NT, u12 = rowt ? d12 : 4 * NT;
-    const int u21 = rowt ? 2 * NT + d11 : 4 * NT + 1, u22 = rowt ? 2 * NT + d12 : 4 * NT + 1;
-    // Every lane evaluates a record and a row (idle lanes with zero
-    // admittances and valid indices), so each loaded value is consumed on the
-    // straight-line path and the loads of the next state stay in flight; only
-    // LDS writes and stores depend on the lane's role.  Record slots k >= n
-    // and row slots k >= rows are never read.
+    // Every lane evaluates a record and a row (inert lanes with zero
+    // admittances, valid buses and empty row ranges), so each loaded value is
+    // consumed on the straight-line path and the loads of the next state stay
+    // in flight; only stores depend on the lane's role.
     auto proc = [&](int s, int p, const In &x) {
-        const EwRec r = ew_record(x.vi, x.ti, x.vj, x.tj, G, B);
+        const EwRec r = ew_record(x.vi, x.ti, x.vj, x.tj, gb.x, gb.y);
         s_ab[p][0][k] = r.a;
         s_ab[p][1][k] = r.b;
         if constexpr (WITH_J) {
@@ -397,10 +369,10 @@ __global__ void __launch_bounds__(NT)
                 s_rem[p][2][k] = r.rqt;
                 s_rem[p][3][k] = r.rqv;
             } else {
-                s_J[p][t11] = r.rpt;
-                s_J[p][t12] = r.rpv;
-                s_J[p][t21] = r.rqt;
-                s_J[p][t22] = r.rqv;
+                s_J[p][o11] = r.rpt;
+                s_J[p][o12] = r.rpv;
+                s_J[p][kQ<NT> + o11] = r.rqt;
+                s_J[p][kQ<NT> + o12] = r.rqv;
             }
         }
         lds_barrier();
@@ -412,15 +384,13 @@ __global__ void __launch_bounds__(NT)
             Q[(size_t)s * nb + ir] = o.q;
         }
         if constexpr (WITH_J) {
-            s_J[p][u11] = o.j11;
-            s_J[p][u12] = o.j12;
-            s_J[p][u21] = o.j21;
-            s_J[p][u22] = o.j22;
-        }
-        if constexpr (WITH_J && PAR) {
-            if (live && !diag && (k == 0 || s_slot[k - 1] != ls)) {  // first record of its slot sums the slot
+            s_J[p][d11] = o.j11;
+            s_J[p][d12] = o.j12;
+            s_J[p][kQ<NT> + d11] = o.j21;
+            s_J[p][kQ<NT> + d12] = o.j22;
+            if constexpr (PAR) {  // the first record of a slot sums the slot, in record order
                 double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-                for (int q = k; q < c.n && s_slot[q] == ls; ++q) {
+                for (int q = k; q < k + run; ++q) {
                     a0 += s_rem[p][0][q];
                     a1 += s_rem[p][1][q];
                     a2 += s_rem[p][2][q];
@@ -428,16 +398,14 @@ __global__ void __launch_bounds__(NT)
                 }
                 s_J[p][o11] = a0;
                 s_J[p][o12] = a1;
-                s_J[p][2 * NT + o11] = a2;
-                s_J[p][2 * NT + o12] = a3;
+                s_J[p][kQ<NT> + o11] = a2;
+                s_J[p][kQ<NT> + o12] = a3;
             }
-        }
-        if constexpr (WITH_J) {
             lds_barrier();
             write_jrows<NT>(c, s_J[p], J + (size_t)s * (size_t)g.nnz_j);
         }
     };
-    pipelined_states<In>(sb, se, load, proc);
+    pipelined_states<In, ONE>(sb, se, load, proc);
 }
 
 // ===================================================================
@@ -449,16 +417,14 @@ __global__ void __launch_bounds__(NT)
 // and writes the four real parts in place into J (Section IV.B.2).
 // U = e^{j theta} and V = v U are formed on the fly from (vm, va); a row's
 // own V_i and U_i reach the other threads of the row through LDS.
-template <int NT, bool WITH_J>
+template <int NT, bool WITH_J, bool ONE>
 __global__ void __launch_bounds__(NT)
     k_ybus(DevGrid g, int nstate, int spb, int nchunk, bool state_major, const double *__restrict__ vm, const double *__restrict__ va,
            double *__restrict__ P, double *__restrict__ Q, double *__restrict__ J) {
-    __shared__ int s_irow[NT + 1];
-    __shared__ int s_yrow[NT + 1];
-    __shared__ int s_dslot[NT];
-    __shared__ double s_yv[2][2][NT];  // Y_ij V_j
-    __shared__ double s_vu[2][4][NT];  // per row: V_i, U_i (re, im)
-    __shared__ __align__(16) double s_J[2][WITH_J ? 4 * NT + 2 : 2];  // + two pad slots (see k_ew)
+    constexpr int NBUF = ONE ? 1 : 2;
+    __shared__ double s_yv[NBUF][2][NT];  // Y_ij V_j
+    __shared__ double s_vu[NBUF][4][NT];  // per row: V_i, U_i (re, im)
+    __shared__ __align__(16) double s_J[NBUF][WITH_J ? kJStage<NT> : 2];
 
     const int W = g.ntiles * nchunk;
     const int w = work_index(gridDim.x);
@@ -466,8 +432,12 @@ __global__ void __launch_bounds__(NT)
     const int t = state_major ? w % g.ntiles : w / nchunk;
     const int sb = (state_major ? w / g.ntiles : w - t * nchunk) * spb;
     const int se = min(nstate, sb + spb);
-    const Tile c = tile_of(g, t);
     const int k = threadIdx.x;
+    const size_t lane = (size_t)t * NT + k;
+    const int j = g.ylane_j[lane];
+    const int2 pk = g.ylane_pk[lane];
+    const double2 yl = g.ylane_y[lane];
+    const Tile c = tile_of(g, t);
     const size_t nb = (size_t)g.nb;
 
     if (c.n > NT) {
@@ -481,10 +451,10 @@ __global__ void __launch_bounds__(NT)
             for (int base = 0; base < d; base += NT) {
                 if (base + k < d) {
                     const int p = c.s0 + base + k;
-                    const int j = g.ycol[p];
+                    const int jc = g.ycol[p];
                     double sn, cs;
-                    sincos_dev(vas[j], &sn, &cs);
-                    const double v = vms[j];
+                    sincos_dev(vas[jc], &sn, &cs);
+                    const double v = vms[jc];
                     const Cx yv = cmul({g.yre[p], g.yim[p]}, {v * cs, v * sn});
                     s_yv[0][0][k] = yv.re;
                     s_yv[0][1][k] = yv.im;
@@ -516,14 +486,14 @@ __global__ void __launch_bounds__(NT)
                 double *Js = J + (size_t)s * (size_t)g.nnz_j;
                 for (int lp = k; lp < d; lp += NT) {
                     const int p = c.s0 + lp;
-                    const int j = g.ycol[p];
+                    const int jc = g.ycol[p];
                     double snj, csj;
-                    sincos_dev(vas[j], &snj, &csj);
-                    const double v = vms[j];
+                    sincos_dev(vas[jc], &snj, &csj);
+                    const double v = vms[jc];
                     const Cx Y = {g.yre[p], g.yim[p]};
                     const Cx Uj = {csj, snj};
                     const Cx yv = cmul(Y, {v * csj, v * snj});
-                    const bool dg = j == i;
+                    const bool dg = jc == i;
                     const Cx x = {(dg ? Ic.re : 0.0) - yv.re, (dg ? Ic.im : 0.0) + yv.im};  // delta conj(I) - conj(YV)
                     const Cx dst = cmul({-Vi.im, Vi.re}, x);                                  // j V_i x
                     Cx dsv = cmul(Vi, cconj(cmul(Y, Uj)));
@@ -539,49 +509,34 @@ __global__ void __launch_bounds__(NT)
         return;
     }
 
-    stage_rows<NT>(g, c, s_irow, s_yrow);
-    const bool live = k < c.ns;
-    int j = 0;
-    Cx Y = {0.0, 0.0};
-    if (live) {
-        const int p = c.s0 + k;
-        j = g.ycol[p];
-        Y = {g.yre[p], g.yim[p]};
-    }
+    // ---- packed tile: lane k holds nonzero c.s0 + k (inert past c.ns) with
+    // its column bus, tile row, diagonal flag and LDS targets (the pad for
+    // the diagonal nonzero, whose entries the row thread writes).
+    const int row = lo16(pk.y);
+    const bool diag = hi16(pk.y) != 0;
+    const int o11 = lo16(pk.x), o12 = hi16(pk.x);
+    const Cx Y = {yl.x, yl.y};
     const bool rowt = k < c.nrows;
-    const int ir = c.r0 + k;
-    __syncthreads();
-    const int row = live ? row_of(k, s_yrow, c.nrows) : 0;
-    const bool diag = live && j == c.r0 + row;
-    if (diag) s_dslot[row] = k;
-    const int o11 = s_yrow[row] + k;
-    const int o12 = s_yrow[row + 1] + k;
-    __syncthreads();
-    int ra = 0, rz = 0, dl = 0;
+    const int ir = c.r0 + (rowt ? k : 0);
+    int ra = 0, rz = 0, dd11 = kPad<NT>, dd12 = kPad<NT>;
     Cx Yd = {0.0, 0.0};
     if (rowt) {
-        ra = s_yrow[k];
-        rz = s_yrow[k + 1];
-        dl = s_dslot[k];
-        Yd = {g.yre[c.s0 + dl], g.yim[c.s0 + dl]};
+        const int2 rw = g.row_yb[ir];
+        ra = lo16(rw.x);
+        rz = hi16(rw.x);
+        dd11 = ra + rw.y;
+        dd12 = rz + rw.y;
+        Yd = {g.yre[c.s0 + rw.y], g.yim[c.s0 + rw.y]};
     }
-
-    const int lj = live ? j : c.r0;  // idle lanes load a valid bus (unconditional loads)
     struct In {
         double v, th;
     };
     auto load = [&](int s, In &x) {
-        x.v = vm[(size_t)s * nb + lj];
-        x.th = va[(size_t)s * nb + lj];
+        x.v = vm[(size_t)s * nb + j];
+        x.th = va[(size_t)s * nb + j];
     };
-    const bool woff = live && !diag;
-    const int t11 = woff ? o11 : 4 * NT, t12 = woff ? o12 : 4 * NT;
-    const int t21 = woff ? 2 * NT + o11 : 4 * NT + 1, t22 = woff ? 2 * NT + o12 : 4 * NT + 1;
-    const int dd11 = s_yrow[rowt ? k : 0] + dl, dd12 = s_yrow[rowt ? k + 1 : 1] + dl;
-    const int u11 = rowt ? dd11 : 4 * NT, u12 = rowt ? dd12 : 4 * NT;
-    const int u21 = rowt ? 2 * NT + dd11 : 4 * NT + 1, u22 = rowt ? 2 * NT + dd12 : 4 * NT + 1;
-    // As in k_ew: every lane computes, only LDS writes and stores depend on
-    // the lane's role (idle lanes have Y = 0 and a valid bus).
+    // As in k_ew: every lane computes, only stores depend on the lane's role
+    // (inert lanes have Y = 0 and a valid bus).
     auto proc = [&](int s, int p, const In &x) {
         double sn, cs;
         sincos_dev(x.th, &sn, &cs);
@@ -614,23 +569,23 @@ __global__ void __launch_bounds__(NT)
             const Cx x2 = {Ic.re - yvi.re, Ic.im + yvi.im};
             const Cx dst = cmul({-Vk.im, Vk.re}, x2);
             const Cx dsv = cadd(cmul(Vk, cconj(yu)), cmul(Ic, Ui));
-            s_J[p][u11] = dst.re;
-            s_J[p][u12] = dsv.re;
-            s_J[p][u21] = dst.im;
-            s_J[p][u22] = dsv.im;
+            s_J[p][dd11] = dst.re;
+            s_J[p][dd12] = dsv.re;
+            s_J[p][kQ<NT> + dd11] = dst.im;
+            s_J[p][kQ<NT> + dd12] = dsv.im;
             // off-diagonal entry of this nonzero
             const Cx Vi = {s_vu[p][0][row], s_vu[p][1][row]};
             const Cx dso = cmul({-Vi.im, Vi.re}, {-yv.re, yv.im});  // j V_i (-conj(Y_ij V_j))
             const Cx dvo = cmul(Vi, cconj(cmul(Y, Uj)));
-            s_J[p][t11] = dso.re;
-            s_J[p][t12] = dvo.re;
-            s_J[p][t21] = dso.im;
-            s_J[p][t22] = dvo.im;
+            s_J[p][o11] = dso.re;
+            s_J[p][o12] = dvo.re;
+            s_J[p][kQ<NT> + o11] = dso.im;
+            s_J[p][kQ<NT> + o12] = dvo.im;
             lds_barrier();
             write_jrows<NT>(c, s_J[p], J + (size_t)s * (size_t)g.nnz_j);
         }
     };
-    pipelined_states<In>(sb, se, load, proc);
+    pipelined_states<In, ONE>(sb, se, load, proc);
 }
 
 // ===================================================================
@@ -665,14 +620,12 @@ __device__ __forceinline__ double vjp_own(double sum, double vi, double lpi, dou
     return fma(2.0 * vi, fma(lpi, dA, -(lqi * dC)), sum);
 }
 
-template <int NT>
+template <int NT, bool ONE>
 __global__ void __launch_bounds__(NT)
     k_ew_vjp(DevGrid g, int nstate, int spb, int nchunk, bool state_major, const double *__restrict__ vm,
              const double *__restrict__ va, const double *__restrict__ lp, const double *__restrict__ lq,
              double *__restrict__ gvm, double *__restrict__ gva) {
-    __shared__ int s_irow[NT + 1];
-    __shared__ int s_yrow[NT + 1];
-    __shared__ double s_val[2][2][NT];
+    __shared__ double s_val[ONE ? 1 : 2][2][NT];
 
     const int W = g.ntiles * nchunk;
     const int w = work_index(gridDim.x);
@@ -680,20 +633,24 @@ __global__ void __launch_bounds__(NT)
     const int t = state_major ? w % g.ntiles : w / nchunk;
     const int sb = (state_major ? w / g.ntiles : w - t * nchunk) * spb;
     const int se = min(nstate, sb + spb);
-    const Tile c = tile_of(g, t);
     const int k = threadIdx.x;
+    const size_t lane = (size_t)t * NT + k;
+    const int j = g.lane_j[lane];
+    const int rowl = lo16(g.lane_pk[lane].y);
+    const double2 gb = g.lane_gb[lane], grb = g.lane_grbr[lane];
+    const Tile c = tile_of(g, t);
     const size_t nb = (size_t)g.nb;
 
-    auto fetch = [&](size_t so, int i, int j) {
+    auto fetch = [&](size_t so, int i, int jj) {
         VjpIn x;
         x.vi = vm[so + i];
         x.ti = va[so + i];
-        x.vj = vm[so + j];
-        x.tj = va[so + j];
+        x.vj = vm[so + jj];
+        x.tj = va[so + jj];
         x.lpi = lp[so + i];
         x.lqi = lq[so + i];
-        x.lpj = lp[so + j];
-        x.lqj = lq[so + j];
+        x.lpj = lp[so + jj];
+        x.lqj = lq[so + jj];
         return x;
     };
 
@@ -730,49 +687,34 @@ __global__ void __launch_bounds__(NT)
         return;
     }
 
-    stage_rows<NT>(g, c, s_irow, s_yrow);
-    const bool live = k < c.n;
-    int j = 0;
-    double G = 0.0, B = 0.0, Gr = 0.0, Br = 0.0;
-    if (live) {
-        const int e = c.i0 + k;
-        j = g.nbr[e];
-        G = g.G[e];
-        B = g.B[e];
-        Gr = g.Gr[e];
-        Br = g.Br[e];
-    }
+    // ---- packed tile (lane tables as in k_ew)
     const bool rowt = k < c.nrows;
-    const int ir = c.r0 + k;
+    const int ir = c.r0 + (rowt ? k : 0);
+    int ra = 0, rz = 0;
     double dA = 0.0, dC = 0.0;
     if (rowt) {
+        const int2 rw = g.row_ew[ir];
+        ra = lo16(rw.x);
+        rz = hi16(rw.x);
         dA = g.dA[ir];
         dC = g.dC[ir];
     }
-    __syncthreads();
-    const int row = live ? row_of(k, s_irow, c.nrows) : 0;
-    const int i = c.r0 + row;
-    int ra = 0, rz = 0;
-    if (rowt) {
-        ra = s_irow[k];
-        rz = s_irow[k + 1];
-    }
-    const int li = live ? i : c.r0, lj = live ? j : c.r0, lr = rowt ? ir : c.r0;  // unconditional loads
+    const int li = c.r0 + rowl;
     struct In {
         VjpIn x;
         double vr, lpr, lqr;
     };
     auto load = [&](int s, In &in) {
         const size_t so = (size_t)s * nb;
-        in.x = fetch(so, li, lj);
-        in.vr = vm[so + lr];
-        in.lpr = lp[so + lr];
-        in.lqr = lq[so + lr];
+        in.x = fetch(so, li, j);
+        in.vr = vm[so + ir];
+        in.lpr = lp[so + ir];
+        in.lqr = lq[so + ir];
     };
     // As in k_ew: every lane computes; stores depend on the lane's role.
     auto proc = [&](int s, int p, const In &in) {
         double ga, gv;
-        vjp_record(in.x, G, B, Gr, Br, ga, gv);
+        vjp_record(in.x, gb.x, gb.y, grb.x, grb.y, ga, gv);
         s_val[p][0][k] = ga;
         s_val[p][1][k] = gv;
         lds_barrier();
@@ -785,7 +727,7 @@ __global__ void __launch_bounds__(NT)
             gvm[so + ir] = gm;
         }
     };
-    pipelined_states<In>(sb, se, load, proc);
+    pipelined_states<In, ONE>(sb, se, load, proc);
 }
 
 // ===================================================================
@@ -868,7 +810,22 @@ __global__ void k_ybus_assemble(DevSetup s) {
     s.yim[p] = im;
 }
 
-template <int NT>
+// Lane values: copies of the record constants (element-wise) or Ybus values
+// in lane order; inert lanes get zeros.
+__global__ void k_lane_fill(DevLaneFill f, bool ew) {
+    const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= f.nlanes) return;
+    if (ew) {
+        const int e = f.lane_rec[l];
+        f.lane_gb[l] = e >= 0 ? make_double2(f.G[e], f.B[e]) : make_double2(0.0, 0.0);
+        f.lane_grbr[l] = e >= 0 ? make_double2(f.Gr[e], f.Br[e]) : make_double2(0.0, 0.0);
+    } else {
+        const int q = f.ylane_slot[l];
+        f.ylane_y[l] = q >= 0 ? make_double2(f.yre[q], f.yim[q]) : make_double2(0.0, 0.0);
+    }
+}
+
+template <int NT, bool ONE>
 hipError_t launch_nt(const DevGrid &g, const Launch &L, hipStream_t st) {
     const int spb = L.states_per_block;
     const int nchunk = (L.nstate + spb - 1) / spb;
@@ -879,30 +836,30 @@ hipError_t launch_nt(const DevGrid &g, const Launch &L, hipStream_t st) {
     switch (L.kind) {
         case K_EW_S:
             if (L.has_parallel)
-                hipLaunchKernelGGL((k_ew<NT, true, false>), grid, block, 0, st, g, L.nstate, spb, nchunk, L.state_major, L.vm, L.va,
+                hipLaunchKernelGGL((k_ew<NT, true, false, ONE>), grid, block, 0, st, g, L.nstate, spb, nchunk, L.state_major, L.vm, L.va,
                                    L.p, L.q, nullptr);
             else
-                hipLaunchKernelGGL((k_ew<NT, false, false>), grid, block, 0, st, g, L.nstate, spb, nchunk, L.state_major, L.vm, L.va,
+                hipLaunchKernelGGL((k_ew<NT, false, false, ONE>), grid, block, 0, st, g, L.nstate, spb, nchunk, L.state_major, L.vm, L.va,
                                    L.p, L.q, nullptr);
             break;
         case K_EW_SJ:
             if (L.has_parallel)
-                hipLaunchKernelGGL((k_ew<NT, true, true>), grid, block, 0, st, g, L.nstate, spb, nchunk, L.state_major, L.vm, L.va,
+                hipLaunchKernelGGL((k_ew<NT, true, true, ONE>), grid, block, 0, st, g, L.nstate, spb, nchunk, L.state_major, L.vm, L.va,
                                    L.p, L.q, L.jval);
             else
-                hipLaunchKernelGGL((k_ew<NT, false, true>), grid, block, 0, st, g, L.nstate, spb, nchunk, L.state_major, L.vm, L.va,
+                hipLaunchKernelGGL((k_ew<NT, false, true, ONE>), grid, block, 0, st, g, L.nstate, spb, nchunk, L.state_major, L.vm, L.va,
                                    L.p, L.q, L.jval);
             break;
         case K_YB_S:
-            hipLaunchKernelGGL((k_ybus<NT, false>), grid, block, 0, st, g, L.nstate, spb, nchunk, L.state_major, L.vm, L.va, L.p, L.q,
+            hipLaunchKernelGGL((k_ybus<NT, false, ONE>), grid, block, 0, st, g, L.nstate, spb, nchunk, L.state_major, L.vm, L.va, L.p, L.q,
                                nullptr);
             break;
         case K_YB_SJ:
-            hipLaunchKernelGGL((k_ybus<NT, true>), grid, block, 0, st, g, L.nstate, spb, nchunk, L.state_major, L.vm, L.va, L.p, L.q,
+            hipLaunchKernelGGL((k_ybus<NT, true, ONE>), grid, block, 0, st, g, L.nstate, spb, nchunk, L.state_major, L.vm, L.va, L.p, L.q,
                                L.jval);
             break;
         case K_EW_VJP:
-            hipLaunchKernelGGL((k_ew_vjp<NT>), grid, block, 0, st, g, L.nstate, spb, nchunk, L.state_major, L.vm, L.va, L.lp, L.lq,
+            hipLaunchKernelGGL((k_ew_vjp<NT, ONE>), grid, block, 0, st, g, L.nstate, spb, nchunk, L.state_major, L.vm, L.va, L.lp, L.lq,
                                L.gvm, L.gva);
             break;
         default:
@@ -911,28 +868,28 @@ hipError_t launch_nt(const DevGrid &g, const Launch &L, hipStream_t st) {
     return hipGetLastError();
 }
 
-template <int NT>
+template <int NT, bool ONE>
 int occupancy_nt(int kind, bool par) {
     int n = 0;
     hipError_t e = hipErrorInvalidValue;
     auto q = [&](const void *f) { e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, NT, 0); };
     switch (kind) {
         case K_EW_S:
-            q(par ? reinterpret_cast<const void *>(&k_ew<NT, true, false>)
-                  : reinterpret_cast<const void *>(&k_ew<NT, false, false>));
+            q(par ? reinterpret_cast<const void *>(&k_ew<NT, true, false, ONE>)
+                  : reinterpret_cast<const void *>(&k_ew<NT, false, false, ONE>));
             break;
         case K_EW_SJ:
-            q(par ? reinterpret_cast<const void *>(&k_ew<NT, true, true>)
-                  : reinterpret_cast<const void *>(&k_ew<NT, false, true>));
+            q(par ? reinterpret_cast<const void *>(&k_ew<NT, true, true, ONE>)
+                  : reinterpret_cast<const void *>(&k_ew<NT, false, true, ONE>));
             break;
         case K_YB_S:
-            q(reinterpret_cast<const void *>(&k_ybus<NT, false>));
+            q(reinterpret_cast<const void *>(&k_ybus<NT, false, ONE>));
             break;
         case K_YB_SJ:
-            q(reinterpret_cast<const void *>(&k_ybus<NT, true>));
+            q(reinterpret_cast<const void *>(&k_ybus<NT, true, ONE>));
             break;
         case K_EW_VJP:
-            q(reinterpret_cast<const void *>(&k_ew_vjp<NT>));
+            q(reinterpret_cast<const void *>(&k_ew_vjp<NT, ONE>));
             break;
         default:
             break;
@@ -940,21 +897,27 @@ int occupancy_nt(int kind, bool par) {
     return e == hipSuccess ? n : 0;
 }
 
-}  // namespace
-
-hipError_t launch_eval(const DevGrid &g, const Launch &L, hipStream_t stream) {
+template <bool ONE>
+hipError_t launch_one(const DevGrid &g, const Launch &L, hipStream_t stream) {
     switch (L.tile_items) {
         case 64:
-            return launch_nt<64>(g, L, stream);
+            return launch_nt<64, ONE>(g, L, stream);
         case 128:
-            return launch_nt<128>(g, L, stream);
+            return launch_nt<128, ONE>(g, L, stream);
         case 256:
-            return launch_nt<256>(g, L, stream);
+            return launch_nt<256, ONE>(g, L, stream);
         case 512:
-            return launch_nt<512>(g, L, stream);
+            return launch_nt<512, ONE>(g, L, stream);
         default:
             return hipErrorInvalidValue;
     }
+}
+
+}  // namespace
+
+// One state per workgroup runs the instantiation without the state loop.
+hipError_t launch_eval(const DevGrid &g, const Launch &L, hipStream_t stream) {
+    return L.states_per_block == 1 ? launch_one<true>(g, L, stream) : launch_one<false>(g, L, stream);
 }
 
 int resident_blocks_per_cu(int kind, int tile_items, bool has_parallel) {
@@ -969,16 +932,16 @@ int resident_blocks_per_cu(int kind, int tile_items, bool has_parallel) {
     if (v > 0) return v;
     switch (tile_items) {
         case 64:
-            v = occupancy_nt<64>(kind, has_parallel);
+            v = occupancy_nt<64, false>(kind, has_parallel);
             break;
         case 128:
-            v = occupancy_nt<128>(kind, has_parallel);
+            v = occupancy_nt<128, false>(kind, has_parallel);
             break;
         case 256:
-            v = occupancy_nt<256>(kind, has_parallel);
+            v = occupancy_nt<256, false>(kind, has_parallel);
             break;
         default:
-            v = occupancy_nt<512>(kind, has_parallel);
+            v = occupancy_nt<512, false>(kind, has_parallel);
             break;
     }
     slot.store(v);
@@ -996,6 +959,13 @@ hipError_t launch_setup_items(const DevSetup &s, hipStream_t stream) {
         const int64_t blocks = (s.nb + 255) / 256;
         hipLaunchKernelGGL(k_bus_diag, dim3((unsigned)blocks), dim3(256), 0, stream, s);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_lane_fill(const DevLaneFill &f, bool ew, hipStream_t stream) {
+    if (f.nlanes == 0) return hipSuccess;
+    const int64_t blocks = (f.nlanes + 255) / 256;
+    hipLaunchKernelGGL(k_lane_fill, dim3((unsigned)blocks), dim3(256), 0, stream, f, ew);
     return hipGetLastError();
 }
 
