@@ -9,9 +9,17 @@ problem (grid data, state and outputs), R x 23 MB >= 512 MB.
 Printed (one JSON line): evals/s, the roofline of the dominant kernel
 (algorithmic bytes per launch / average launch time, HIP events on the
 launch stream), the CPU oracle's rate on the host, and side measurements:
-the Ybus method under the same protocol, warm-cache rates, 512 batched
-states on a 20k-bus grid, 64 uneven grids x 4 states, and the adjoint
-(32 states at 100k buses) against its forward pass.
+the Ybus method under the same protocol, warm-cache rates, a plain copy of
+the same byte count (the practical bandwidth ceiling at this size), 512
+batched states on a 20k-bus grid, 64 uneven grids x 4 states, and the
+adjoint (32 states at 100k buses) against its forward pass.
+
+Counter runs (HBM traffic of the dominant kernel):
+    rocprofv3 --pmc FETCH_SIZE --output-format csv -d D1 -o f -- python3 bench.py --probe
+    rocprofv3 --pmc WRITE_SIZE --output-format csv -d D2 -o w -- python3 bench.py --probe
+    python3 bench.py --traffic D1/.../f_counter_collection.csv D2/.../w_counter_collection.csv
+The probe runs the headline launches and one plain copy of a known byte
+count; each counter is scaled by known bytes / counted bytes of that copy.
 """
 from __future__ import annotations
 
@@ -29,6 +37,65 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+# sources that decide the headline kernel's memory traffic (kernels and lane-table layout)
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2302_10736_amd", "csrc", f) for f in ("pf_kernels.hip", "pf_api.cpp")]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_ew_cfg1_100k_traffic.json")
+HEADLINE_KERNEL = "k_ew<256, false, true, true>"  # element-wise S+J, one state per workgroup
+COPY_PROBE_DOUBLES = 4 * 1024 * 1024  # 32 MiB read + 32 MiB written by the calibration copy
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SRCS:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_csv(fetch_csv, write_csv):
+    """Per-launch HBM bytes of the headline kernel from two rocprofv3 counter
+    CSVs (FETCH_SIZE, WRITE_SIZE in KiB per dispatch), each scaled by the
+    known bytes of the probe's copy kernel over what the counter read for it."""
+    import csv
+
+    def per_kernel(path, counter):
+        acc = {}
+        with open(path) as f:
+            for row in csv.DictReader(f):
+                if row.get("Counter_Name") != counter:
+                    continue
+                name = row["Kernel_Name"]
+                key = (name, row.get("Dispatch_Id", row.get("Correlation_Id")))
+                acc[key] = acc.get(key, 0.0) + float(row["Counter_Value"])
+        out = {}
+        for (name, _), v in acc.items():
+            out.setdefault(name, []).append(v)
+        return out
+
+    def pick(d, pred, what):
+        names = [n for n in d if pred(n)]
+        if len(names) != 1:
+            raise SystemExit(f"expected one {what} kernel in the counter file, found {names}")
+        vals = d[names[0]]
+        return names[0], sum(vals) / len(vals), len(vals)
+
+    head = lambda n: "k_ew<256, false, true, true>" in n
+    copy = lambda n: "copy" in n.lower() and "k_ew" not in n
+    res = {"kernel": HEADLINE_KERNEL, "kernel_sha256_16": kernel_hash(), "copy_bytes_each_way": 8 * COPY_PROBE_DOUBLES}
+    total = 0.0
+    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        d = per_kernel(path, counter)
+        hn, hv, hc = pick(d, head, "headline")
+        # the calibration copy is by far the largest copy dispatch (state clones are 0.8 MB)
+        cn = [n for n in d if copy(n)]
+        if not cn:
+            raise SystemExit("no copy kernel in the counter file")
+        cn, cv = max(((n, max(d[n])) for n in cn), key=lambda t: t[1])
+        factor = 8 * COPY_PROBE_DOUBLES / (cv * 1024.0)
+        res[counter] = {"headline_kib_per_dispatch": hv, "dispatches": hc, "copy_kernel": cn,
+                        "copy_kib": cv, "scale": factor, "bytes_per_launch": hv * 1024.0 * factor}
+        total += hv * 1024.0 * factor
+    res["bytes_per_launch"] = total
+    return res
 
 
 def algorithmic_bytes(nb, nl, nnz_y, nstate, with_j=True, method="ew", vjp=False):
@@ -59,7 +126,17 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--only", default="", help="comma list of side measurements to run")
+    ap.add_argument("--probe", action="store_true",
+                    help="counter-run workload: headline launches, then one copy of known size; no timing")
+    ap.add_argument("--traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the headline kernel's HBM traffic from two counter CSVs and exit")
     args = ap.parse_args()
+    if args.traffic:
+        res = traffic_from_csv(*args.traffic)
+        with open(TRAFFIC_FILE, "w") as f:
+            json.dump(res, f, indent=1)
+        print(json.dumps(res))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the library runs on a single "
               "MI355X and has no multi-GPU path", file=sys.stderr)
@@ -113,6 +190,17 @@ def main():
         d = reps[k % R]
         pf.pf_jacobian_values(d["G"], pf.PF_METHOD_ELEMENTWISE, d["vm"], d["va"], d["p"], d["q"], d["j"])
 
+    if args.probe:
+        for k in range(2 * R):
+            ew_sj(k)
+        a = torch.ones(COPY_PROBE_DOUBLES, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"probe done: {2 * R} headline launches, one copy of {8 * COPY_PROBE_DOUBLES} bytes")
+        return
+
     K, W = args.steps, args.warmup
     ev_s, wall_s = timed(ew_sj, K, W)
     value = K / wall_s
@@ -123,12 +211,9 @@ def main():
 
     # traffic measured by rocprofv3 counters for this exact kernel source, if recorded
     traffic = None
-    ksrc = os.path.join(ROOT, "paper_2302_10736_amd", "csrc", "pf_kernels.hip")
-    khash = hashlib.sha256(open(ksrc, "rb").read()).hexdigest()[:16]
-    tfile = os.path.join(ROOT, "profiles", "k_ew_cfg1_100k_traffic.json")
-    if os.path.exists(tfile):
-        t = json.load(open(tfile))
-        if t.get("kernel_sha256_16") == khash:
+    if os.path.exists(TRAFFIC_FILE):
+        t = json.load(open(TRAFFIC_FILE))
+        if t.get("kernel_sha256_16") == kernel_hash():
             traffic = t.get("bytes_per_launch")
 
     out = {
@@ -150,7 +235,7 @@ def main():
                    "replicas_rotated": R, "tile_items": tile},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_ew<256,false,true>", "algorithmic_bytes_per_launch": abytes,
+                     "kernel": HEADLINE_KERNEL, "algorithmic_bytes_per_launch": abytes,
                      "avg_launch_us": avg_launch * 1e6},
     }
 
@@ -172,6 +257,18 @@ def main():
                             "achieved_GBs": yb_bytes / (ev / K) / 1e9, "algorithmic_bytes": yb_bytes,
                             "ew_speedup_vs_ybus": (ev / K) / avg_launch}
         log(f"Ybus S+J: {ev / K * 1e6:.2f} us/launch")
+
+    if want("copy"):
+        # a plain device copy moving the same number of bytes (half read, half written)
+        n = abytes // 16
+        ca = [torch.ones(n, dtype=torch.float64, device=dev) for _ in range(R)]
+        cb = [torch.empty(n, dtype=torch.float64, device=dev) for _ in range(R)]
+        ev, wall = timed(lambda k: cb[k % R].copy_(ca[k % R]), K, W)
+        extra["copy_same_bytes"] = {"bytes": 16 * n, "avg_launch_us": ev / K * 1e6,
+                                    "GBs": 16 * n / (ev / K) / 1e9,
+                                    "headline_over_copy_time": avg_launch / (ev / K)}
+        del ca, cb
+        log(f"copy of the same bytes: {ev / K * 1e6:.2f} us")
 
     if want("warm"):
         def ew_warm(k):
