@@ -131,7 +131,8 @@ void build_tiles(pf_grid *g, int cap) {
 struct HostLanes {
     std::vector<int32_t> lane_j, lane_rec, ylane_j, ylane_slot;
     std::vector<int32_t> lane_pk, ylane_pk;  // pairs
-    std::vector<int32_t> row_ew, row_yb;     // pairs per bus
+    std::vector<int32_t> row_ew, row_yb;     // pairs per bus, + one inert entry at nb
+    std::vector<int32_t> ydslot;             // [nb] global Ybus slot of each diagonal
 };
 
 HostLanes build_lanes(const pf_grid *g) {
@@ -145,9 +146,16 @@ HostLanes build_lanes(const pf_grid *g) {
     h.ylane_slot.assign(nl, -1);
     h.lane_pk.assign(2 * nl, 0);
     h.ylane_pk.assign(2 * nl, 0);
-    h.row_ew.assign(2 * (size_t)g->nb, 0);
-    h.row_yb.assign(2 * (size_t)g->nb, 0);
     const int32_t padpair = pad | (pad << 16);
+    // Entry nb is what lanes without a row read: empty ranges, pad targets.
+    h.row_ew.assign(2 * ((size_t)g->nb + 1), 0);
+    h.row_yb.assign(2 * ((size_t)g->nb + 1), 0);
+    h.row_ew[2 * (size_t)g->nb + 1] = padpair;
+    h.row_yb[2 * (size_t)g->nb + 1] = pad;
+    h.ydslot.assign(g->nb, 0);
+    for (int32_t i = 0; i < g->nb; ++i)
+        for (int32_t q = g->yrow[i]; q < g->yrow[i + 1]; ++q)
+            if (g->ycol[q] == i) h.ydslot[i] = q;
     for (size_t t = 0; t < g->tiles.size(); ++t) {
         const pf::TileDesc &c = g->tiles[t];
         const size_t base = t * NT;
@@ -209,9 +217,10 @@ int upload_tiles(pf_grid *g) {
     Arena ar;
     const size_t o_t = ar.take<pf::TileDesc>(nt);
     const size_t o_lj = ar.take<int32_t>(nl), o_lrec = ar.take<int32_t>(nl), o_lpk = ar.take<int2>(nl);
-    const size_t o_lgb = ar.take<double2>(nl), o_lgr = ar.take<double2>(nl), o_rew = ar.take<int2>(g->nb);
+    const size_t o_lgb = ar.take<double2>(nl), o_lgr = ar.take<double2>(nl), o_rew = ar.take<int2>(g->nb + 1);
     const size_t o_yj = ar.take<int32_t>(nl), o_yslot = ar.take<int32_t>(nl), o_ypk = ar.take<int2>(nl);
-    const size_t o_yy = ar.take<double2>(nl), o_ryb = ar.take<int2>(g->nb);
+    const size_t o_yy = ar.take<double2>(nl), o_ryb = ar.take<int2>(g->nb + 1);
+    const size_t o_yds = ar.take<int32_t>(g->nb), o_ydg = ar.take<double2>(g->nb + 1);
     e = hipMalloc(&g->dtile, ar.off);
     if (e != hipSuccess) {
         g->dtile = nullptr;
@@ -227,11 +236,12 @@ int upload_tiles(pf_grid *g) {
     up(o_lj, h.lane_j.data(), nl * 4);
     up(o_lrec, h.lane_rec.data(), nl * 4);
     up(o_lpk, h.lane_pk.data(), nl * 8);
-    up(o_rew, h.row_ew.data(), (size_t)g->nb * 8);
+    up(o_rew, h.row_ew.data(), ((size_t)g->nb + 1) * 8);
     up(o_yj, h.ylane_j.data(), nl * 4);
     up(o_yslot, h.ylane_slot.data(), nl * 4);
     up(o_ypk, h.ylane_pk.data(), nl * 8);
-    up(o_ryb, h.row_yb.data(), (size_t)g->nb * 8);
+    up(o_ryb, h.row_yb.data(), ((size_t)g->nb + 1) * 8);
+    up(o_yds, h.ydslot.data(), (size_t)g->nb * 4);
     if (ee != hipSuccess) return hip_fail(ee, "hipMemcpy(schedule)");
     pf::DevGrid &d = g->dev;
     d.tiles = reinterpret_cast<const pf::TileDesc *>(base + o_t);
@@ -245,6 +255,7 @@ int upload_tiles(pf_grid *g) {
     d.ylane_pk = reinterpret_cast<const int2 *>(base + o_ypk);
     d.ylane_y = reinterpret_cast<const double2 *>(base + o_yy);
     d.row_yb = reinterpret_cast<const int2 *>(base + o_ryb);
+    d.ydiag = reinterpret_cast<const double2 *>(base + o_ydg);
     pf::DevLaneFill &f = g->lanes;
     f.nlanes = (int64_t)nl;
     f.lane_rec = reinterpret_cast<const int32_t *>(base + o_lrec);
@@ -258,6 +269,9 @@ int upload_tiles(pf_grid *g) {
     f.lane_gb = reinterpret_cast<double2 *>(base + o_lgb);
     f.lane_grbr = reinterpret_cast<double2 *>(base + o_lgr);
     f.ylane_y = reinterpret_cast<double2 *>(base + o_yy);
+    f.nb = g->nb;
+    f.ydslot = reinterpret_cast<const int32_t *>(base + o_yds);
+    f.ydiag = reinterpret_cast<double2 *>(base + o_ydg);
     // Record constants exist once the setup kernels ran; Ybus values once
     // pf_ybus ran.  Until then the Ybus lanes stay unfilled and the Ybus
     // evaluation calls refuse to run.
@@ -441,7 +455,8 @@ int pf_build_pattern(int32_t nb, int32_t nl, const int32_t *fbus, const int32_t 
         size_t o_yrow = ar.take<int32_t>(nb + 1), o_irow = ar.take<int32_t>(nb + 1);
         size_t o_ycol = ar.take<int32_t>(g->nnz_y), o_nbr = ar.take<int32_t>(ni), o_slot = ar.take<int32_t>(ni);
         size_t o_G = ar.take<double>(ni), o_B = ar.take<double>(ni), o_Gr = ar.take<double>(ni),
-               o_Br = ar.take<double>(ni), o_dA = ar.take<double>(nb), o_dC = ar.take<double>(nb);
+               o_Br = ar.take<double>(ni), o_dA = ar.take<double>(nb + 1),
+               o_dC = ar.take<double>(nb + 1);
         size_t o_yre = ar.take<double>(g->nnz_y), o_yim = ar.take<double>(g->nnz_y);
         // setup-only arrays
         size_t o_ibr = ar.take<int32_t>(ni), o_srow = ar.take<int32_t>(g->nnz_y),

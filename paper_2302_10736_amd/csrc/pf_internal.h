@@ -40,7 +40,7 @@ struct DevGrid {
     const int32_t *slot;  // [nitems] global slot of the item
     const double *G, *B;  // [nitems] coupling admittance Re / Im of this end (0 for the shunt record)
     const double *Gr, *Br;  // [nitems] coupling admittance of the other end (adjoint)
-    const double *dA, *dC;    // [nb] sum of own-end admittances + shunt (Re / Im)
+    const double *dA, *dC;    // [nb+1] sum of own-end admittances + shunt (Re / Im); [nb] = 0
     const double *yre, *yim;  // [nnz_y] Ybus values
     const TileDesc *tiles;    // [ntiles]
 
@@ -51,20 +51,24 @@ struct DevGrid {
     const int2 *lane_pk;        // {o11 | o12 << 16, row | run << 16}
     const double2 *lane_gb;     // {G, B}
     const double2 *lane_grbr;   // {Gr, Br}
-    const int2 *row_ew;         // [nb] {ra | rz << 16, d11 | d12 << 16}
+    const int2 *row_ew;         // [nb+1] {ra | rz << 16, d11 | d12 << 16}; [nb] inert
     const int32_t *ylane_j;     // Ybus nonzero: column bus
     const int2 *ylane_pk;       // {o11 | o12 << 16, row | diag << 16}
     const double2 *ylane_y;     // {Re Y, Im Y}
-    const int2 *row_yb;         // [nb] {ya | yz << 16, dls}
+    const int2 *row_yb;         // [nb+1] {ya | yz << 16, dls}; [nb] inert
+    const double2 *ydiag;       // [nb+1] Ybus diagonal of each bus; [nb] = 0
 };
 
 // Gather sources of the lane tables: record (element-wise) and slot (Ybus)
 // of every lane, -1 for inert lanes.
 struct DevLaneFill {
     int64_t nlanes;
+    int32_t nb;
     const int32_t *lane_rec, *ylane_slot;
+    const int32_t *ydslot;  // [nb] global slot of each bus's diagonal
     const double *G, *B, *Gr, *Br, *yre, *yim;
     double2 *lane_gb, *lane_grbr, *ylane_y;
+    double2 *ydiag;  // [nb+1]
 };
 
 // Setup data, only read by the setup kernels.

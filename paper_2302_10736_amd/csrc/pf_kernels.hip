@@ -51,6 +51,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 
 #include "pf_internal.h"
@@ -127,22 +128,19 @@ __device__ __forceinline__ void write_jrows(const Tile &c, const double *s_J, do
     }
 }
 
-// Walk states [sb, se) with the per-state inputs of each state loaded one
-// state ahead.  Two register sets alternate (states are taken in pairs), so
+// Walk states [sb, se) (never empty) with the per-state inputs of each state
+// loaded one state ahead; `ra` holds state sb's inputs on entry.  Two register sets alternate (states are taken in pairs), so
 // the loop never copies registers that are still being loaded: a copy would
 // make the wave wait for every outstanding memory operation, including the
 // previous state's stores.  `proc(s, parity, in)` gets parity = (s - sb) & 1
 // for the double-buffered LDS.
 template <class In, bool ONE, class Load, class Proc>
-__device__ __forceinline__ void pipelined_states(int sb, int se, Load &&load, Proc &&proc) {
+__device__ __forceinline__ void pipelined_states(int sb, int se, In &ra, Load &&load, Proc &&proc) {
     if constexpr (ONE) {  // one state per workgroup: nothing to overlap, half the registers
-        In x{};
-        load(sb, x);
-        proc(sb, 0, x);
+        proc(sb, 0, ra);
         return;
     }
-    In ra{}, rb{};
-    if (sb < se) load(sb, ra);
+    In rb{};
     for (int s = sb; s < se; s += 2) {
         if (s + 1 < se) load(s + 1, rb);
         proc(s, 0, ra);
@@ -333,14 +331,6 @@ __global__ void __launch_bounds__(NT)
     const int o11 = lo16(pk.x), o12 = hi16(pk.x);
     const bool rowt = k < c.nrows;
     const int ir = c.r0 + (rowt ? k : 0);
-    int2 rw = make_int2(0, kPad<NT> | (kPad<NT> << 16));
-    double dA = 0.0, dC = 0.0;
-    if (rowt) {
-        rw = g.row_ew[ir];
-        dA = g.dA[ir];
-        dC = g.dC[ir];
-    }
-    const int ra = lo16(rw.x), rz = hi16(rw.x), d11 = lo16(rw.y), d12 = hi16(rw.y);
     const int li = c.r0 + rowl;
     struct In {
         double vi, ti, vj, tj, vr;
@@ -354,10 +344,19 @@ __global__ void __launch_bounds__(NT)
         x.tj = vas[j];
         x.vr = vms[ir];
     };
+    // The first state's gathers go out before the row loads, and every load
+    // is unconditional (each lane's indices are valid), so the waits before
+    // the record phase cover the gathers only.
+    In first;
+    load(sb, first);
+    const int irr = rowt ? ir : g.nb;  // lanes without a row read the inert entry
+    const int2 rw = g.row_ew[irr];
+    const double dA = g.dA[irr], dC = g.dC[irr];
+    const int ra = lo16(rw.x), rz = hi16(rw.x), d11 = lo16(rw.y), d12 = hi16(rw.y);
     // Every lane evaluates a record and a row (inert lanes with zero
     // admittances, valid buses and empty row ranges), so each loaded value is
     // consumed on the straight-line path and the loads of the next state stay
-    // in flight; only stores depend on the lane's role.
+    // in flight.  Stores come last: no load is waited for after a store.
     auto proc = [&](int s, int p, const In &x) {
         const EwRec r = ew_record(x.vi, x.ti, x.vj, x.tj, gb.x, gb.y);
         s_ab[p][0][k] = r.a;
@@ -379,10 +378,6 @@ __global__ void __launch_bounds__(NT)
         double as, bs;
         row_sum2(s_ab[p][0], s_ab[p][1], ra, rz, as, bs);
         const EwRow o = ew_row(x.vr, dA, dC, as, bs);
-        if (P && rowt) {
-            P[(size_t)s * nb + ir] = o.p;
-            Q[(size_t)s * nb + ir] = o.q;
-        }
         if constexpr (WITH_J) {
             s_J[p][d11] = o.j11;
             s_J[p][d12] = o.j12;
@@ -401,11 +396,17 @@ __global__ void __launch_bounds__(NT)
                 s_J[p][kQ<NT> + o11] = a2;
                 s_J[p][kQ<NT> + o12] = a3;
             }
+        }
+        if (P && rowt) {
+            P[(size_t)s * nb + ir] = o.p;
+            Q[(size_t)s * nb + ir] = o.q;
+        }
+        if constexpr (WITH_J) {
             lds_barrier();
             write_jrows<NT>(c, s_J[p], J + (size_t)s * (size_t)g.nnz_j);
         }
     };
-    pipelined_states<In, ONE>(sb, se, load, proc);
+    pipelined_states<In, ONE>(sb, se, first, load, proc);
 }
 
 // ===================================================================
@@ -518,16 +519,6 @@ __global__ void __launch_bounds__(NT)
     const Cx Y = {yl.x, yl.y};
     const bool rowt = k < c.nrows;
     const int ir = c.r0 + (rowt ? k : 0);
-    int ra = 0, rz = 0, dd11 = kPad<NT>, dd12 = kPad<NT>;
-    Cx Yd = {0.0, 0.0};
-    if (rowt) {
-        const int2 rw = g.row_yb[ir];
-        ra = lo16(rw.x);
-        rz = hi16(rw.x);
-        dd11 = ra + rw.y;
-        dd12 = rz + rw.y;
-        Yd = {g.yre[c.s0 + rw.y], g.yim[c.s0 + rw.y]};
-    }
     struct In {
         double v, th;
     };
@@ -535,6 +526,13 @@ __global__ void __launch_bounds__(NT)
         x.v = vm[(size_t)s * nb + j];
         x.th = va[(size_t)s * nb + j];
     };
+    In first;  // first state's gathers before the row loads, as in k_ew
+    load(sb, first);
+    const int irr = rowt ? ir : g.nb;
+    const int2 rw = g.row_yb[irr];
+    const double2 ydg = g.ydiag[irr];
+    const Cx Yd = {ydg.x, ydg.y};
+    const int ra = lo16(rw.x), rz = hi16(rw.x), dd11 = ra + rw.y, dd12 = rz + rw.y;
     // As in k_ew: every lane computes, only stores depend on the lane's role
     // (inert lanes have Y = 0 and a valid bus).
     auto proc = [&](int s, int p, const In &x) {
@@ -557,10 +555,6 @@ __global__ void __launch_bounds__(NT)
         const Cx Vk = {s_vu[p][0][kr], s_vu[p][1][kr]};
         const Cx Ic = {I.re, -I.im};
         const Cx S = cmul(Vk, Ic);
-        if (P && rowt) {
-            P[(size_t)s * nb + ir] = S.re;
-            Q[(size_t)s * nb + ir] = S.im;
-        }
         if constexpr (WITH_J) {
             // diagonal entry of row k (Y_ii V_i recomputed from Y_ii and V_i)
             const Cx Ui = {s_vu[p][2][kr], s_vu[p][3][kr]};
@@ -581,11 +575,17 @@ __global__ void __launch_bounds__(NT)
             s_J[p][o12] = dvo.re;
             s_J[p][kQ<NT> + o11] = dso.im;
             s_J[p][kQ<NT> + o12] = dvo.im;
+        }
+        if (P && rowt) {  // stores last (see k_ew)
+            P[(size_t)s * nb + ir] = S.re;
+            Q[(size_t)s * nb + ir] = S.im;
+        }
+        if constexpr (WITH_J) {
             lds_barrier();
             write_jrows<NT>(c, s_J[p], J + (size_t)s * (size_t)g.nnz_j);
         }
     };
-    pipelined_states<In, ONE>(sb, se, load, proc);
+    pipelined_states<In, ONE>(sb, se, first, load, proc);
 }
 
 // ===================================================================
@@ -690,15 +690,6 @@ __global__ void __launch_bounds__(NT)
     // ---- packed tile (lane tables as in k_ew)
     const bool rowt = k < c.nrows;
     const int ir = c.r0 + (rowt ? k : 0);
-    int ra = 0, rz = 0;
-    double dA = 0.0, dC = 0.0;
-    if (rowt) {
-        const int2 rw = g.row_ew[ir];
-        ra = lo16(rw.x);
-        rz = hi16(rw.x);
-        dA = g.dA[ir];
-        dC = g.dC[ir];
-    }
     const int li = c.r0 + rowl;
     struct In {
         VjpIn x;
@@ -711,6 +702,12 @@ __global__ void __launch_bounds__(NT)
         in.lpr = lp[so + ir];
         in.lqr = lq[so + ir];
     };
+    In first;  // first state's gathers before the row loads, as in k_ew
+    load(sb, first);
+    const int irr = rowt ? ir : g.nb;
+    const int2 rw = g.row_ew[irr];
+    const double dA = g.dA[irr], dC = g.dC[irr];
+    const int ra = lo16(rw.x), rz = hi16(rw.x);
     // As in k_ew: every lane computes; stores depend on the lane's role.
     auto proc = [&](int s, int p, const In &in) {
         double ga, gv;
@@ -727,7 +724,7 @@ __global__ void __launch_bounds__(NT)
             gvm[so + ir] = gm;
         }
     };
-    pipelined_states<In, ONE>(sb, se, load, proc);
+    pipelined_states<In, ONE>(sb, se, first, load, proc);
 }
 
 // ===================================================================
@@ -770,7 +767,12 @@ __global__ void k_items_init(DevSetup s) {
 // ((y_h + y_hk)/m^2 at a from end, y_k + y_hk at a to end) and the shunt.
 __global__ void k_bus_diag(DevSetup s) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= s.nb) return;
+    if (i > s.nb) return;
+    if (i == s.nb) {  // the inert entry read by lanes without a row
+        s.dA[i] = 0.0;
+        s.dC[i] = 0.0;
+        return;
+    }
     double re = 0.0, im = 0.0;
     for (int e = s.irow[i]; e < s.irow[i + 1]; ++e) {
         const int br = s.item_br[e];
@@ -814,14 +816,20 @@ __global__ void k_ybus_assemble(DevSetup s) {
 // in lane order; inert lanes get zeros.
 __global__ void k_lane_fill(DevLaneFill f, bool ew) {
     const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (l >= f.nlanes) return;
     if (ew) {
+        if (l >= f.nlanes) return;
         const int e = f.lane_rec[l];
         f.lane_gb[l] = e >= 0 ? make_double2(f.G[e], f.B[e]) : make_double2(0.0, 0.0);
         f.lane_grbr[l] = e >= 0 ? make_double2(f.Gr[e], f.Br[e]) : make_double2(0.0, 0.0);
     } else {
-        const int q = f.ylane_slot[l];
-        f.ylane_y[l] = q >= 0 ? make_double2(f.yre[q], f.yim[q]) : make_double2(0.0, 0.0);
+        if (l < f.nlanes) {
+            const int q = f.ylane_slot[l];
+            f.ylane_y[l] = q >= 0 ? make_double2(f.yre[q], f.yim[q]) : make_double2(0.0, 0.0);
+        }
+        if (l <= f.nb) {
+            const int q = l < f.nb ? f.ydslot[l] : -1;
+            f.ydiag[l] = q >= 0 ? make_double2(f.yre[q], f.yim[q]) : make_double2(0.0, 0.0);
+        }
     }
 }
 
@@ -956,15 +964,16 @@ hipError_t launch_setup_items(const DevSetup &s, hipStream_t stream) {
         if (e != hipSuccess) return e;
     }
     if (s.nb > 0) {
-        const int64_t blocks = (s.nb + 255) / 256;
+        const int64_t blocks = ((int64_t)s.nb + 1 + 255) / 256;
         hipLaunchKernelGGL(k_bus_diag, dim3((unsigned)blocks), dim3(256), 0, stream, s);
     }
     return hipGetLastError();
 }
 
 hipError_t launch_lane_fill(const DevLaneFill &f, bool ew, hipStream_t stream) {
-    if (f.nlanes == 0) return hipSuccess;
-    const int64_t blocks = (f.nlanes + 255) / 256;
+    const int64_t n = ew ? f.nlanes : std::max<int64_t>(f.nlanes, (int64_t)f.nb + 1);
+    if (n == 0) return hipSuccess;
+    const int64_t blocks = (n + 255) / 256;
     hipLaunchKernelGGL(k_lane_fill, dim3((unsigned)blocks), dim3(256), 0, stream, f, ew);
     return hipGetLastError();
 }
