@@ -4,7 +4,11 @@ One step = one evaluation of S = P + jQ and all Jacobian values of a
 100,000-bus, 130,000-branch synthetic grid (one voltage state) by the
 element-wise method: one kernel launch.  To keep every step cold in the
 256 MB Infinity Cache, steps rotate over R independent replicas of the
-problem (grid data, state and outputs), R x 23 MB >= 512 MB.
+problem (grid data, state and outputs), R x 27 MB >= 512 MB.  Steps are
+issued as replays of HIP graphs that record R consecutive launches: a
+Python call costs about as much host time as the kernel takes, so one call
+per step would measure the host.  The eager one-call-per-step rate is
+reported beside it.
 
 Printed (one JSON line): evals/s, the roofline of the dominant kernel
 (algorithmic bytes per launch / average launch time, HIP events on the
@@ -170,25 +174,60 @@ def main():
     tile, spb, order, ntiles = G0.schedule()
     log(f"grid nb={g.nb} nl={g.nl} nnzY={nnz_y} nnzJ={nnz_j} tiles={ntiles} replicas={R}")
 
-    def timed(fn, steps, warmup):
-        for k in range(warmup):
-            fn(k)
+    side = torch.cuda.Stream()  # the launch stream (default priority)
+
+    def timed(fn, steps, warmup, period=R):
+        """Time exactly `steps` launches fn(k, stream), issued as replays of HIP
+        graphs that record `period` consecutive launches (plus one graph for
+        the remainder), so the host cost of a call does not bound the rate.
+        Returns (seconds by HIP events on the launch stream, wall seconds)."""
+        period = max(1, min(period, steps))
+        with torch.cuda.stream(side):
+            for k in range(max(warmup, period)):
+                fn(k, side)
         torch.cuda.synchronize()
-        s = torch.cuda.current_stream()
+
+        def record(n):
+            gr = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(gr, stream=side):
+                for k in range(n):
+                    fn(k, side)
+            return gr
+        full, rest = divmod(steps, period)
+        g_full = record(period) if full else None
+        g_rest = record(rest) if rest else None
+        with torch.cuda.stream(side):
+            for _ in range(2):
+                (g_full or g_rest).replay()
+        torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         t0 = time.perf_counter()
-        e0.record(s)
-        for k in range(steps):
-            fn(k)
-        e1.record(s)
+        with torch.cuda.stream(side):
+            e0.record(side)
+            for _ in range(full):
+                g_full.replay()
+            if g_rest is not None:
+                g_rest.replay()
+            e1.record(side)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         return e0.elapsed_time(e1) / 1e3, wall
 
-    def ew_sj(k):
+    def eager_timed(fn, steps, warmup):
+        """The same launches issued one Python call at a time (host-bound)."""
+        for k in range(warmup):
+            fn(k, side)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(steps):
+            fn(k, side)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    def ew_sj(k, st=None):
         d = reps[k % R]
-        pf.pf_jacobian_values(d["G"], pf.PF_METHOD_ELEMENTWISE, d["vm"], d["va"], d["p"], d["q"], d["j"])
+        pf.pf_jacobian_values(d["G"], pf.PF_METHOD_ELEMENTWISE, d["vm"], d["va"], d["p"], d["q"], d["j"], stream=st)
 
     if args.probe:
         for k in range(2 * R):
@@ -230,7 +269,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic (seeded generator standing in for the paper's MATPOWER cases)",
         "config": {"workload": "100k-bus grid (nb=100000, nl=130000, 20% transformers), 1 voltage state, "
-                               "element-wise S + full polar Jacobian, one launch per step",
+                               "element-wise S + full polar Jacobian, one launch per step, steps issued as "
+                               "HIP-graph replays over 24 cold replicas",
                    "nb": g.nb, "nl": g.nl, "nnz_y": nnz_y, "nnz_j": nnz_j, "states": 1,
                    "replicas_rotated": R, "tile_items": tile},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -248,9 +288,9 @@ def main():
             pf.pf_ybus(d["G"])
         torch.cuda.synchronize()
 
-        def yb_sj(k):
+        def yb_sj(k, st):
             d = reps[k % R]
-            pf.pf_jacobian_values(d["G"], pf.PF_METHOD_YBUS, d["vm"], d["va"], d["p"], d["q"], d["j"])
+            pf.pf_jacobian_values(d["G"], pf.PF_METHOD_YBUS, d["vm"], d["va"], d["p"], d["q"], d["j"], stream=st)
         ev, wall = timed(yb_sj, K, W)
         yb_bytes = algorithmic_bytes(g.nb, g.nl, nnz_y, 1, method="ybus")
         extra["ybus_sj"] = {"evals_per_s": K / wall, "avg_launch_us": ev / K * 1e6,
@@ -263,7 +303,7 @@ def main():
         n = abytes // 16
         ca = [torch.ones(n, dtype=torch.float64, device=dev) for _ in range(R)]
         cb = [torch.empty(n, dtype=torch.float64, device=dev) for _ in range(R)]
-        ev, wall = timed(lambda k: cb[k % R].copy_(ca[k % R]), K, W)
+        ev, wall = timed(lambda k, st: cb[k % R].copy_(ca[k % R]), K, W)
         extra["copy_same_bytes"] = {"bytes": 16 * n, "avg_launch_us": ev / K * 1e6,
                                     "GBs": 16 * n / (ev / K) / 1e9,
                                     "headline_over_copy_time": avg_launch / (ev / K)}
@@ -271,22 +311,25 @@ def main():
         log(f"copy of the same bytes: {ev / K * 1e6:.2f} us")
 
     if want("warm"):
-        def ew_warm(k):
+        def ew_warm(k, st):
             d = reps[0]
-            pf.pf_jacobian_values(d["G"], pf.PF_METHOD_ELEMENTWISE, d["vm"], d["va"], d["p"], d["q"], d["j"])
+            pf.pf_jacobian_values(d["G"], pf.PF_METHOD_ELEMENTWISE, d["vm"], d["va"], d["p"], d["q"], d["j"], stream=st)
         ev, wall = timed(ew_warm, K, W)
         extra["ew_sj_warm_cache"] = {"evals_per_s": K / wall, "avg_launch_us": ev / K * 1e6}
+        wall = eager_timed(ew_sj, K, W)
+        extra["ew_sj_eager_python_calls"] = {"evals_per_s": K / wall, "us_per_call": wall / K * 1e6,
+                                             "note": "one binding call per step; bound by host time"}
 
-        def ew_s(k):
+        def ew_s(k, st):
             d = reps[k % R]
-            pf.pf_injections_elementwise(d["G"], d["vm"], d["va"], d["p"], d["q"])
+            pf.pf_injections_elementwise(d["G"], d["vm"], d["va"], d["p"], d["q"], stream=st)
         ev, wall = timed(ew_s, K, W)
         extra["ew_s_only"] = {"evals_per_s": K / wall, "avg_launch_us": ev / K * 1e6,
                               "achieved_GBs": algorithmic_bytes(g.nb, g.nl, nnz_y, 1, with_j=False) / (ev / K) / 1e9}
         if "ybus_sj" in extra:
-            def yb_s(k):
+            def yb_s(k, st):
                 d = reps[k % R]
-                pf.pf_injections_ybus(d["G"], d["vm"], d["va"], d["p"], d["q"])
+                pf.pf_injections_ybus(d["G"], d["vm"], d["va"], d["p"], d["q"], stream=st)
             ev, wall = timed(yb_s, K, W)
             extra["ybus_s_only"] = {"evals_per_s": K / wall, "avg_launch_us": ev / K * 1e6}
         log("warm/S-only done")
@@ -304,10 +347,10 @@ def main():
         q2 = torch.empty_like(p2)
         j2 = torch.empty(B, G2.nnz_j, dtype=torch.float64, device=dev)
 
-        def b_sj(k):
-            pf.pf_jacobian_values(G2, pf.PF_METHOD_ELEMENTWISE, vm2d, va2d, p2, q2, j2)
+        def b_sj(k, st):
+            pf.pf_jacobian_values(G2, pf.PF_METHOD_ELEMENTWISE, vm2d, va2d, p2, q2, j2, stream=st)
         steps = max(20, K // 40)
-        ev, wall = timed(b_sj, steps, 5)
+        ev, wall = timed(b_sj, steps, 5, period=10)
         bb = algorithmic_bytes(g2.nb, g2.nl, G2.nnz_y, B)
         extra["batched_20k_x512"] = {"state_evals_per_s": B * steps / wall, "avg_launch_us": ev / steps * 1e6,
                                      "achieved_GBs": bb / (ev / steps) / 1e9,
@@ -328,10 +371,10 @@ def main():
         q3 = torch.empty_like(p3)
         j3 = torch.empty(4, G3.nnz_j, dtype=torch.float64, device=dev)
 
-        def m_sj(k):
-            pf.pf_jacobian_values(G3, pf.PF_METHOD_ELEMENTWISE, vm3d, va3d, p3, q3, j3)
+        def m_sj(k, st):
+            pf.pf_jacobian_values(G3, pf.PF_METHOD_ELEMENTWISE, vm3d, va3d, p3, q3, j3, stream=st)
         steps = max(20, K // 40)
-        ev, wall = timed(m_sj, steps, 5)
+        ev, wall = timed(m_sj, steps, 5, period=10)
         mb = algorithmic_bytes(big.nb, big.nl, G3.nnz_y, 4)
         extra["multigrid_64x4"] = {"grid_state_evals_per_s": 256 * steps / wall, "avg_launch_us": ev / steps * 1e6,
                                    "achieved_GBs": mb / (ev / steps) / 1e9,
@@ -353,8 +396,10 @@ def main():
         gv = torch.empty_like(vm4d)
         ga = torch.empty_like(vm4d)
         steps = max(50, K // 20)
-        ev_f, _ = timed(lambda k: pf.pf_injections_elementwise(G4, vm4d, va4d, p4, q4), steps, 5)
-        ev_b, _ = timed(lambda k: pf.pf_injections_vjp(G4, vm4d, va4d, lp4d, lq4d, gv, ga), steps, 5)
+        ev_f, _ = timed(lambda k, st: pf.pf_injections_elementwise(G4, vm4d, va4d, p4, q4, stream=st), steps, 5,
+                        period=10)
+        ev_b, _ = timed(lambda k, st: pf.pf_injections_vjp(G4, vm4d, va4d, lp4d, lq4d, gv, ga, stream=st), steps, 5,
+                        period=10)
         fb = algorithmic_bytes(g.nb, g.nl, G4.nnz_y, B, with_j=False)
         bb = algorithmic_bytes(g.nb, g.nl, G4.nnz_y, B, vjp=True)
         extra["adjoint_100k_x32"] = {"forward_us": ev_f / steps * 1e6, "vjp_us": ev_b / steps * 1e6,

@@ -174,8 +174,8 @@ int pf_injections_vjp(const pf_grid *g, int32_t nstate, const double *vm, const 
                       void *stream);
 
 /* Launch schedule.
- *   tile_items        records per work tile (64, 128, 256 or 512); a
- *                     workgroup has that many threads
+ *   tile_items        workgroup size (64, 128, 256 or 512): branch ends per
+ *                     element-wise work tile, Ybus nonzeros per Ybus tile
  *   states_per_block  voltage states one workgroup evaluates in turn, with
  *                     the tile's constants held in registers (>= 1; 0 =
  *                     automatic)
@@ -186,11 +186,51 @@ int pf_injections_vjp(const pf_grid *g, int32_t nstate, const double *vm, const 
  *                     adjacent, so concurrent workgroups write neighbouring
  *                     parts of J)
  * Changing the schedule never changes results.  Rebuilds the tile list on
- * the host and device; not for use while work on the handle is in flight. */
+ * the host and device; not for use while work on the handle is in flight.
+ * Graphs recorded before the call must be recorded again. */
 enum { PF_ORDER_AUTO = 0, PF_ORDER_TILE_MAJOR = 1, PF_ORDER_STATE_MAJOR = 2 };
 int pf_set_schedule(pf_grid *g, int32_t tile_items, int32_t states_per_block, int32_t order);
+/* ntiles: element-wise work tiles of the current schedule. */
 int pf_get_schedule(const pf_grid *g, int32_t *tile_items, int32_t *states_per_block, int32_t *order,
                     int32_t *ntiles);
+
+/* Recorded evaluation sequences (HIP graphs).
+ * The evaluation calls above only enqueue kernels (no allocation, no host
+ * synchronisation, no memory set), so a fixed sequence of them on fixed
+ * buffers can be recorded once and replayed with a single launch; loops that
+ * evaluate one grid many times (Newton iterations, repeated scenario sweeps)
+ * then pay the host cost of a call once.
+ *
+ * pf_graph_create records `nops` operations in order:
+ *   PF_OP_INJECTIONS  pf_injections_elementwise / pf_injections_ybus by
+ *                     `method`; P = out_a, Q = out_b
+ *   PF_OP_JACOBIAN    pf_jacobian_values(method); P = out_a, Q = out_b
+ *                     (both may be NULL), J = jval
+ *   PF_OP_VJP         pf_injections_vjp; lam_p, lam_q in, g_vm = out_a,
+ *                     g_va = out_b
+ * with the checks, layouts and error codes of those calls; unused pointers
+ * are ignored.  On error *out stays NULL and nothing is recorded.  The graph
+ * refers to the grid's device tables and to the given buffers (caller-owned,
+ * device memory): free the graph before the grid, keep the buffers alive
+ * while it is in use.  pf_ybus may run between launches (Ybus values are
+ * refreshed in place); after pf_set_schedule, pf_graph_launch returns
+ * PF_ESTATE and the graph must be recorded again.  pf_graph_launch enqueues
+ * the whole sequence on `stream`; replays on one stream run in order, replays
+ * on different streams may overlap and then race on shared outputs. */
+typedef struct pf_graph pf_graph;
+enum { PF_OP_INJECTIONS = 0, PF_OP_JACOBIAN = 1, PF_OP_VJP = 2 };
+typedef struct {
+    int32_t op;      /* PF_OP_* */
+    int32_t method;  /* PF_METHOD_* (PF_OP_INJECTIONS, PF_OP_JACOBIAN) */
+    int32_t nstate;
+    const double *vm, *va;
+    const double *lam_p, *lam_q; /* PF_OP_VJP */
+    double *out_a, *out_b;
+    double *jval; /* PF_OP_JACOBIAN */
+} pf_op;
+int pf_graph_create(const pf_grid *g, const pf_op *ops, int32_t nops, pf_graph **out);
+int pf_graph_launch(const pf_graph *gr, void *stream);
+void pf_graph_free(pf_graph *gr);
 
 /* Description of the last error on the calling thread ("" if none).  The
  * string stays valid until the next pf_* call on that thread. */

@@ -61,12 +61,13 @@ struct pf_grid {
     std::vector<int32_t> slot_row, slot_item;
 
     int32_t tile_items = 256, states_per_block = 0, order = PF_ORDER_AUTO;
-    std::vector<pf::TileDesc> tiles;
+    std::vector<pf::TileDesc> tiles, ytiles;  // element-wise and Ybus work tiles
     int32_t num_cus = 0;
     pf::DevLaneFill lanes{};  // gather sources and targets of the lane values
 
     void *dmem = nullptr;   // grid data
     void *dtile = nullptr;  // schedule
+    uint64_t sched_gen = 0;  // bumped by every schedule change (recorded graphs check it)
     pf::DevGrid dev{};
     pf::DevSetup setup{};  // device view used by the setup kernels
 };
@@ -79,123 +80,159 @@ bool finite_all(const double *a, int64_t n) {
     return true;
 }
 
-// Greedy row-aligned tiles inside each grid: a tile holds whole rows with at
-// most `cap` records in total; a row with more records than `cap` forms a
-// tile of its own, which the kernels walk in chunks.
-void build_tiles(pf_grid *g, int cap) {
+// Row-aligned tiles inside each grid, built greedily.
+//   Element-wise tiles (g->tiles): at most NT branch ends (one lane each), NT
+//   rows and kEwSlots(NT) Ybus slots (the LDS copy of the tile's J rows).  A
+//   row with more than NT branch ends is a tile of its own, walked in chunks.
+//   Ybus tiles (g->ytiles): at most NT slots (one lane each); a row with more
+//   than NT slots is a tile of its own.
+// Shunt records take no lane: their only content is the diagonal slot, whose
+// J entries the row thread writes.
+void build_tiles(pf_grid *g, int NT) {
+    const int NS = pf::kEwSlots(NT);
     g->tiles.clear();
+    g->ytiles.clear();
     for (int32_t gi = 0; gi < g->ngrids; ++gi) {
-        int32_t r = g->bus_off[gi], end = g->bus_off[gi + 1];
-        int32_t start = r;
-        int64_t cnt = 0;
-        auto close = [&](int32_t upto) {
-            if (upto > start) {
-                pf::TileDesc d;
-                d.r0 = start;
-                d.nrows = upto - start;
-                d.i0 = g->irow[start];
-                d.n = g->irow[upto] - d.i0;
-                d.s0 = g->yrow[start];
-                d.ns = g->yrow[upto] - d.s0;
-                // Grid gi's J values start at 4 y_off[gi]; its P rows hold
-                // 2 nnz_y(gi) values, so row i's P part starts at
-                // 2 y_off[gi] + 2 yrow[i] and its Q part at 2 y_off[gi+1] + 2 yrow[i].
-                d.jp = 2 * g->y_off[gi] + 2 * (int64_t)d.s0;
-                d.jq = 2 * g->y_off[gi + 1] + 2 * (int64_t)d.s0;
-                g->tiles.push_back(d);
-            }
-            start = upto;
-            cnt = 0;
+        const int32_t rb = g->bus_off[gi], re = g->bus_off[gi + 1];
+        auto desc = [&](int32_t a, int32_t z) {
+            pf::TileDesc d;
+            d.r0 = a;
+            d.nrows = z - a;
+            d.i0 = g->irow[a];
+            d.n = g->irow[z] - d.i0;
+            d.ne = d.n - (z - a);  // one shunt record per row
+            d.s0 = g->yrow[a];
+            d.ns = g->yrow[z] - d.s0;
+            // Grid gi's J values start at 4 y_off[gi]; its P rows hold
+            // 2 nnz_y(gi) values, so row i's P part starts at
+            // 2 y_off[gi] + 2 yrow[i] and its Q part at 2 y_off[gi+1] + 2 yrow[i].
+            d.jp = 2 * g->y_off[gi] + 2 * (int64_t)d.s0;
+            d.jq = 2 * g->y_off[gi + 1] + 2 * (int64_t)d.s0;
+            return d;
         };
-        for (; r < end; ++r) {
-            int64_t n = g->irow[r + 1] - g->irow[r];
-            if (n > cap) {
-                close(r);
-                close(r + 1);
+        // element-wise
+        int32_t start = rb;
+        int64_t ce = 0, cs = 0;
+        auto close = [&](std::vector<pf::TileDesc> &out, int32_t upto) {
+            if (upto > start) out.push_back(desc(start, upto));
+            start = upto;
+            ce = cs = 0;
+        };
+        for (int32_t r = rb; r < re; ++r) {
+            const int64_t ne = g->irow[r + 1] - g->irow[r] - 1, ns = g->yrow[r + 1] - g->yrow[r];
+            if (ne > NT) {
+                close(g->tiles, r);
+                close(g->tiles, r + 1);
                 continue;
             }
-            if (cnt + n > cap) close(r);
-            cnt += n;
+            if (ce + ne > NT || cs + ns > NS || r - start + 1 > NT) close(g->tiles, r);
+            ce += ne;
+            cs += ns;
         }
-        close(end);
+        close(g->tiles, re);
+        // Ybus
+        start = rb;
+        for (int32_t r = rb; r < re; ++r) {
+            const int64_t ns = g->yrow[r + 1] - g->yrow[r];
+            if (ns > NT) {
+                close(g->ytiles, r);
+                close(g->ytiles, r + 1);
+                continue;
+            }
+            if (cs + ns > NT) close(g->ytiles, r);
+            cs += ns;
+        }
+        close(g->ytiles, re);
     }
 }
 
 // Lane tables of the packed tiles (tile size NT).  Positions inside the LDS
-// copy of a tile's J rows: the P rows take [0, 2 NT), the Q rows start at
-// 2 NT + 2, and position 2 NT (Q: 4 NT + 2) is a pad that absorbs the
-// writes of lanes with nothing to write.  For row r of a tile with local
-// slot range [ya, yz) and local slot ls, dP/dtheta sits at ya + ls and
-// dP/dv at yz + ls (Section IV.B.2: J11 and J12 entries of one row are
-// adjacent, as are J21 and J22).
+// copy of a tile's J rows (slot capacity NS): the P rows take [0, 2 NS), the
+// Q rows start at 2 NS + 2, and position 2 NS (Q: 4 NS + 2) is a pad that
+// absorbs the writes of lanes with nothing to write.  For row r of a tile
+// with local slot range [ya, yz) and local slot ls, dP/dtheta sits at
+// ya + ls and dP/dv at yz + ls (Section IV.B.2: J11 and J12 entries of one
+// row are adjacent, as are J21 and J22).
 struct HostLanes {
-    std::vector<int32_t> lane_j, lane_rec, ylane_j, ylane_slot;
-    std::vector<int32_t> lane_pk, ylane_pk;  // pairs
-    std::vector<int32_t> row_ew, row_yb;     // pairs per bus, + one inert entry at nb
-    std::vector<int32_t> ydslot;             // [nb] global Ybus slot of each diagonal
+    std::vector<int32_t> lane_j, lane_rec, lane_pk, lane_run;
+    std::vector<int32_t> ylane_j, ylane_slot, ylane_pk;  // ylane_pk: pairs
+    std::vector<int32_t> row_ew, row_yb;                 // pairs per bus, + one inert entry at nb
+    std::vector<int32_t> ydslot;                         // [nb] global Ybus slot of each diagonal
 };
 
 HostLanes build_lanes(const pf_grid *g) {
     const int NT = g->tile_items;
-    const int32_t pad = 2 * NT;
-    const size_t nl = g->tiles.size() * (size_t)NT;
+    const int32_t epad = 2 * pf::kEwSlots(NT), ypad = 2 * NT;
+    const size_t nle = g->tiles.size() * (size_t)NT, nly = g->ytiles.size() * (size_t)NT;
     HostLanes h;
-    h.lane_j.assign(nl, 0);
-    h.lane_rec.assign(nl, -1);
-    h.ylane_j.assign(nl, 0);
-    h.ylane_slot.assign(nl, -1);
-    h.lane_pk.assign(2 * nl, 0);
-    h.ylane_pk.assign(2 * nl, 0);
-    const int32_t padpair = pad | (pad << 16);
+    h.lane_j.assign(nle, 0);
+    h.lane_rec.assign(nle, -1);
+    h.lane_pk.assign(nle, pf::ew_pack(epad, epad, 0));
+    h.lane_run.assign(g->has_parallel ? nle : 1, 0);
+    h.ylane_j.assign(nly, 0);
+    h.ylane_slot.assign(nly, -1);
+    h.ylane_pk.assign(2 * nly, 0);
     // Entry nb is what lanes without a row read: empty ranges, pad targets.
     h.row_ew.assign(2 * ((size_t)g->nb + 1), 0);
     h.row_yb.assign(2 * ((size_t)g->nb + 1), 0);
-    h.row_ew[2 * (size_t)g->nb + 1] = padpair;
-    h.row_yb[2 * (size_t)g->nb + 1] = pad;
+    h.row_ew[2 * (size_t)g->nb + 1] = epad | (epad << 16);
+    h.row_yb[2 * (size_t)g->nb + 1] = ypad;
     h.ydslot.assign(g->nb, 0);
-    for (int32_t i = 0; i < g->nb; ++i)
+    auto diag_slot = [&](int32_t i) {
         for (int32_t q = g->yrow[i]; q < g->yrow[i + 1]; ++q)
-            if (g->ycol[q] == i) h.ydslot[i] = q;
+            if (g->ycol[q] == i) return q;
+        return g->yrow[i];  // every bus has its diagonal slot
+    };
+    for (int32_t i = 0; i < g->nb; ++i) h.ydslot[i] = diag_slot(i);
     for (size_t t = 0; t < g->tiles.size(); ++t) {
         const pf::TileDesc &c = g->tiles[t];
         const size_t base = t * NT;
-        for (int k = 0; k < NT; ++k) {
-            h.lane_j[base + k] = c.r0;
-            h.ylane_j[base + k] = c.r0;
-            h.lane_pk[2 * (base + k)] = padpair;
-            h.ylane_pk[2 * (base + k)] = padpair;
-        }
-        if (c.n > NT) continue;  // long row: walked without lane tables
+        for (int k = 0; k < NT; ++k) h.lane_j[base + k] = c.r0;
+        if (c.ne > NT) continue;  // long row: walked without lane tables
+        int32_t lane = 0;
         for (int32_t row = 0; row < c.nrows; ++row) {
             const int32_t i = c.r0 + row;
             const int32_t ya = g->yrow[i] - c.s0, yz = g->yrow[i + 1] - c.s0;
-            const int32_t ra = g->irow[i] - c.i0, rz = g->irow[i + 1] - c.i0;
-            int32_t dls = ya;
-            for (int32_t q = g->yrow[i]; q < g->yrow[i + 1]; ++q)
-                if (g->ycol[q] == i) dls = q - c.s0;
-            h.row_ew[2 * i] = ra | (rz << 16);
-            h.row_ew[2 * i + 1] = (ya + dls) | ((yz + dls) << 16);
-            h.row_yb[2 * i] = ya | (yz << 16);
-            h.row_yb[2 * i + 1] = dls;
+            const int32_t dls = h.ydslot[i] - c.s0;
+            const int32_t ra = lane;
             for (int32_t e = g->irow[i]; e < g->irow[i + 1]; ++e) {
-                const size_t L = base + (e - c.i0);
-                const int32_t j = g->nbr[e], ls = g->slot[e] - c.s0;
-                const bool head = j != i && (e == g->irow[i] || g->slot[e - 1] != g->slot[e]);
+                if (g->item_br[e] < 0) continue;  // the shunt record
+                const size_t L = base + lane++;
+                const int32_t ls = g->slot[e] - c.s0;
+                // first branch end of its slot (parallel branches share a slot)
+                const bool head = e == g->irow[i] || g->slot[e - 1] != g->slot[e] || g->item_br[e - 1] < 0;
                 int32_t run = 0;
                 if (head)
                     while (e + run < g->irow[i + 1] && g->slot[e + run] == g->slot[e]) ++run;
-                h.lane_j[L] = j;
+                h.lane_j[L] = g->nbr[e];
                 h.lane_rec[L] = e;
-                h.lane_pk[2 * L] = head ? ((ya + ls) | ((yz + ls) << 16)) : padpair;
-                h.lane_pk[2 * L + 1] = row | (run << 16);
+                h.lane_pk[L] = head ? pf::ew_pack(ya + ls, yz + ls, row) : pf::ew_pack(epad, epad, row);
+                if (g->has_parallel) h.lane_run[L] = run;
             }
+            h.row_ew[2 * i] = ra | (lane << 16);
+            h.row_ew[2 * i + 1] = (ya + dls) | ((yz + dls) << 16);
+        }
+    }
+    for (size_t t = 0; t < g->ytiles.size(); ++t) {
+        const pf::TileDesc &c = g->ytiles[t];
+        const size_t base = t * NT;
+        for (int k = 0; k < NT; ++k) {
+            h.ylane_j[base + k] = c.r0;
+            h.ylane_pk[2 * (base + k)] = ypad | (ypad << 16);
+        }
+        if (c.ns > NT) continue;
+        for (int32_t row = 0; row < c.nrows; ++row) {
+            const int32_t i = c.r0 + row;
+            const int32_t ya = g->yrow[i] - c.s0, yz = g->yrow[i + 1] - c.s0;
+            h.row_yb[2 * i] = ya | (yz << 16);
+            h.row_yb[2 * i + 1] = h.ydslot[i] - c.s0;
             for (int32_t q = g->yrow[i]; q < g->yrow[i + 1]; ++q) {
                 const size_t L = base + (q - c.s0);
                 const int32_t ls = q - c.s0;
                 const bool dg = g->ycol[q] == i;
                 h.ylane_j[L] = g->ycol[q];
                 h.ylane_slot[L] = q;
-                h.ylane_pk[2 * L] = dg ? padpair : ((ya + ls) | ((yz + ls) << 16));
+                h.ylane_pk[2 * L] = dg ? (ypad | (ypad << 16)) : ((ya + ls) | ((yz + ls) << 16));
                 h.ylane_pk[2 * L + 1] = row | ((dg ? 1 : 0) << 16);
             }
         }
@@ -212,14 +249,16 @@ int upload_tiles(pf_grid *g) {
         if (e != hipSuccess) return hip_fail(e, "hipFree(schedule)");
     }
     const HostLanes h = build_lanes(g);
-    const size_t nt = g->tiles.size();
-    const size_t nl = nt * (size_t)g->tile_items;
+    const size_t nt = g->tiles.size(), nyt = g->ytiles.size();
+    const size_t nle = nt * (size_t)g->tile_items, nly = nyt * (size_t)g->tile_items;
+    const size_t nrun = h.lane_run.size();
     Arena ar;
-    const size_t o_t = ar.take<pf::TileDesc>(nt);
-    const size_t o_lj = ar.take<int32_t>(nl), o_lrec = ar.take<int32_t>(nl), o_lpk = ar.take<int2>(nl);
-    const size_t o_lgb = ar.take<double2>(nl), o_lgr = ar.take<double2>(nl), o_rew = ar.take<int2>(g->nb + 1);
-    const size_t o_yj = ar.take<int32_t>(nl), o_yslot = ar.take<int32_t>(nl), o_ypk = ar.take<int2>(nl);
-    const size_t o_yy = ar.take<double2>(nl), o_ryb = ar.take<int2>(g->nb + 1);
+    const size_t o_t = ar.take<pf::TileDesc>(nt), o_yt = ar.take<pf::TileDesc>(nyt);
+    const size_t o_lj = ar.take<int32_t>(nle), o_lrec = ar.take<int32_t>(nle), o_lpk = ar.take<int32_t>(nle);
+    const size_t o_lrun = ar.take<int32_t>(nrun);
+    const size_t o_lgb = ar.take<double2>(nle), o_lgr = ar.take<double2>(nle), o_rew = ar.take<int2>(g->nb + 1);
+    const size_t o_yj = ar.take<int32_t>(nly), o_yslot = ar.take<int32_t>(nly), o_ypk = ar.take<int2>(nly);
+    const size_t o_yy = ar.take<double2>(nly), o_ryb = ar.take<int2>(g->nb + 1);
     const size_t o_yds = ar.take<int32_t>(g->nb), o_ydg = ar.take<double2>(g->nb + 1);
     e = hipMalloc(&g->dtile, ar.off);
     if (e != hipSuccess) {
@@ -233,21 +272,26 @@ int upload_tiles(pf_grid *g) {
         if (ee == hipSuccess && bytes) ee = hipMemcpy(base + off, src, bytes, hipMemcpyHostToDevice);
     };
     up(o_t, g->tiles.data(), nt * sizeof(pf::TileDesc));
-    up(o_lj, h.lane_j.data(), nl * 4);
-    up(o_lrec, h.lane_rec.data(), nl * 4);
-    up(o_lpk, h.lane_pk.data(), nl * 8);
+    up(o_yt, g->ytiles.data(), nyt * sizeof(pf::TileDesc));
+    up(o_lj, h.lane_j.data(), nle * 4);
+    up(o_lrec, h.lane_rec.data(), nle * 4);
+    up(o_lpk, h.lane_pk.data(), nle * 4);
+    up(o_lrun, h.lane_run.data(), nrun * 4);
     up(o_rew, h.row_ew.data(), ((size_t)g->nb + 1) * 8);
-    up(o_yj, h.ylane_j.data(), nl * 4);
-    up(o_yslot, h.ylane_slot.data(), nl * 4);
-    up(o_ypk, h.ylane_pk.data(), nl * 8);
+    up(o_yj, h.ylane_j.data(), nly * 4);
+    up(o_yslot, h.ylane_slot.data(), nly * 4);
+    up(o_ypk, h.ylane_pk.data(), nly * 8);
     up(o_ryb, h.row_yb.data(), ((size_t)g->nb + 1) * 8);
     up(o_yds, h.ydslot.data(), (size_t)g->nb * 4);
     if (ee != hipSuccess) return hip_fail(ee, "hipMemcpy(schedule)");
     pf::DevGrid &d = g->dev;
     d.tiles = reinterpret_cast<const pf::TileDesc *>(base + o_t);
     d.ntiles = (int32_t)nt;
+    d.ytiles = reinterpret_cast<const pf::TileDesc *>(base + o_yt);
+    d.nytiles = (int32_t)nyt;
     d.lane_j = reinterpret_cast<const int32_t *>(base + o_lj);
-    d.lane_pk = reinterpret_cast<const int2 *>(base + o_lpk);
+    d.lane_pk = reinterpret_cast<const int32_t *>(base + o_lpk);
+    d.lane_run = reinterpret_cast<const int32_t *>(base + o_lrun);
     d.lane_gb = reinterpret_cast<const double2 *>(base + o_lgb);
     d.lane_grbr = reinterpret_cast<const double2 *>(base + o_lgr);
     d.row_ew = reinterpret_cast<const int2 *>(base + o_rew);
@@ -257,7 +301,8 @@ int upload_tiles(pf_grid *g) {
     d.row_yb = reinterpret_cast<const int2 *>(base + o_ryb);
     d.ydiag = reinterpret_cast<const double2 *>(base + o_ydg);
     pf::DevLaneFill &f = g->lanes;
-    f.nlanes = (int64_t)nl;
+    f.nlanes = (int64_t)nle;
+    f.nylanes = (int64_t)nly;
     f.lane_rec = reinterpret_cast<const int32_t *>(base + o_lrec);
     f.ylane_slot = reinterpret_cast<const int32_t *>(base + o_yslot);
     f.G = d.G;
@@ -646,6 +691,7 @@ int pf_set_schedule(pf_grid *g, int32_t tile_items, int32_t states_per_block, in
         return fail(PF_EINVAL, "unknown order");
     g->states_per_block = states_per_block;
     g->order = order;
+    ++g->sched_gen;
     if (tile_items != g->tile_items) {
         g->tile_items = tile_items;
         build_tiles(g, tile_items);
@@ -686,7 +732,8 @@ int check_eval(const pf_grid *g, int32_t nstate) {
 int auto_states_per_block(const pf_grid *g, int kind, int32_t nstate) {
     if (g->states_per_block > 0) return std::min<int32_t>(g->states_per_block, std::max(nstate, 1));
     if (nstate <= 1) return 1;
-    const int64_t nt = std::max<int64_t>(1, (int64_t)g->tiles.size());
+    const bool yb = kind == pf::K_YB_S || kind == pf::K_YB_SJ;
+    const int64_t nt = std::max<int64_t>(1, (int64_t)(yb ? g->ytiles : g->tiles).size());
     int per_cu = pf::resident_blocks_per_cu(kind, g->tile_items, g->has_parallel);
     if (per_cu <= 0) per_cu = 4;
     const int64_t capacity = (int64_t)std::max(g->num_cus, 1) * per_cu;
@@ -807,6 +854,124 @@ int pf_injections_vjp(const pf_grid *g, int32_t nstate, const double *vm, const 
     L.gvm = g_vm;
     L.gva = g_va;
     return run(g, L, stream);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- graphs
+
+struct pf_graph {
+    const pf_grid *g = nullptr;
+    uint64_t gen = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+int op_kind(const pf_op &o) {
+    switch (o.op) {
+        case PF_OP_INJECTIONS:
+            return o.method == PF_METHOD_YBUS ? pf::K_YB_S : pf::K_EW_S;
+        case PF_OP_JACOBIAN:
+            return o.method == PF_METHOD_YBUS ? pf::K_YB_SJ : pf::K_EW_SJ;
+        default:
+            return pf::K_EW_VJP;
+    }
+}
+
+int record_op(const pf_grid *g, const pf_op &o, void *stream) {
+    switch (o.op) {
+        case PF_OP_INJECTIONS:
+            if (o.method == PF_METHOD_ELEMENTWISE)
+                return pf_injections_elementwise(g, o.nstate, o.vm, o.va, o.out_a, o.out_b, stream);
+            if (o.method == PF_METHOD_YBUS) return pf_injections_ybus(g, o.nstate, o.vm, o.va, o.out_a, o.out_b, stream);
+            return fail(PF_EINVAL, "unknown method");
+        case PF_OP_JACOBIAN:
+            return pf_jacobian_values(g, o.method, o.nstate, o.vm, o.va, o.out_a, o.out_b, o.jval, stream);
+        case PF_OP_VJP:
+            return pf_injections_vjp(g, o.nstate, o.vm, o.va, o.lam_p, o.lam_q, o.out_a, o.out_b, stream);
+        default:
+            return fail(PF_EINVAL, "unknown op");
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int pf_graph_create(const pf_grid *g, const pf_op *ops, int32_t nops, pf_graph **out) {
+    g_err.clear();
+    if (!out) return fail(PF_EINVAL, "out must not be NULL");
+    *out = nullptr;
+    if (!g) return fail(PF_EINVAL, "NULL handle");
+    if (!ops || nops <= 0) return fail(PF_EINVAL, "need at least one op");
+    if (g->host_only) return fail(PF_ESTATE, "handle was built with PF_BUILD_HOST_ONLY");
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (cur != g->device) return fail(PF_EINVAL, "current HIP device differs from the handle's device");
+    // Resolve every launch shape before recording, so that nothing but
+    // kernel launches happens while the stream is captured.
+    for (int32_t k = 0; k < nops; ++k)
+        if (ops[k].nstate > 0) auto_states_per_block(g, op_kind(ops[k]), ops[k].nstate);
+    hipStream_t s = nullptr;
+    e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
+    e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        (void)hipStreamDestroy(s);
+        return hip_fail(e, "hipStreamBeginCapture");
+    }
+    int st = PF_OK;
+    for (int32_t k = 0; k < nops && st == PF_OK; ++k) st = record_op(g, ops[k], s);
+    std::string err = g_err;
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(s, &graph);
+    (void)hipStreamDestroy(s);
+    if (st != PF_OK || e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        if (st != PF_OK) return fail(st, err);
+        return hip_fail(e, "hipStreamEndCapture");
+    }
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return hip_fail(e, "hipGraphInstantiate");
+    }
+    pf_graph *gr = new (std::nothrow) pf_graph;
+    if (!gr) {
+        (void)hipGraphExecDestroy(exec);
+        (void)hipGraphDestroy(graph);
+        return fail(PF_ENOMEM, "host allocation failed");
+    }
+    gr->g = g;
+    gr->gen = g->sched_gen;
+    gr->graph = graph;
+    gr->exec = exec;
+    *out = gr;
+    return PF_OK;
+}
+
+int pf_graph_launch(const pf_graph *gr, void *stream) {
+    g_err.clear();
+    if (!gr) return fail(PF_EINVAL, "NULL graph");
+    if (gr->gen != gr->g->sched_gen) return fail(PF_ESTATE, "the grid's schedule changed since the graph was recorded");
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (cur != gr->g->device) return fail(PF_EINVAL, "current HIP device differs from the handle's device");
+    e = hipGraphLaunch(gr->exec, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    return PF_OK;
+}
+
+void pf_graph_free(pf_graph *gr) {
+    if (!gr) return;
+    if (gr->exec) (void)hipGraphExecDestroy(gr->exec);
+    if (gr->graph) (void)hipGraphDestroy(gr->graph);
+    delete gr;
 }
 
 }  // extern "C"

@@ -14,10 +14,19 @@ namespace pf {
 // One work tile: consecutive whole bus rows of one grid (see pf_kernels.hip).
 struct TileDesc {
     int32_t r0, nrows;  // first row (global bus), number of rows
-    int32_t i0, n;      // first record, number of records
+    int32_t i0, n;      // first record, number of records (shunt records included)
+    int32_t ne;         // branch-end records (n - nrows)
     int32_t s0, ns;     // first Ybus slot, number of slots
     int64_t jp, jq;     // offsets of the tile's P rows and Q rows in one state's J values
 };
+
+// Ybus slots an element-wise tile may hold (its LDS copy of the J rows),
+// for NT branch ends per tile: rows carry ~1.4 slots per branch end.
+constexpr int kEwSlots(int NT) { return NT + NT / 2; }
+
+// Element-wise lane word: LDS targets o11, o12 (11 bits each, at most
+// 2 kEwSlots(512) = 1536) and the tile row (9 bits, < 512).
+constexpr int32_t ew_pack(int32_t o11, int32_t o12, int32_t row) { return o11 | (o12 << 11) | (row << 22); }
 
 // Device view of a handle, passed to kernels by value.
 //
@@ -32,7 +41,8 @@ struct DevGrid {
     int32_t nb;           // buses over all grids
     int64_t nnz_y;        // Ybus nonzeros over all grids
     int64_t nnz_j;        // 4 nnz_y
-    int32_t ntiles;
+    int32_t ntiles;       // element-wise tiles
+    int32_t nytiles;      // Ybus tiles
     const int32_t *yrow;  // [nb+1] slot row pointer (global slot numbering)
     const int32_t *irow;  // [nb+1] item row pointer
     const int32_t *ycol;  // [nnz_y] global bus index of the column
@@ -42,13 +52,15 @@ struct DevGrid {
     const double *Gr, *Br;  // [nitems] coupling admittance of the other end (adjoint)
     const double *dA, *dC;    // [nb+1] sum of own-end admittances + shunt (Re / Im); [nb] = 0
     const double *yre, *yim;  // [nnz_y] Ybus values
-    const TileDesc *tiles;    // [ntiles]
+    const TileDesc *tiles;    // [ntiles] element-wise tiles
+    const TileDesc *ytiles;   // [nytiles] Ybus tiles
 
-    // Lane tables of the packed tiles, [ntiles * tile_items], entry
-    // t * tile_items + k for thread k of tile t (see pf_kernels.hip for the
-    // encodings).  Entries of idle lanes and of long-row tiles are inert.
-    const int32_t *lane_j;      // element-wise record: remote bus
-    const int2 *lane_pk;        // {o11 | o12 << 16, row | run << 16}
+    // Lane tables of the packed tiles, [ntiles * tile_items] (element-wise)
+    // and [nytiles * tile_items] (Ybus), entry t * tile_items + k for thread
+    // k of tile t.  Entries of idle lanes and of long-row tiles are inert.
+    const int32_t *lane_j;      // element-wise branch end: remote bus
+    const int32_t *lane_pk;     // ew_pack(o11, o12, row)
+    const int32_t *lane_run;    // with parallel branches: records of the slot (first record of a slot), else 0
     const double2 *lane_gb;     // {G, B}
     const double2 *lane_grbr;   // {Gr, Br}
     const int2 *row_ew;         // [nb+1] {ra | rz << 16, d11 | d12 << 16}; [nb] inert
@@ -62,7 +74,7 @@ struct DevGrid {
 // Gather sources of the lane tables: record (element-wise) and slot (Ybus)
 // of every lane, -1 for inert lanes.
 struct DevLaneFill {
-    int64_t nlanes;
+    int64_t nlanes, nylanes;  // element-wise, Ybus
     int32_t nb;
     const int32_t *lane_rec, *ylane_slot;
     const int32_t *ydslot;  // [nb] global slot of each bus's diagonal

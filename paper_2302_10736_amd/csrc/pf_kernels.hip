@@ -91,16 +91,17 @@ using Tile = TileDesc;
 
 __device__ __forceinline__ Tile tile_of(const DevGrid &g, int t) { return g.tiles[t]; }
 
-// LDS copy of one state's J rows of a packed tile: the P rows in [0, 2 NT),
-// the Q rows from kQ<NT> on, and one pad position (kPad<NT>, and
-// kQ<NT> + kPad<NT> on the Q side) that absorbs the writes of lanes with
-// nothing to write.  The Q offset keeps both halves 16-byte aligned.
-template <int NT>
-constexpr int kQ = 2 * NT + 2;
-template <int NT>
-constexpr int kPad = 2 * NT;
-template <int NT>
-constexpr int kJStage = 4 * NT + 4;
+// LDS copy of one state's J rows of a packed tile with at most NS Ybus
+// slots: the P rows in [0, 2 NS), the Q rows from kQ<NS> on, and one pad
+// position (kPad<NS>, and kQ<NS> + kPad<NS> on the Q side) that absorbs the
+// writes of lanes with nothing to write.  The Q offset keeps both halves
+// 16-byte aligned.
+template <int NS>
+constexpr int kQ = 2 * NS + 2;
+template <int NS>
+constexpr int kPad = 2 * NS;
+template <int NS>
+constexpr int kJStage = 4 * NS + 4;
 
 // Two 16-bit fields of a lane-table word.
 __device__ __forceinline__ int lo16(int v) { return v & 0xffff; }
@@ -116,17 +117,23 @@ __device__ __forceinline__ Cx cmul(Cx a, Cx b) {
 __device__ __forceinline__ Cx cconj(Cx a) { return {a.re, -a.im}; }
 __device__ __forceinline__ Cx cadd(Cx a, Cx b) { return {a.re + b.re, a.im + b.im}; }
 
-// Copy a staged tile of J rows (LDS) to global memory with 16-byte stores.
-template <int NT>
+// Copy a staged tile of J rows (LDS, slot capacity NS) to global memory
+// with 16-byte stores.
+template <int NT, int NS>
 __device__ __forceinline__ void write_jrows(const Tile &c, const double *s_J, double *Js) {
     const double2 *src = reinterpret_cast<const double2 *>(s_J);
     double2 *dp = reinterpret_cast<double2 *>(Js + c.jp);
     double2 *dq = reinterpret_cast<double2 *>(Js + c.jq);
     for (int q = threadIdx.x; q < c.ns; q += NT) {
         dp[q] = src[q];
-        dq[q] = src[kQ<NT> / 2 + q];
+        dq[q] = src[kQ<NS> / 2 + q];
     }
 }
+
+// Fields of an element-wise lane word (ew_pack).
+__device__ __forceinline__ int ew_o11(int v) { return v & 0x7ff; }
+__device__ __forceinline__ int ew_o12(int v) { return (v >> 11) & 0x7ff; }
+__device__ __forceinline__ int ew_row(int v) { return (int)((unsigned)v >> 22); }
 
 // Walk states [sb, se) (never empty) with the per-state inputs of each state
 // loaded one state ahead; `ra` holds state sb's inputs on entry.  Two register sets alternate (states are taken in pairs), so
@@ -216,10 +223,11 @@ __global__ void __launch_bounds__(NT)
          double *__restrict__ P, double *__restrict__ Q, double *__restrict__ J) {
     constexpr int NR = (WITH_J && PAR) ? NT : 1;  // remote partials kept for slot sums
     constexpr int NBUF = ONE ? 1 : 2;             // LDS buffers alternate between states
+    constexpr int NS = kEwSlots(NT);              // Ybus slots per tile
     __shared__ int s_ls[NT];   // long rows: local slot of each record of a chunk
     __shared__ int s_dslot[1];  // long rows: local diagonal slot
     __shared__ double s_ab[NBUF][2][NT];
-    __shared__ __align__(16) double s_J[NBUF][WITH_J ? kJStage<NT> : 2];
+    __shared__ __align__(16) double s_J[NBUF][WITH_J ? kJStage<NS> : 2];
     __shared__ double s_rem[NBUF][4][NR];
 
     const int W = g.ntiles * nchunk;
@@ -232,13 +240,13 @@ __global__ void __launch_bounds__(NT)
     // lane table entries do not depend on the tile descriptor: both load at once
     const size_t lane = (size_t)t * NT + k;
     const int j = g.lane_j[lane];
-    const int2 pk = g.lane_pk[lane];
+    const int pk = g.lane_pk[lane];
     const double2 gb = g.lane_gb[lane];
     const Tile c = tile_of(g, t);
     const size_t nb = (size_t)g.nb;
 
-    if (c.n > NT) {
-        // ---- one row with more than NT records, walked in chunks
+    if (c.ne > NT) {
+        // ---- one row with more than NT branch ends, walked in chunks of NT records
         const int i = c.r0;
         const int d = c.ns;  // slots in the row
         const double dA = g.dA[i], dC = g.dC[i];
@@ -321,14 +329,15 @@ __global__ void __launch_bounds__(NT)
         return;
     }
 
-    // ---- packed tile: whole rows, at most NT records.  Lane k holds
-    // record c.i0 + k (inert past c.n); its table entry gives the remote bus,
-    // the tile row, the LDS targets (o11, o12) of its remote partials (the
-    // pad for the shunt record, idle lanes and, with parallel branches,
-    // every record but the first of its slot) and, for the first record of
-    // a slot, the slot's record count.  Thread k < rows also owns row k.
-    const int rowl = lo16(pk.y), run = hi16(pk.y);
-    const int o11 = lo16(pk.x), o12 = hi16(pk.x);
+    // ---- packed tile: whole rows, at most NT branch ends.  Lane k holds
+    // the tile's k-th branch end (inert past c.ne; shunt records take no
+    // lane); its table entry gives the remote bus, the tile row and the LDS
+    // targets (o11, o12) of its remote partials (the pad for idle lanes and,
+    // with parallel branches, every record but the first of its slot, which
+    // also gets the slot's record count).  Thread k < rows also owns row k.
+    const int rowl = ew_row(pk);
+    const int o11 = ew_o11(pk), o12 = ew_o12(pk);
+    const int run = PAR ? g.lane_run[lane] : 0;
     const bool rowt = k < c.nrows;
     const int ir = c.r0 + (rowt ? k : 0);
     const int li = c.r0 + rowl;
@@ -370,8 +379,8 @@ __global__ void __launch_bounds__(NT)
             } else {
                 s_J[p][o11] = r.rpt;
                 s_J[p][o12] = r.rpv;
-                s_J[p][kQ<NT> + o11] = r.rqt;
-                s_J[p][kQ<NT> + o12] = r.rqv;
+                s_J[p][kQ<NS> + o11] = r.rqt;
+                s_J[p][kQ<NS> + o12] = r.rqv;
             }
         }
         lds_barrier();
@@ -381,8 +390,8 @@ __global__ void __launch_bounds__(NT)
         if constexpr (WITH_J) {
             s_J[p][d11] = o.j11;
             s_J[p][d12] = o.j12;
-            s_J[p][kQ<NT> + d11] = o.j21;
-            s_J[p][kQ<NT> + d12] = o.j22;
+            s_J[p][kQ<NS> + d11] = o.j21;
+            s_J[p][kQ<NS> + d12] = o.j22;
             if constexpr (PAR) {  // the first record of a slot sums the slot, in record order
                 double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
                 for (int q = k; q < k + run; ++q) {
@@ -393,8 +402,8 @@ __global__ void __launch_bounds__(NT)
                 }
                 s_J[p][o11] = a0;
                 s_J[p][o12] = a1;
-                s_J[p][kQ<NT> + o11] = a2;
-                s_J[p][kQ<NT> + o12] = a3;
+                s_J[p][kQ<NS> + o11] = a2;
+                s_J[p][kQ<NS> + o12] = a3;
             }
         }
         if (P && rowt) {
@@ -403,7 +412,7 @@ __global__ void __launch_bounds__(NT)
         }
         if constexpr (WITH_J) {
             lds_barrier();
-            write_jrows<NT>(c, s_J[p], J + (size_t)s * (size_t)g.nnz_j);
+            write_jrows<NT, NS>(c, s_J[p], J + (size_t)s * (size_t)g.nnz_j);
         }
     };
     pipelined_states<In, ONE>(sb, se, first, load, proc);
@@ -418,8 +427,10 @@ __global__ void __launch_bounds__(NT)
 // and writes the four real parts in place into J (Section IV.B.2).
 // U = e^{j theta} and V = v U are formed on the fly from (vm, va); a row's
 // own V_i and U_i reach the other threads of the row through LDS.
+// The single-state instantiation is held to 6 waves per SIMD (<= 80 VGPRs),
+// so a 100k-bus grid's workgroups are all resident at once.
 template <int NT, bool WITH_J, bool ONE>
-__global__ void __launch_bounds__(NT)
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? 6 : 1, 8)))
     k_ybus(DevGrid g, int nstate, int spb, int nchunk, bool state_major, const double *__restrict__ vm, const double *__restrict__ va,
            double *__restrict__ P, double *__restrict__ Q, double *__restrict__ J) {
     constexpr int NBUF = ONE ? 1 : 2;
@@ -427,21 +438,21 @@ __global__ void __launch_bounds__(NT)
     __shared__ double s_vu[NBUF][4][NT];  // per row: V_i, U_i (re, im)
     __shared__ __align__(16) double s_J[NBUF][WITH_J ? kJStage<NT> : 2];
 
-    const int W = g.ntiles * nchunk;
+    const int W = g.nytiles * nchunk;
     const int w = work_index(gridDim.x);
     if (w >= W) return;
-    const int t = state_major ? w % g.ntiles : w / nchunk;
-    const int sb = (state_major ? w / g.ntiles : w - t * nchunk) * spb;
+    const int t = state_major ? w % g.nytiles : w / nchunk;
+    const int sb = (state_major ? w / g.nytiles : w - t * nchunk) * spb;
     const int se = min(nstate, sb + spb);
     const int k = threadIdx.x;
     const size_t lane = (size_t)t * NT + k;
     const int j = g.ylane_j[lane];
     const int2 pk = g.ylane_pk[lane];
     const double2 yl = g.ylane_y[lane];
-    const Tile c = tile_of(g, t);
+    const Tile c = g.ytiles[t];
     const size_t nb = (size_t)g.nb;
 
-    if (c.n > NT) {
+    if (c.ns > NT) {
         // ---- one long row: pass 1 sums I_i in chunks (thread 0, in slot order), pass 2 writes J.
         const int i = c.r0;
         const int d = c.ns;
@@ -582,7 +593,7 @@ __global__ void __launch_bounds__(NT)
         }
         if constexpr (WITH_J) {
             lds_barrier();
-            write_jrows<NT>(c, s_J[p], J + (size_t)s * (size_t)g.nnz_j);
+            write_jrows<NT, NT>(c, s_J[p], J + (size_t)s * (size_t)g.nnz_j);
         }
     };
     pipelined_states<In, ONE>(sb, se, first, load, proc);
@@ -636,7 +647,7 @@ __global__ void __launch_bounds__(NT)
     const int k = threadIdx.x;
     const size_t lane = (size_t)t * NT + k;
     const int j = g.lane_j[lane];
-    const int rowl = lo16(g.lane_pk[lane].y);
+    const int rowl = ew_row(g.lane_pk[lane]);
     const double2 gb = g.lane_gb[lane], grb = g.lane_grbr[lane];
     const Tile c = tile_of(g, t);
     const size_t nb = (size_t)g.nb;
@@ -654,7 +665,7 @@ __global__ void __launch_bounds__(NT)
         return x;
     };
 
-    if (c.n > NT) {
+    if (c.ne > NT) {
         const int i = c.r0;
         const double dA = g.dA[i], dC = g.dC[i];
         for (int s = sb; s < se; ++s) {
@@ -822,7 +833,7 @@ __global__ void k_lane_fill(DevLaneFill f, bool ew) {
         f.lane_gb[l] = e >= 0 ? make_double2(f.G[e], f.B[e]) : make_double2(0.0, 0.0);
         f.lane_grbr[l] = e >= 0 ? make_double2(f.Gr[e], f.Br[e]) : make_double2(0.0, 0.0);
     } else {
-        if (l < f.nlanes) {
+        if (l < f.nylanes) {
             const int q = f.ylane_slot[l];
             f.ylane_y[l] = q >= 0 ? make_double2(f.yre[q], f.yim[q]) : make_double2(0.0, 0.0);
         }
@@ -837,7 +848,8 @@ template <int NT, bool ONE>
 hipError_t launch_nt(const DevGrid &g, const Launch &L, hipStream_t st) {
     const int spb = L.states_per_block;
     const int nchunk = (L.nstate + spb - 1) / spb;
-    const int64_t work = (int64_t)g.ntiles * nchunk;
+    const bool yb = L.kind == K_YB_S || L.kind == K_YB_SJ;
+    const int64_t work = (int64_t)(yb ? g.nytiles : g.ntiles) * nchunk;
     const int64_t blocks = (work + kXcds - 1) / kXcds * kXcds;
     if (blocks > INT32_MAX) return hipErrorInvalidConfiguration;
     const dim3 grid((unsigned)blocks), block(NT);
@@ -971,7 +983,7 @@ hipError_t launch_setup_items(const DevSetup &s, hipStream_t stream) {
 }
 
 hipError_t launch_lane_fill(const DevLaneFill &f, bool ew, hipStream_t stream) {
-    const int64_t n = ew ? f.nlanes : std::max<int64_t>(f.nlanes, (int64_t)f.nb + 1);
+    const int64_t n = ew ? f.nlanes : std::max<int64_t>(f.nylanes, (int64_t)f.nb + 1);
     if (n == 0) return hipSuccess;
     const int64_t blocks = (n + 255) / 256;
     hipLaunchKernelGGL(k_lane_fill, dim3((unsigned)blocks), dim3(256), 0, stream, f, ew);

@@ -25,8 +25,17 @@ PF_ORDER_AUTO, PF_ORDER_TILE_MAJOR, PF_ORDER_STATE_MAJOR = 0, 1, 2
 EXPORTS = (
     "pf_build_pattern", "pf_grid_free", "pf_grid_sizes", "pf_pattern_sizes", "pf_grid_offsets",
     "pf_pattern_export", "pf_ybus", "pf_injections_elementwise", "pf_injections_ybus", "pf_jacobian_values",
-    "pf_injections_vjp", "pf_set_schedule", "pf_get_schedule", "pf_last_error", "pf_version",
+    "pf_injections_vjp", "pf_set_schedule", "pf_get_schedule", "pf_graph_create", "pf_graph_launch",
+    "pf_graph_free", "pf_last_error", "pf_version",
 )
+PF_OP_INJECTIONS, PF_OP_JACOBIAN, PF_OP_VJP = 0, 1, 2
+
+
+class PfOp(C.Structure):
+    """``pf_op`` of include/pf.h."""
+    _fields_ = [("op", C.c_int32), ("method", C.c_int32), ("nstate", C.c_int32),
+                ("vm", C.c_void_p), ("va", C.c_void_p), ("lam_p", C.c_void_p), ("lam_q", C.c_void_p),
+                ("out_a", C.c_void_p), ("out_b", C.c_void_p), ("jval", C.c_void_p)]
 
 
 class PFError(RuntimeError):
@@ -61,13 +70,17 @@ def lib() -> C.CDLL:
         L.pf_jacobian_values.argtypes = [P, i32, i32, P, P, P, P, P, P]
         L.pf_injections_vjp.argtypes = [P, i32, P, P, P, P, P, P, P]
         L.pf_set_schedule.argtypes = [P, i32, i32, i32]
+        L.pf_graph_create.argtypes = [P, P, i32, C.POINTER(P)]
+        L.pf_graph_launch.argtypes = [P, P]
+        L.pf_graph_free.argtypes = [P]
+        L.pf_graph_free.restype = None
         L.pf_get_schedule.argtypes = [P, P, P, P, P]
         L.pf_last_error.restype = C.c_char_p
         L.pf_last_error.argtypes = []
         L.pf_version.restype = C.c_char_p
         L.pf_version.argtypes = []
         for name in EXPORTS:
-            if name not in ("pf_grid_free", "pf_last_error", "pf_version"):
+            if name not in ("pf_grid_free", "pf_graph_free", "pf_last_error", "pf_version"):
                 getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -225,3 +238,50 @@ def pf_injections_vjp(grid: Grid, vm, va, lam_p, lam_q, g_vm, g_va, stream=None)
 
 def pf_version() -> str:
     return lib().pf_version().decode()
+
+
+class Graph:
+    """Owner of a ``pf_graph`` (pf_graph_create / pf_graph_launch / pf_graph_free).
+
+    ``ops`` is a sequence of dicts with keys ``op`` (PF_OP_*), ``method``,
+    ``vm``, ``va`` and, as the op needs them, ``lam_p``, ``lam_q``,
+    ``out_a``, ``out_b``, ``jval`` (float64 CUDA tensors; see include/pf.h).
+    The graph keeps references to the tensors and to the grid so that they
+    outlive it.
+    """
+
+    def __init__(self, grid: Grid, ops):
+        arr = (PfOp * len(ops))()
+        keep = [grid]
+        for k, o in enumerate(ops):
+            vm = o["vm"]
+            ns = _nstate(vm, grid.nb)
+            shp = tuple(vm.shape)
+            jshp = (grid.nnz_j,) if vm.dim() == 1 else (ns, grid.nnz_j)
+            arr[k].op = int(o["op"])
+            arr[k].method = int(o.get("method", PF_METHOD_ELEMENTWISE))
+            arr[k].nstate = ns
+            arr[k].vm = _dev(vm, shp, "vm")
+            arr[k].va = _dev(o["va"], shp, "va")
+            for name in ("lam_p", "lam_q", "out_a", "out_b"):
+                setattr(arr[k], name, _dev(o.get(name), shp, name))
+            arr[k].jval = _dev(o.get("jval"), jshp, "jval")
+            keep += [v for v in o.values() if not isinstance(v, int)]
+        self._h = C.c_void_p()
+        check(lib().pf_graph_create(grid.handle, arr, len(ops), C.byref(self._h)))
+        self._keep = keep
+
+    def launch(self, stream=None):
+        check(lib().pf_graph_launch(self._h, _stream(stream)))
+
+    def close(self):
+        if self._h and self._h.value:
+            lib().pf_graph_free(self._h)
+            self._h = C.c_void_p()
+        self._keep = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -191,6 +191,20 @@ def test_eval_on_host_only_handle_is_state_error():
     assert L.pf_injections_elementwise(None, 1, None, None, None, None, None) == pf.PF_EINVAL
 
 
+def test_graph_create_argument_checks():
+    G = pf.Grid.from_grid(_grids.random_small(6, 8, 5), host_only=True)
+    L = pf.lib()
+    out = C.c_void_p()
+    ops = (pf.PfOp * 1)()
+    assert L.pf_graph_create(G.handle, ops, 1, C.byref(out)) == pf.PF_ESTATE
+    assert out.value is None
+    assert L.pf_graph_create(None, ops, 1, C.byref(out)) == pf.PF_EINVAL
+    assert L.pf_graph_create(G.handle, ops, 0, C.byref(out)) == pf.PF_EINVAL
+    assert L.pf_graph_create(G.handle, ops, 1, None) == pf.PF_EINVAL
+    assert L.pf_graph_launch(None, None) == pf.PF_EINVAL
+    L.pf_graph_free(None)  # no-op
+
+
 def test_schedule_choices():
     G = pf.Grid.from_grid(gridgen.config0(), host_only=True)
     for cap in (64, 128, 256, 512):

@@ -158,6 +158,70 @@ def test_determinism_across_runs_and_schedules():
                     assert np.array_equal(ref[k], other[k]), (k, tile, spb, order)
 
 
+def test_graph_replays_match_eager_calls():
+    """A recorded [injections, Jacobian (both methods), VJP] sequence, replayed
+    several times with eager work and input changes in between; every replay
+    equals the eager calls bit for bit."""
+    import torch
+    g = _grids.random_small(700, 1000, 41, parallel=6, isolated=3)
+    rng = np.random.default_rng(5)
+    ns = 3
+    G = pf.Grid.from_grid(g)
+    pf.pf_ybus(G)
+    dev = lambda a: to_dev(a)
+    vm = dev(rng.uniform(0.9, 1.1, (ns, g.nb)))
+    va = dev(rng.normal(0, 0.3, (ns, g.nb)))
+    lp, lq = dev(rng.normal(size=(ns, g.nb))), dev(rng.normal(size=(ns, g.nb)))
+    z = lambda *sh: torch.zeros(*sh, dtype=torch.float64, device="cuda:0")
+    out = {k: z(ns, g.nb) for k in ("p", "q", "p2", "q2", "p3", "q3", "gvm", "gva")}
+    j_ew, j_yb = z(ns, G.nnz_j), z(ns, G.nnz_j)
+    ops = [
+        dict(op=pf.PF_OP_INJECTIONS, method=pf.PF_METHOD_ELEMENTWISE, vm=vm, va=va, out_a=out["p"], out_b=out["q"]),
+        dict(op=pf.PF_OP_JACOBIAN, method=pf.PF_METHOD_ELEMENTWISE, vm=vm, va=va, out_a=out["p2"], out_b=out["q2"],
+             jval=j_ew),
+        dict(op=pf.PF_OP_JACOBIAN, method=pf.PF_METHOD_YBUS, vm=vm, va=va, out_a=out["p3"], out_b=out["q3"], jval=j_yb),
+        dict(op=pf.PF_OP_VJP, vm=vm, va=va, lam_p=lp, lam_q=lq, out_a=out["gvm"], out_b=out["gva"]),
+    ]
+    gr = pf.Graph(G, ops)
+
+    def eager():
+        e = {k: z(ns, g.nb) for k in out}
+        je, jy = z(ns, G.nnz_j), z(ns, G.nnz_j)
+        pf.pf_injections_elementwise(G, vm, va, e["p"], e["q"])
+        pf.pf_jacobian_values(G, pf.PF_METHOD_ELEMENTWISE, vm, va, e["p2"], e["q2"], je)
+        pf.pf_jacobian_values(G, pf.PF_METHOD_YBUS, vm, va, e["p3"], e["q3"], jy)
+        pf.pf_injections_vjp(G, vm, va, lp, lq, e["gvm"], e["gva"])
+        torch.cuda.synchronize()
+        return {k: v.cpu().numpy() for k, v in e.items()}, je.cpu().numpy(), jy.cpu().numpy()
+
+    for rep in range(4):
+        for t in list(out.values()) + [j_ew, j_yb]:
+            t.fill_(float("nan"))
+        gr.launch()
+        torch.cuda.synchronize()
+        want, je, jy = eager()
+        for k in out:
+            assert np.array_equal(out[k].cpu().numpy(), want[k]), (rep, k)
+        assert np.array_equal(j_ew.cpu().numpy(), je), rep
+        assert np.array_equal(j_yb.cpu().numpy(), jy), rep
+        vm.mul_(1.0 + 0.01 * (rep + 1))  # the next replay reads the new inputs
+        va.add_(0.02)
+    # within tolerance of the oracle too (last inputs, state 0)
+    ores = oracle_all(g, vm[0].cpu().numpy(), va[0].cpu().numpy())
+    gr.launch()
+    torch.cuda.synchronize()
+    assert rel_err(j_ew[0].cpu().numpy(), ores["j_ew"], ores["scale"]) <= TOL
+    # a schedule change invalidates the recording
+    G.set_schedule(128, 0)
+    with pytest.raises(pf.PFError) as e:
+        gr.launch()
+    assert e.value.code == pf.PF_ESTATE
+    gr.close()
+    with pytest.raises(pf.PFError) as e:  # Ybus op on a handle without pf_ybus
+        pf.Graph(pf.Grid.from_grid(g), ops[2:3])
+    assert e.value.code == pf.PF_ESTATE
+
+
 def test_ybus_required_before_ybus_calls():
     import torch
     G = pf.Grid.from_grid(gridgen.config0())
