@@ -129,6 +129,7 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="only the headline measurement")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-tune", action="store_true", help="keep the automatic schedules (skip the autotuner)")
     ap.add_argument("--only", default="", help="comma list of side measurements to run")
     ap.add_argument("--probe", action="store_true",
                     help="counter-run workload: headline launches, then one copy of known size; no timing")
@@ -148,7 +149,9 @@ def main():
 
     import torch
 
-    from paper_2302_10736_amd import gridgen, pf
+    import tempfile
+
+    from paper_2302_10736_amd import autotune, gridgen, pf
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
@@ -171,6 +174,15 @@ def main():
             j=torch.empty(1, G.nnz_j, dtype=torch.float64, device=dev)))
     G0 = reps[0]["G"]
     nnz_y, nnz_j = G0.nnz_y, G0.nnz_j
+    # schedules come from the autotuner, tuned afresh (a private cache file)
+    tune_cache = autotune.ScheduleCache(os.path.join(tempfile.mkdtemp(prefix="pf_bench_"), "schedules.json"))
+    tuned = {}
+    if not args.no_tune and not args.probe:
+        res = autotune.tune(G0, "jacobian_ew", 1, cache=tune_cache, save=False)
+        tuned["headline"] = res
+        for d in reps[1:]:
+            d["G"].set_schedule(*res["schedule"])
+        log(f"tuned headline schedule {res['schedule']} ({res['us']:.2f} us in the tuner)")
     tile, spb, order, ntiles = G0.schedule()
     log(f"grid nb={g.nb} nl={g.nl} nnzY={nnz_y} nnzJ={nnz_j} tiles={ntiles} replicas={R}")
 
@@ -350,12 +362,18 @@ def main():
         def b_sj(k, st):
             pf.pf_jacobian_values(G2, pf.PF_METHOD_ELEMENTWISE, vm2d, va2d, p2, q2, j2, stream=st)
         steps = max(20, K // 40)
+        ev_auto, _ = timed(b_sj, max(10, K // 100), 3, period=10)
+        auto_sched = G2.schedule()
+        if not args.no_tune:
+            tuned["batched"] = autotune.tune(G2, "jacobian_ew", B, cache=tune_cache, save=False)
         ev, wall = timed(b_sj, steps, 5, period=10)
         bb = algorithmic_bytes(g2.nb, g2.nl, G2.nnz_y, B)
         extra["batched_20k_x512"] = {"state_evals_per_s": B * steps / wall, "avg_launch_us": ev / steps * 1e6,
                                      "achieved_GBs": bb / (ev / steps) / 1e9,
                                      "frac_hbm": bb / (ev / steps) / 1e9 / HBM_PEAK_GBS,
-                                     "algorithmic_bytes": bb, "schedule": G2.schedule()}
+                                     "algorithmic_bytes": bb, "schedule": G2.schedule(),
+                                     "automatic_schedule": auto_sched,
+                                     "automatic_schedule_us": ev_auto / max(10, K // 100) * 1e6}
         log(f"batched: {ev / steps * 1e6:.1f} us/launch")
         del vm2d, va2d, p2, q2, j2, G2
         torch.cuda.empty_cache()
@@ -374,12 +392,15 @@ def main():
         def m_sj(k, st):
             pf.pf_jacobian_values(G3, pf.PF_METHOD_ELEMENTWISE, vm3d, va3d, p3, q3, j3, stream=st)
         steps = max(20, K // 40)
+        if not args.no_tune:
+            cands = [(t, s, o) for t in (128, 256, 512) for s in (0, 1, 4) for o in (1, 2)]
+            tuned["multigrid"] = autotune.tune(G3, "jacobian_ew", 4, cache=tune_cache, cands=cands, save=False)
         ev, wall = timed(m_sj, steps, 5, period=10)
         mb = algorithmic_bytes(big.nb, big.nl, G3.nnz_y, 4)
         extra["multigrid_64x4"] = {"grid_state_evals_per_s": 256 * steps / wall, "avg_launch_us": ev / steps * 1e6,
                                    "achieved_GBs": mb / (ev / steps) / 1e9,
                                    "frac_hbm": mb / (ev / steps) / 1e9 / HBM_PEAK_GBS, "algorithmic_bytes": mb,
-                                   "buses": big.nb, "branches": big.nl}
+                                   "buses": big.nb, "branches": big.nl, "schedule": G3.schedule()}
         log(f"multigrid: {ev / steps * 1e6:.1f} us/launch")
         del vm3d, va3d, p3, q3, j3, G3
         torch.cuda.empty_cache()
@@ -407,6 +428,9 @@ def main():
                                      "forward_GBs": fb / (ev_f / steps) / 1e9, "vjp_GBs": bb / (ev_b / steps) / 1e9}
         log(f"adjoint: fwd {ev_f / steps * 1e6:.1f} us, vjp {ev_b / steps * 1e6:.1f} us")
 
+    if tuned:
+        extra["autotuner"] = {k: {"schedule": v["schedule"], "us": v["us"], "tried": v["tried"]}
+                              for k, v in tuned.items()}
     if extra:
         out["extra"] = extra
 
