@@ -310,6 +310,18 @@ def main():
                             "ew_speedup_vs_ybus": (ev / K) / avg_launch}
         log(f"Ybus S+J: {ev / K * 1e6:.2f} us/launch")
 
+    if want("two_phase"):
+        # the paper's two-step structure: branch evaluation into scratch, then the bus reduction
+        def tp_sj(k, st):
+            d = reps[k % R]
+            pf.pf_jacobian_values(d["G"], pf.PF_METHOD_ELEMENTWISE_TWO_PHASE, d["vm"], d["va"], d["p"], d["q"], d["j"],
+                                  stream=st)
+        ev, wall = timed(tp_sj, K, W)
+        extra["ew_two_phase_sj"] = {"evals_per_s": K / wall, "avg_eval_us": ev / K * 1e6,
+                                    "achieved_GBs": abytes / (ev / K) / 1e9, "launches_per_eval": 2,
+                                    "fused_speedup": (ev / K) / avg_launch}
+        log(f"two-phase S+J: {ev / K * 1e6:.2f} us/eval")
+
     if want("copy"):
         # a plain device copy moving the same number of bytes (half read, half written)
         n = abytes // 16

@@ -81,7 +81,14 @@ typedef enum pf_status {
 
 typedef enum pf_method {
     PF_METHOD_ELEMENTWISE = 0, /* eqs. (5)-(7): per branch end, then reduction */
-    PF_METHOD_YBUS = 1         /* eqs. (1), (3), (4): complex CSR SpMV, two-pass Jacobian */
+    PF_METHOD_YBUS = 1,        /* eqs. (1), (3), (4): complex CSR SpMV, two-pass Jacobian */
+    /* Element-wise in the paper's two steps (Section IV.C): every branch
+     * evaluated once (both ends) into scratch, then a separate per-bus
+     * reduction into P, Q and J.  A baseline for the fused method above;
+     * pf_jacobian_values only.  Its first call on a handle allocates the
+     * scratch (10 doubles per record, kept until pf_grid_free); states run
+     * one after another, two launches each. */
+    PF_METHOD_ELEMENTWISE_TWO_PHASE = 2
 } pf_method;
 
 enum {

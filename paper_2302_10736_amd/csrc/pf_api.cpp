@@ -64,6 +64,8 @@ struct pf_grid {
     std::vector<pf::TileDesc> tiles, ytiles;  // element-wise and Ybus work tiles
     int32_t num_cus = 0;
     pf::DevLaneFill lanes{};  // gather sources and targets of the lane values
+    pf::DevTwoPhase tp{};     // two-phase element-wise tables (scratch allocated on first use)
+    void *dscr = nullptr;
 
     void *dmem = nullptr;   // grid data
     void *dtile = nullptr;  // schedule
@@ -509,6 +511,9 @@ int pf_build_pattern(int32_t nb, int32_t nl, const int32_t *fbus, const int32_t 
         size_t o_r = ar.take<double>(nl), o_x = ar.take<double>(nl), o_b = ar.take<double>(nl),
                o_tap = ar.take<double>(nl), o_sh = ar.take<double>(nl);
         size_t o_gs = ar.take<double>(nb), o_bs = ar.take<double>(nb);
+        // two-phase tables
+        size_t o_bf = ar.take<int32_t>(nl), o_bt = ar.take<int32_t>(nl), o_brec = ar.take<int32_t>(2 * (size_t)nl),
+               o_jpq = ar.take<int2>(nb);
         e = hipMalloc(&g->dmem, ar.off);
         if (e != hipSuccess) {
             g->dmem = nullptr;
@@ -545,6 +550,21 @@ int pf_build_pattern(int32_t nb, int32_t nl, const int32_t *fbus, const int32_t 
         chk(up(o_sh, shift, nl * 8));
         chk(up(o_gs, gsp, nb * 8));
         chk(up(o_bs, bsp, nb * 8));
+        {
+            std::vector<int32_t> brec(2 * (size_t)nl, 0);
+            for (int64_t e2 = 0; e2 < ni; ++e2)
+                if (g->item_br[e2] >= 0) brec[g->item_br[e2]] = (int32_t)e2;
+            std::vector<int32_t> jpq(2 * (size_t)nb);
+            for (int32_t k = 0; k < ngrids; ++k)
+                for (int32_t i = g->bus_off[k]; i < g->bus_off[k + 1]; ++i) {
+                    jpq[2 * (size_t)i] = (int32_t)(2 * g->y_off[k] + 2 * (int64_t)g->yrow[i]);
+                    jpq[2 * (size_t)i + 1] = (int32_t)(2 * g->y_off[k + 1] + 2 * (int64_t)g->yrow[i]);
+                }
+            chk(up(o_bf, gf.data(), (size_t)nl * 4));
+            chk(up(o_bt, gt.data(), (size_t)nl * 4));
+            chk(up(o_brec, brec.data(), 2 * (size_t)nl * 4));
+            chk(up(o_jpq, jpq.data(), (size_t)nb * 8));
+        }
         if (ee != hipSuccess) {
             int rc = hip_fail(ee, "hipMemcpy(grid)");
             pf_grid_free(g);
@@ -596,6 +616,25 @@ int pf_build_pattern(int32_t nb, int32_t nl, const int32_t *fbus, const int32_t 
         s.yre = F64(o_yre);
         s.yim = F64(o_yim);
         g->setup = s;
+        pf::DevTwoPhase &tp = g->tp;
+        tp.nb = nb;
+        tp.nl = nl;
+        tp.nrec = ni;
+        tp.br_from = I32(o_bf);
+        tp.br_to = I32(o_bt);
+        tp.br_rec = I32(o_brec);
+        tp.r = s.r;
+        tp.x = s.x;
+        tp.b = s.b;
+        tp.tap = s.tap;
+        tp.shift = s.shift;
+        tp.gs = s.gs;
+        tp.bs = s.bs;
+        tp.irow = d.irow;
+        tp.item_br = s.item_br;
+        tp.slot = d.slot;
+        tp.yrow = d.yrow;
+        tp.jpq = reinterpret_cast<const int2 *>(base + o_jpq);
         e = pf::launch_setup_items(s, nullptr);
         if (e == hipSuccess) e = hipDeviceSynchronize();
         if (e != hipSuccess) {
@@ -620,6 +659,7 @@ void pf_grid_free(pf_grid *g) {
     if (!g) return;
     if (g->dmem) (void)hipFree(g->dmem);
     if (g->dtile) (void)hipFree(g->dtile);
+    if (g->dscr) (void)hipFree(g->dscr);
     delete g;
 }
 
@@ -742,6 +782,22 @@ int auto_states_per_block(const pf_grid *g, int kind, int32_t nstate) {
     return (int)((nstate + chunks - 1) / chunks);
 }
 
+// Scratch of the two-phase element-wise method: ten values per record,
+// allocated on the first call that needs it.
+int ensure_two_phase_scratch(const pf_grid *g) {
+    pf_grid *mg = const_cast<pf_grid *>(g);
+    if (mg->dscr) return PF_OK;
+    const size_t bytes = 10 * (size_t)g->nitems * sizeof(double);
+    hipError_t e = hipMalloc(&mg->dscr, bytes);
+    if (e != hipSuccess) {
+        mg->dscr = nullptr;
+        return e == hipErrorOutOfMemory ? fail(PF_ENOMEM, "device allocation of the two-phase scratch failed")
+                                        : hip_fail(e, "hipMalloc(two-phase scratch)");
+    }
+    mg->tp.scr = static_cast<double *>(mg->dscr);
+    return PF_OK;
+}
+
 int run(const pf_grid *g, pf::Launch &L, void *stream) {
     L.tile_items = g->tile_items;
     L.has_parallel = g->has_parallel;
@@ -820,12 +876,27 @@ int pf_jacobian_values(const pf_grid *g, int32_t method, int32_t nstate, const d
     g_err.clear();
     int st = check_eval(g, nstate);
     if (st) return st;
-    if (method != PF_METHOD_ELEMENTWISE && method != PF_METHOD_YBUS) return fail(PF_EINVAL, "unknown method");
+    if (method != PF_METHOD_ELEMENTWISE && method != PF_METHOD_YBUS && method != PF_METHOD_ELEMENTWISE_TWO_PHASE)
+        return fail(PF_EINVAL, "unknown method");
     if (method == PF_METHOD_YBUS && !g->ybus_valid)
         return fail(PF_ESTATE, "pf_ybus has not been called on this handle");
     if (nstate > 0 && (!vm || !va || !jval)) return fail(PF_EINVAL, "NULL state or Jacobian pointer");
     if ((p == nullptr) != (q == nullptr)) return fail(PF_EINVAL, "p and q must both be given or both be NULL");
     if (reinterpret_cast<uintptr_t>(jval) % 16) return fail(PF_EINVAL, "jval must be 16-byte aligned");
+    if (method == PF_METHOD_ELEMENTWISE_TWO_PHASE) {
+        if (nstate == 0) return PF_OK;
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+        if (cur != g->device) return fail(PF_EINVAL, "current HIP device differs from the handle's device");
+        st = ensure_two_phase_scratch(g);
+        if (st) return st;
+        pf::DevTwoPhase d = g->tp;
+        d.ydslot = g->lanes.ydslot;
+        e = pf::launch_two_phase(d, nstate, 4 * g->nnz_y, vm, va, p, q, jval, static_cast<hipStream_t>(stream));
+        if (e != hipSuccess) return hip_fail(e, "kernel launch");
+        return PF_OK;
+    }
     pf::Launch L{};
     L.kind = method == PF_METHOD_ELEMENTWISE ? pf::K_EW_SJ : pf::K_YB_SJ;
     L.nstate = nstate;
@@ -913,8 +984,13 @@ int pf_graph_create(const pf_grid *g, const pf_op *ops, int32_t nops, pf_graph *
     if (cur != g->device) return fail(PF_EINVAL, "current HIP device differs from the handle's device");
     // Resolve every launch shape before recording, so that nothing but
     // kernel launches happens while the stream is captured.
-    for (int32_t k = 0; k < nops; ++k)
+    for (int32_t k = 0; k < nops; ++k) {
         if (ops[k].nstate > 0) auto_states_per_block(g, op_kind(ops[k]), ops[k].nstate);
+        if (ops[k].op == PF_OP_JACOBIAN && ops[k].method == PF_METHOD_ELEMENTWISE_TWO_PHASE) {
+            const int st0 = ensure_two_phase_scratch(g);
+            if (st0) return st0;
+        }
+    }
     hipStream_t s = nullptr;
     e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
     if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");

@@ -101,6 +101,22 @@ struct DevSetup {
     double *yre, *yim;                      // [nnz_y] outputs
 };
 
+// Two-phase element-wise evaluation, the paper's own structure (Section
+// IV.C): phase 1 evaluates every branch (both ends) and writes each end's
+// P, Q and eight partials to scratch at the end's record position; phase 2
+// sums each bus row in record order into P, Q and the row's J entries.
+struct DevTwoPhase {
+    int32_t nb, nl;
+    int64_t nrec;                           // records: the scratch stride
+    const int32_t *br_from, *br_to;         // [nl] global bus numbers
+    const int32_t *br_rec;                  // [2 nl] record of the from end, of the to end
+    const double *r, *x, *b, *tap, *shift;  // [nl]
+    const double *gs, *bs;                  // [nb]
+    const int32_t *irow, *item_br, *slot, *yrow, *ydslot;
+    const int2 *jpq;                        // [nb] offsets of row i's P and Q parts in one state's J
+    double *scr;                            // [10][nrec]
+};
+
 enum Kind { K_EW_S = 0, K_EW_SJ = 1, K_YB_S = 2, K_YB_SJ = 3, K_EW_VJP = 4 };
 
 struct Launch {
@@ -123,5 +139,8 @@ hipError_t launch_setup_items(const DevSetup &s, hipStream_t stream);
 // slot arrays.
 hipError_t launch_lane_fill(const DevLaneFill &f, bool ew, hipStream_t stream);
 hipError_t launch_ybus_assemble(const DevSetup &s, hipStream_t stream);
+// States [0, nstate) one after another, two launches each.
+hipError_t launch_two_phase(const DevTwoPhase &d, int32_t nstate, int64_t nnz_j, const double *vm, const double *va,
+                            double *p, double *q, double *jval, hipStream_t stream);
 
 }  // namespace pf

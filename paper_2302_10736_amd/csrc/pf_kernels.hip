@@ -823,6 +823,106 @@ __global__ void k_ybus_assemble(DevSetup s) {
     s.yim[p] = im;
 }
 
+// ===================================================================
+// Two-phase element-wise evaluation (see DevTwoPhase).  Per branch end at
+// bus i with remote bus j, with the series admittance g_s + j b_s = 1/(r + jx),
+// tap m and shift phi on the from side, eqs. (5)-(6) in real form read
+//   d = theta_i - theta_j - phi_e,  w = v_i v_j,
+//   alpha = G cos d + B sin d,  beta = G sin d - B cos d,  G = g_s/m, B = b_s/m,
+//   P = v_i^2 A - w alpha,  Q = -v_i^2 C - w beta,
+// with A = g_s/m^2, C = (b/2 + b_s)/m^2, phi_e = phi at the from end and
+// A = g_s, C = b/2 + b_s, phi_e = -phi at the to end; the partials follow from
+// d alpha/d d = -beta and d beta/d d = alpha.
+__device__ __forceinline__ void tp_end(double *sc, int64_t stride, int e, double vi, double vj, double d, double A,
+                                       double C, double G, double B) {
+    double sn, cs;
+    sincos_dev(d, &sn, &cs);
+    const double al = fma(G, cs, B * sn), be = fma(G, sn, -(B * cs));
+    const double w = vi * vj;
+    sc[0 * stride + e] = fma(vi * vi, A, -(w * al));          // P_e
+    sc[1 * stride + e] = fma(-(vi * vi), C, -(w * be));       // Q_e
+    sc[2 * stride + e] = w * be;                              // dP/dtheta_i
+    sc[3 * stride + e] = fma(2.0 * vi, A, -(vj * al));        // dP/dv_i
+    sc[4 * stride + e] = -(w * al);                           // dQ/dtheta_i
+    sc[5 * stride + e] = fma(-2.0 * vi, C, -(vj * be));       // dQ/dv_i
+    sc[6 * stride + e] = -(w * be);                           // dP/dtheta_j
+    sc[7 * stride + e] = -(vi * al);                          // dP/dv_j
+    sc[8 * stride + e] = w * al;                              // dQ/dtheta_j
+    sc[9 * stride + e] = -(vi * be);                          // dQ/dv_j
+}
+
+__global__ void k_tp_branch(DevTwoPhase d, const double *__restrict__ vm, const double *__restrict__ va) {
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= d.nl) return;
+    const int h = d.br_from[l], k = d.br_to[l];
+    const double r = d.r[l], x = d.x[l];
+    const double den = fma(r, r, x * x);
+    const double gsr = r / den, bsr = -x / den;
+    const double m = d.tap[l] == 0.0 ? 1.0 : d.tap[l];
+    const double bh = 0.5 * d.b[l], phi = d.shift[l];
+    const double vh = vm[h], th = va[h], vk = vm[k], tk = va[k];
+    const double G = gsr / m, B = bsr / m;
+    tp_end(d.scr, d.nrec, d.br_rec[2 * l], vh, vk, th - tk - phi, gsr / (m * m), (bh + bsr) / (m * m), G, B);
+    tp_end(d.scr, d.nrec, d.br_rec[2 * l + 1], vk, vh, tk - th + phi, gsr, bh + bsr, G, B);
+}
+
+__global__ void k_tp_reduce(DevTwoPhase d, const double *__restrict__ vm, double *__restrict__ P,
+                            double *__restrict__ Q, double *__restrict__ J) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= d.nb) return;
+    const int64_t st = d.nrec;
+    const double *sc = d.scr;
+    const double v = vm[i];
+    const int y0 = d.yrow[i], deg = d.yrow[i + 1] - y0;
+    const int64_t jp = d.jpq[i].x, jq = d.jpq[i].y;
+    double p = 0.0, q = 0.0, o0 = 0.0, o1 = 0.0, o2 = 0.0, o3 = 0.0;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int cur = -1;
+    auto flush = [&]() {
+        if (cur < 0) return;
+        J[jp + cur] = a0;
+        J[jp + deg + cur] = a1;
+        J[jq + cur] = a2;
+        J[jq + deg + cur] = a3;
+    };
+    for (int e = d.irow[i]; e < d.irow[i + 1]; ++e) {
+        if (d.item_br[e] < 0) {  // the bus shunt, at its sorted place
+            const double gg = d.gs[i], bb = d.bs[i];
+            p = fma(v * v, gg, p);
+            q = fma(-(v * v), bb, q);
+            o1 = fma(2.0 * v, gg, o1);
+            o3 = fma(-2.0 * v, bb, o3);
+            continue;
+        }
+        p += sc[0 * st + e];
+        q += sc[1 * st + e];
+        o0 += sc[2 * st + e];
+        o1 += sc[3 * st + e];
+        o2 += sc[4 * st + e];
+        o3 += sc[5 * st + e];
+        const int ls = d.slot[e] - y0;
+        if (ls != cur) {  // parallel branches share a slot and are adjacent
+            flush();
+            cur = ls;
+            a0 = a1 = a2 = a3 = 0.0;
+        }
+        a0 += sc[6 * st + e];
+        a1 += sc[7 * st + e];
+        a2 += sc[8 * st + e];
+        a3 += sc[9 * st + e];
+    }
+    flush();
+    const int dp = d.ydslot[i] - y0;
+    J[jp + dp] = o0;
+    J[jp + deg + dp] = o1;
+    J[jq + dp] = o2;
+    J[jq + deg + dp] = o3;
+    if (P) {
+        P[i] = p;
+        Q[i] = q;
+    }
+}
+
 // Lane values: copies of the record constants (element-wise) or Ybus values
 // in lane order; inert lanes get zeros.
 __global__ void k_lane_fill(DevLaneFill f, bool ew) {
@@ -988,6 +1088,20 @@ hipError_t launch_lane_fill(const DevLaneFill &f, bool ew, hipStream_t stream) {
     const int64_t blocks = (n + 255) / 256;
     hipLaunchKernelGGL(k_lane_fill, dim3((unsigned)blocks), dim3(256), 0, stream, f, ew);
     return hipGetLastError();
+}
+
+hipError_t launch_two_phase(const DevTwoPhase &d, int32_t nstate, int64_t nnz_j, const double *vm, const double *va,
+                            double *p, double *q, double *jval, hipStream_t stream) {
+    const unsigned gb = (unsigned)((d.nl + 255) / 256), gr = (unsigned)((d.nb + 255) / 256);
+    for (int32_t s = 0; s < nstate; ++s) {
+        const size_t so = (size_t)s * d.nb;
+        if (d.nl > 0) hipLaunchKernelGGL(k_tp_branch, dim3(gb), dim3(256), 0, stream, d, vm + so, va + so);
+        hipLaunchKernelGGL(k_tp_reduce, dim3(gr), dim3(256), 0, stream, d, vm + so, p ? p + so : nullptr,
+                           q ? q + so : nullptr, jval + (size_t)s * (size_t)nnz_j);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_ybus_assemble(const DevSetup &s, hipStream_t stream) {
