@@ -120,6 +120,71 @@ def algorithmic_bytes(nb, nl, nnz_y, nstate, with_j=True, method="ew", vjp=False
     return nstate * per_state + grid
 
 
+def size_sweep(torch, gridgen, pf, log):
+    """Device time of one evaluation (one state, warm, graph replays) by both
+    methods over grid sizes from 118 buses to five replicas of an 82k-bus
+    grid; per-bus times, the time-cost ratio (per-bus time over that of the
+    118-bus grid) and the Ybus / element-wise time ratio per size."""
+    dev = torch.device("cuda:0")
+    side = torch.cuda.Stream()
+
+    def gtime(fn, n=20, reps=10):
+        with torch.cuda.stream(side):
+            fn(side)
+        torch.cuda.synchronize()
+        gr = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(gr, stream=side):
+            for _ in range(n):
+                fn(side)
+        with torch.cuda.stream(side):
+            gr.replay()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(side):
+            e0.record(side)
+            for _ in range(reps):
+                gr.replay()
+            e1.record(side)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e3 / (n * reps)  # us
+
+    cases = [(nb, None) for nb in (118, 500, 2000, 10_000, 30_000, 82_000)] + [(82_000, k) for k in (2, 3, 4, 5)]
+    base82 = None
+    rows = []
+    for idx, (nb, reps_k) in enumerate(cases):
+        if reps_k is None:
+            g = gridgen.make_grid(nb, round(1.27 * nb), 0.15, cfg=5, grid=idx)
+            if nb == 82_000:
+                base82 = g
+            G = pf.Grid.from_grid(g)
+            ntot = nb
+        else:
+            big, bo, ro = gridgen.concat([base82] * reps_k)
+            G = pf.Grid.from_grid(big, bo, ro)
+            ntot = big.nb
+        pf.pf_ybus(G)
+        vm, va = gridgen.states(ntot, 1, cfg=5, grid=idx)
+        a, b = torch.as_tensor(vm, device=dev), torch.as_tensor(va, device=dev)
+        p, q = torch.empty_like(a), torch.empty_like(a)
+        j = torch.empty(1, G.nnz_j, dtype=torch.float64, device=dev)
+        t = {
+            "ew_s": gtime(lambda st: pf.pf_injections_elementwise(G, a, b, p, q, stream=st)),
+            "ew_sj": gtime(lambda st: pf.pf_jacobian_values(G, 0, a, b, p, q, j, stream=st)),
+            "ybus_s": gtime(lambda st: pf.pf_injections_ybus(G, a, b, p, q, stream=st)),
+            "ybus_sj": gtime(lambda st: pf.pf_jacobian_values(G, 1, a, b, p, q, j, stream=st)),
+        }
+        rows.append({"buses": ntot, "replicas_of_82k": reps_k, "us": t,
+                     "ns_per_bus": {k: 1e3 * v / ntot for k, v in t.items()},
+                     "ybus_over_ew": {"s": t["ybus_s"] / t["ew_s"], "sj": t["ybus_sj"] / t["ew_sj"]}})
+        log(f"{ntot:>8d} buses: " + ", ".join(f"{k} {v:.2f} us" for k, v in t.items()))
+        del G, a, b, p, q, j
+        torch.cuda.empty_cache()
+    ref = rows[0]["ns_per_bus"]
+    for r in rows:
+        r["time_cost_ratio_vs_118"] = {k: r["ns_per_bus"][k] / ref[k] for k in ref}
+    return {"sweep": "EW and Ybus, one state, warm, device time per evaluation", "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -130,6 +195,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-tune", action="store_true", help="keep the automatic schedules (skip the autotuner)")
+    ap.add_argument("--sweep", action="store_true",
+                    help="grid-size sweep instead of the benchmark: EW and Ybus per-bus times and time-cost ratios")
     ap.add_argument("--only", default="", help="comma list of side measurements to run")
     ap.add_argument("--probe", action="store_true",
                     help="counter-run workload: headline launches, then one copy of known size; no timing")
@@ -158,6 +225,9 @@ def main():
         sys.exit(1)
     dev = torch.device("cuda:0")
     log = lambda *a: print(*a, file=sys.stderr, flush=True)
+    if args.sweep:
+        print(json.dumps(size_sweep(torch, gridgen, pf, log)), flush=True)
+        return
 
     # ------------------------------------------------------------ workload
     g = gridgen.config1()
