@@ -41,6 +41,10 @@ def lib():
         L.orc_jac_ew.argtypes = [i32, i32] + [P] * 14
         L.orc_vjp.restype = None
         L.orc_vjp.argtypes = [i32] + [P] * 5
+        L.orc_branch_flows.restype = None
+        L.orc_branch_flows.argtypes = [i32] + [P] * 13
+        L.orc_branch_flow_jac.restype = None
+        L.orc_branch_flow_jac.argtypes = [i32] + [P] * 10
         _lib = L
     return _lib
 
@@ -145,3 +149,19 @@ def vjp(nb, pattern, jval, lam_p, lam_q):
     g = np.empty(2 * nb)
     lib().orc_vjp(nb, _p(jrow), _p(jcol), _p(_f64(jval)), _p(lam), _p(g))
     return g[nb:].copy(), g[:nb].copy()  # (g_vm, g_va)
+
+
+def branch_flows(g, vm, va):
+    """(pf, qf, pt, qt) per branch: S_hk and S_kh of eqs. (5)-(6)."""
+    vm, va = _f64(vm), _f64(va)
+    out = [np.empty(g.nl) for _ in range(4)]
+    lib().orc_branch_flows(g.nl, *map(_p, _branch(g)[:7]), _p(vm), _p(va), *map(_p, out))
+    return tuple(out)
+
+
+def branch_flow_jac(g, vm, va):
+    """[16, nl]: d(Pf, Qf, Pt, Qt) / d(theta_h, theta_k, v_h, v_k), four rows each."""
+    vm, va = _f64(vm), _f64(va)
+    jac = np.empty((16, g.nl))
+    lib().orc_branch_flow_jac(g.nl, *map(_p, _branch(g)[:7]), _p(vm), _p(va), _p(jac))
+    return jac

@@ -305,3 +305,52 @@ void orc_vjp(int32_t nb, const int32_t *jrow, const int32_t *jcol, const double 
     for (int32_t row = 0; row < 2 * nb; ++row)
         for (int32_t t = jrow[row]; t < jrow[row + 1]; ++t) g[jcol[t]] += jval[t] * lam[row];
 }
+
+/* Branch flows, eqs. (5)-(6): the power entering branch l at its h end,
+ * S_hk = pf + j qf, and at its k end, S_kh = pt + j qt (branch order). */
+void orc_branch_flows(int32_t nl, const int32_t *fbus, const int32_t *tbus, const double *r,
+                      const double *x, const double *b, const double *tap, const double *shift,
+                      const double *vm, const double *va, double *pf, double *qf, double *pt,
+                      double *qt)
+{
+    for (int32_t l = 0; l < nl; ++l) {
+        int32_t h = fbus[l], k = tbus[l];
+        double m = (tap[l] == 0.0) ? 1.0 : tap[l];
+        cplx yhk = 1.0 / (r[l] + I * x[l]);
+        cplx yh = I * (b[l] / 2.0), yk = I * (b[l] / 2.0);
+        double vh = vm[h], vk = vm[k];
+        double delta = va[h] - va[k] - shift[l];
+        cplx shk = vh * vh * conj(yh + yhk) / (m * m) - vh * vk * conj(yhk) / m * cexp(I * delta);
+        cplx skh = -vh * vk * conj(yhk) / m * cexp(-I * delta) + vk * vk * conj(yk + yhk);
+        pf[l] = creal(shk);
+        qf[l] = cimag(shk);
+        pt[l] = creal(skh);
+        qt[l] = cimag(skh);
+    }
+}
+
+/* The 16 partial derivatives of the branch flows, jac[16][nl]: row q of
+ * 4 q..4 q + 3 holds d(Pf, Qf, Pt, Qt)[q] / d(theta_h, theta_k, v_h, v_k). */
+void orc_branch_flow_jac(int32_t nl, const int32_t *fbus, const int32_t *tbus, const double *r,
+                         const double *x, const double *b, const double *tap, const double *shift,
+                         const double *vm, const double *va, double *jac)
+{
+    for (int32_t l = 0; l < nl; ++l) {
+        int32_t h = fbus[l], k = tbus[l];
+        double m = (tap[l] == 0.0) ? 1.0 : tap[l];
+        cplx yhk = 1.0 / (r[l] + I * x[l]);
+        cplx ysh = I * (b[l] / 2.0);
+        cplx ah = conj(ysh + yhk) / (m * m), ak = conj(ysh + yhk), c = conj(yhk) / m;
+        double vh = vm[h], vk = vm[k];
+        double d = va[h] - va[k] - shift[l];
+        cplx ef = cexp(I * d), et = cexp(-I * d);
+        cplx f[4] = {-I * vh * vk * c * ef, I * vh * vk * c * ef, 2.0 * vh * ah - vk * c * ef, -vh * c * ef};
+        cplx t[4] = {I * vh * vk * c * et, -I * vh * vk * c * et, -vk * c * et, 2.0 * vk * ak - vh * c * et};
+        for (int v = 0; v < 4; ++v) {
+            jac[(size_t)(0 + v) * nl + l] = creal(f[v]);
+            jac[(size_t)(4 + v) * nl + l] = cimag(f[v]);
+            jac[(size_t)(8 + v) * nl + l] = creal(t[v]);
+            jac[(size_t)(12 + v) * nl + l] = cimag(t[v]);
+        }
+    }
+}

@@ -391,3 +391,93 @@ def test_vjp_complex_step(seed):
             (ref_vm if which == 0 else ref_va)[k] = d
     assert rel_inf(gvm, ref_vm) <= 1e-13
     assert rel_inf(gva, ref_va) <= 1e-13
+
+
+# ------------------------------------------------------------- branch flows
+
+@pytest.mark.parametrize("flip", [False, True])
+@pytest.mark.parametrize("case", [
+    (0.01, 0.1, 0.02, 1.05, 0.05, (1.02, 0.98), (0.1, -0.05)),
+    (0.03, 0.2, 0.08, 0.95, -0.08, (0.97, 1.04), (-0.2, 0.15)),
+])
+def test_branch_flows_kirchhoff(case, flip):
+    r, x, b, tap, shift, vm, va = case
+    vm, va = np.array(vm), np.array(va)
+    S12, S21 = kirchhoff_two_bus(r, x, b, tap, shift, vm, va)
+    g = _grids.two_bus(r, x, b, tap, shift, flip=flip)
+    if flip:
+        vm, va = vm[::-1].copy(), va[::-1].copy()
+    pf_, qf, pt, qt = oracle.branch_flows(g, vm, va)
+    assert abs(pf_[0] + 1j * qf[0] - S12) <= 1e-14 * abs(S12)
+    assert abs(pt[0] + 1j * qt[0] - S21) <= 1e-14 * abs(S21)
+
+
+def flows_to_buses(g, flows, vm):
+    pf_, qf, pt, qt = flows
+    s = np.zeros(g.nb, complex)
+    np.add.at(s, g.fbus, pf_ + 1j * qf)
+    np.add.at(s, g.tbus, pt + 1j * qt)
+    return s + vm ** 2 * (g.gs - 1j * g.bs)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_branch_flows_sum_to_ybus_injections(seed):
+    g = _grids.random_small(60, 110, 100 + seed, parallel=5, isolated=2)
+    vm, va = _grids.random_state(g.nb, seed)
+    yb = oracle.ybus(g)
+    p, q = oracle.inject_ybus(yb, vm, va)  # the other method's code path
+    s = flows_to_buses(g, oracle.branch_flows(g, vm, va), vm)
+    assert np.max(np.abs(s - (p + 1j * q))) <= 1e-13 * term_scale(yb, vm)
+
+
+def test_branch_flows_lossless():
+    g = _grids.random_small(40, 70, 7, lossless=True)
+    g.b = np.zeros(g.nl)
+    vm, va = _grids.random_state(g.nb, 3)
+    pf_, qf, pt, qt = oracle.branch_flows(g, vm, va)
+    assert np.max(np.abs(pf_ + pt)) <= 1e-13 * np.max(np.abs(pf_))
+
+
+def textbook_branch_flows(g, vm, va):
+    """P and Q of both ends from the branch admittances in polar form,
+    P_hk = v_h^2 G_ff + v_h v_k (G_ft cos d + B_ft sin d),
+    Q_hk = -v_h^2 B_ff + v_h v_k (G_ft sin d - B_ft cos d), d = theta_h - theta_k,
+    with the usual pi-model branch entries (real-analytic in vm, va, so a
+    complex step differentiates it)."""
+    h, k = g.fbus, g.tbus
+    m = np.where(g.tap == 0.0, 1.0, g.tap)
+    ys = 1.0 / (g.r + 1j * g.x)
+    yff = (ys + 0.5j * g.b) / m ** 2
+    yft = -ys / (m * np.exp(-1j * g.shift))
+    ytf = -ys / (m * np.exp(1j * g.shift))
+    ytt = ys + 0.5j * g.b
+
+    def ends(vi, vj, ti, tj, yii, yij):
+        d = ti - tj
+        p = vi ** 2 * yii.real + vi * vj * (yij.real * np.cos(d) + yij.imag * np.sin(d))
+        q = -vi ** 2 * yii.imag + vi * vj * (yij.real * np.sin(d) - yij.imag * np.cos(d))
+        return p, q
+    pf_, qf = ends(vm[h], vm[k], va[h], va[k], yff, yft)
+    pt, qt = ends(vm[k], vm[h], va[k], va[h], ytt, ytf)
+    return pf_, qf, pt, qt
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_branch_flow_jacobian_complex_step(seed):
+    g = _grids.random_small(25, 45, 200 + seed, parallel=3)
+    vm, va = _grids.random_state(g.nb, seed)
+    jac = oracle.branch_flow_jac(g, vm, va)
+    flows = oracle.branch_flows(g, vm, va)
+    ref = textbook_branch_flows(g, vm.astype(complex), va.astype(complex))
+    for a, b_ in zip(flows, ref):
+        assert np.max(np.abs(a - b_.real)) <= 1e-13 * np.max(np.abs(a))
+    h_step = 1e-30
+    want = np.zeros((16, g.nl))
+    for l in range(g.nl):
+        for v, (arr, bus) in enumerate(((va, g.fbus[l]), (va, g.tbus[l]), (vm, g.fbus[l]), (vm, g.tbus[l]))):
+            vm_c, va_c = vm.astype(complex), va.astype(complex)
+            (va_c if arr is va else vm_c)[bus] += 1j * h_step
+            out = textbook_branch_flows(g, vm_c, va_c)
+            for f in range(4):
+                want[4 * f + v, l] = out[f][l].imag / h_step
+    assert np.max(np.abs(jac - want)) <= 1e-12 * np.max(np.abs(want))
