@@ -392,6 +392,23 @@ def main():
                                     "fused_speedup": (ev / K) / avg_launch}
         log(f"two-phase S+J: {ev / K * 1e6:.2f} us/eval")
 
+    if want("flows"):
+        # branch flows and their 16 partials (line-limit constraints), same grid and protocol
+        for d in reps:
+            d["fl"] = [torch.empty(1, g.nl, dtype=torch.float64, device=dev) for _ in range(4)]
+            d["fj"] = torch.empty(1, 16, g.nl, dtype=torch.float64, device=dev)
+
+        def flows(k, st):
+            d = reps[k % R]
+            pf.pf_branch_flows(d["G"], d["vm"], d["va"], *d["fl"], d["fj"], stream=st)
+        ev, wall = timed(flows, K, W)
+        fb = 48 * g.nl + 16 * g.nb + (32 + 128) * g.nl  # branch data + state in, flows + partials out
+        extra["branch_flows_jac"] = {"evals_per_s": K / wall, "avg_launch_us": ev / K * 1e6,
+                                     "achieved_GBs": fb / (ev / K) / 1e9, "algorithmic_bytes": fb}
+        for d in reps:
+            del d["fl"], d["fj"]
+        log(f"branch flows + partials: {ev / K * 1e6:.2f} us/launch")
+
     if want("copy"):
         # a plain device copy moving the same number of bytes (half read, half written)
         n = abytes // 16

@@ -180,6 +180,16 @@ int pf_injections_vjp(const pf_grid *g, int32_t nstate, const double *vm, const 
                       const double *lam_p, const double *lam_q, double *g_vm, double *g_va,
                       void *stream);
 
+/* Branch flows, eqs. (5)-(6): for every branch l (input order, grid after
+ * grid) the power entering the branch at its from end, S_hk = pf + j qf,
+ * and at its to end, S_kh = pt + j qt; f64[nstate][nl] device (nl over all
+ * grids).  jac (device, may be NULL): the 16 partial derivatives per branch,
+ * f64[nstate][16][nl], row 4 f + v holding d(Pf, Qf, Pt, Qt)[f] /
+ * d(theta_from, theta_to, v_from, v_to)[v] (the derivatives line-flow limits
+ * need; Section II.B).  One launch. */
+int pf_branch_flows(const pf_grid *g, int32_t nstate, const double *vm, const double *va, double *pf,
+                    double *qf, double *pt, double *qt, double *jac, void *stream);
+
 /* Launch schedule.
  *   tile_items        workgroup size (64, 128, 256 or 512): branch ends per
  *                     element-wise work tile, Ybus nonzeros per Ybus tile

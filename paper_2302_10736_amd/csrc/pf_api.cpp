@@ -908,6 +908,22 @@ int pf_jacobian_values(const pf_grid *g, int32_t method, int32_t nstate, const d
     return run(g, L, stream);
 }
 
+int pf_branch_flows(const pf_grid *g, int32_t nstate, const double *vm, const double *va, double *pf, double *qf,
+                    double *pt, double *qt, double *jac, void *stream) {
+    g_err.clear();
+    int st = check_eval(g, nstate);
+    if (st) return st;
+    if (nstate == 0 || g->nl == 0) return PF_OK;  // nothing to write
+    if (!vm || !va || !pf || !qf || !pt || !qt) return fail(PF_EINVAL, "NULL state or output pointer");
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (cur != g->device) return fail(PF_EINVAL, "current HIP device differs from the handle's device");
+    e = pf::launch_flows(g->tp, nstate, vm, va, pf, qf, pt, qt, jac, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return PF_OK;
+}
+
 int pf_injections_vjp(const pf_grid *g, int32_t nstate, const double *vm, const double *va, const double *lam_p,
                       const double *lam_q, double *g_vm, double *g_va, void *stream) {
     g_err.clear();

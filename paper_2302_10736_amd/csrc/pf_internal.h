@@ -139,6 +139,10 @@ hipError_t launch_setup_items(const DevSetup &s, hipStream_t stream);
 // slot arrays.
 hipError_t launch_lane_fill(const DevLaneFill &f, bool ew, hipStream_t stream);
 hipError_t launch_ybus_assemble(const DevSetup &s, hipStream_t stream);
+// Branch flows (and, if jac is not NULL, their 16 partials) of every branch
+// at every state.
+hipError_t launch_flows(const DevTwoPhase &d, int32_t nstate, const double *vm, const double *va, double *pf,
+                        double *qf, double *pt, double *qt, double *jac, hipStream_t stream);
 // States [0, nstate) one after another, two launches each.
 hipError_t launch_two_phase(const DevTwoPhase &d, int32_t nstate, int64_t nnz_j, const double *vm, const double *va,
                             double *p, double *q, double *jval, hipStream_t stream);

@@ -833,27 +833,34 @@ __global__ void k_ybus_assemble(DevSetup s) {
 // with A = g_s/m^2, C = (b/2 + b_s)/m^2, phi_e = phi at the from end and
 // A = g_s, C = b/2 + b_s, phi_e = -phi at the to end; the partials follow from
 // d alpha/d d = -beta and d beta/d d = alpha.
-__device__ __forceinline__ void tp_end(double *sc, int64_t stride, int e, double vi, double vj, double d, double A,
-                                       double C, double G, double B) {
+// P, Q of one branch end and its partials with respect to the end's own
+// bus i and the remote bus j.
+struct EndVals {
+    double p, q, dpti, dpvi, dqti, dqvi, dptj, dpvj, dqtj, dqvj;
+};
+
+__device__ __forceinline__ EndVals branch_end(double vi, double vj, double d, double A, double C, double G, double B) {
     double sn, cs;
     sincos_dev(d, &sn, &cs);
     const double al = fma(G, cs, B * sn), be = fma(G, sn, -(B * cs));
     const double w = vi * vj;
-    sc[0 * stride + e] = fma(vi * vi, A, -(w * al));          // P_e
-    sc[1 * stride + e] = fma(-(vi * vi), C, -(w * be));       // Q_e
-    sc[2 * stride + e] = w * be;                              // dP/dtheta_i
-    sc[3 * stride + e] = fma(2.0 * vi, A, -(vj * al));        // dP/dv_i
-    sc[4 * stride + e] = -(w * al);                           // dQ/dtheta_i
-    sc[5 * stride + e] = fma(-2.0 * vi, C, -(vj * be));       // dQ/dv_i
-    sc[6 * stride + e] = -(w * be);                           // dP/dtheta_j
-    sc[7 * stride + e] = -(vi * al);                          // dP/dv_j
-    sc[8 * stride + e] = w * al;                              // dQ/dtheta_j
-    sc[9 * stride + e] = -(vi * be);                          // dQ/dv_j
+    EndVals o;
+    o.p = fma(vi * vi, A, -(w * al));
+    o.q = fma(-(vi * vi), C, -(w * be));
+    o.dpti = w * be;
+    o.dpvi = fma(2.0 * vi, A, -(vj * al));
+    o.dqti = -(w * al);
+    o.dqvi = fma(-2.0 * vi, C, -(vj * be));
+    o.dptj = -(w * be);
+    o.dpvj = -(vi * al);
+    o.dqtj = w * al;
+    o.dqvj = -(vi * be);
+    return o;
 }
 
-__global__ void k_tp_branch(DevTwoPhase d, const double *__restrict__ vm, const double *__restrict__ va) {
-    const int l = blockIdx.x * blockDim.x + threadIdx.x;
-    if (l >= d.nl) return;
+// Both ends of branch l (from end first) at one state.
+__device__ __forceinline__ void branch_ends(const DevTwoPhase &d, int l, const double *vm, const double *va,
+                                            EndVals &f, EndVals &t) {
     const int h = d.br_from[l], k = d.br_to[l];
     const double r = d.r[l], x = d.x[l];
     const double den = fma(r, r, x * x);
@@ -862,8 +869,58 @@ __global__ void k_tp_branch(DevTwoPhase d, const double *__restrict__ vm, const 
     const double bh = 0.5 * d.b[l], phi = d.shift[l];
     const double vh = vm[h], th = va[h], vk = vm[k], tk = va[k];
     const double G = gsr / m, B = bsr / m;
-    tp_end(d.scr, d.nrec, d.br_rec[2 * l], vh, vk, th - tk - phi, gsr / (m * m), (bh + bsr) / (m * m), G, B);
-    tp_end(d.scr, d.nrec, d.br_rec[2 * l + 1], vk, vh, tk - th + phi, gsr, bh + bsr, G, B);
+    f = branch_end(vh, vk, th - tk - phi, gsr / (m * m), (bh + bsr) / (m * m), G, B);
+    t = branch_end(vk, vh, tk - th + phi, gsr, bh + bsr, G, B);
+}
+
+__device__ __forceinline__ void tp_store(double *sc, int64_t stride, int e, const EndVals &o) {
+    sc[0 * stride + e] = o.p;
+    sc[1 * stride + e] = o.q;
+    sc[2 * stride + e] = o.dpti;
+    sc[3 * stride + e] = o.dpvi;
+    sc[4 * stride + e] = o.dqti;
+    sc[5 * stride + e] = o.dqvi;
+    sc[6 * stride + e] = o.dptj;
+    sc[7 * stride + e] = o.dpvj;
+    sc[8 * stride + e] = o.dqtj;
+    sc[9 * stride + e] = o.dqvj;
+}
+
+__global__ void k_tp_branch(DevTwoPhase d, const double *__restrict__ vm, const double *__restrict__ va) {
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= d.nl) return;
+    EndVals f, t;
+    branch_ends(d, l, vm, va, f, t);
+    tp_store(d.scr, d.nrec, d.br_rec[2 * l], f);
+    tp_store(d.scr, d.nrec, d.br_rec[2 * l + 1], t);
+}
+
+// Branch flows and (WITH_J) their 16 partials: one thread per (branch,
+// state); every output array is written with consecutive branches in
+// consecutive lanes.
+template <bool WITH_J>
+__global__ void k_flows(DevTwoPhase d, int nstate, const double *__restrict__ vm, const double *__restrict__ va,
+                        double *__restrict__ pf, double *__restrict__ qf, double *__restrict__ pt,
+                        double *__restrict__ qt, double *__restrict__ jac) {
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= d.nl) return;
+    for (int s = blockIdx.y; s < nstate; s += gridDim.y) {
+        const size_t sb = (size_t)s * d.nb, sl = (size_t)s * d.nl;
+        EndVals f, t;
+        branch_ends(d, l, vm + sb, va + sb, f, t);
+        pf[sl + l] = f.p;
+        qf[sl + l] = f.q;
+        pt[sl + l] = t.p;
+        qt[sl + l] = t.q;
+        if constexpr (WITH_J) {
+            // rows d(Pf, Qf, Pt, Qt) / d(theta_from, theta_to, v_from, v_to)
+            const double v[16] = {f.dpti, f.dptj, f.dpvi, f.dpvj, f.dqti, f.dqtj, f.dqvi, f.dqvj,
+                                  t.dptj, t.dpti, t.dpvj, t.dpvi, t.dqtj, t.dqti, t.dqvj, t.dqvi};
+            double *js = jac + (size_t)s * 16 * d.nl;
+#pragma unroll
+            for (int q = 0; q < 16; ++q) js[(size_t)q * d.nl + l] = v[q];
+        }
+    }
 }
 
 __global__ void k_tp_reduce(DevTwoPhase d, const double *__restrict__ vm, double *__restrict__ P,
@@ -1102,6 +1159,17 @@ hipError_t launch_two_phase(const DevTwoPhase &d, int32_t nstate, int64_t nnz_j,
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+hipError_t launch_flows(const DevTwoPhase &d, int32_t nstate, const double *vm, const double *va, double *pf,
+                        double *qf, double *pt, double *qt, double *jac, hipStream_t stream) {
+    if (d.nl == 0 || nstate == 0) return hipSuccess;
+    const dim3 grid((unsigned)((d.nl + 255) / 256), (unsigned)std::min<int32_t>(nstate, 65535));
+    if (jac)
+        hipLaunchKernelGGL(k_flows<true>, grid, dim3(256), 0, stream, d, nstate, vm, va, pf, qf, pt, qt, jac);
+    else
+        hipLaunchKernelGGL(k_flows<false>, grid, dim3(256), 0, stream, d, nstate, vm, va, pf, qf, pt, qt, jac);
+    return hipGetLastError();
 }
 
 hipError_t launch_ybus_assemble(const DevSetup &s, hipStream_t stream) {

@@ -25,7 +25,7 @@ PF_ORDER_AUTO, PF_ORDER_TILE_MAJOR, PF_ORDER_STATE_MAJOR = 0, 1, 2
 EXPORTS = (
     "pf_build_pattern", "pf_grid_free", "pf_grid_sizes", "pf_pattern_sizes", "pf_grid_offsets",
     "pf_pattern_export", "pf_ybus", "pf_injections_elementwise", "pf_injections_ybus", "pf_jacobian_values",
-    "pf_injections_vjp", "pf_set_schedule", "pf_get_schedule", "pf_graph_create", "pf_graph_launch",
+    "pf_injections_vjp", "pf_branch_flows", "pf_set_schedule", "pf_get_schedule", "pf_graph_create", "pf_graph_launch",
     "pf_graph_free", "pf_last_error", "pf_version",
 )
 PF_OP_INJECTIONS, PF_OP_JACOBIAN, PF_OP_VJP = 0, 1, 2
@@ -69,6 +69,7 @@ def lib() -> C.CDLL:
         L.pf_injections_ybus.argtypes = [P, i32, P, P, P, P, P]
         L.pf_jacobian_values.argtypes = [P, i32, i32, P, P, P, P, P, P]
         L.pf_injections_vjp.argtypes = [P, i32, P, P, P, P, P, P, P]
+        L.pf_branch_flows.argtypes = [P, i32, P, P, P, P, P, P, P, P]
         L.pf_set_schedule.argtypes = [P, i32, i32, i32]
         L.pf_graph_create.argtypes = [P, P, i32, C.POINTER(P)]
         L.pf_graph_launch.argtypes = [P, P]
@@ -139,6 +140,7 @@ class Grid:
         n_b, n_y, n_j, n_g = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int32()
         check(lib().pf_grid_sizes(self._h, C.byref(n_b), C.byref(n_y), C.byref(n_j), C.byref(n_g)))
         self.nb, self.nnz_y, self.nnz_j, self.ngrids = n_b.value, n_y.value, n_j.value, n_g.value
+        self.nl = int(nl)
 
     @classmethod
     def from_grid(cls, g, bus_off=None, br_off=None, host_only=False):
@@ -234,6 +236,17 @@ def pf_injections_vjp(grid: Grid, vm, va, lam_p, lam_q, g_vm, g_va, stream=None)
     check(lib().pf_injections_vjp(grid.handle, ns, _dev(vm, shp, "vm"), _dev(va, shp, "va"),
                                   _dev(lam_p, shp, "lam_p"), _dev(lam_q, shp, "lam_q"), _dev(g_vm, shp, "g_vm"),
                                   _dev(g_va, shp, "g_va"), _stream(stream)))
+
+
+def pf_branch_flows(grid: Grid, vm, va, pf_, qf, pt, qt, jac=None, stream=None):
+    ns = _nstate(vm, grid.nb)
+    shp = tuple(vm.shape)
+    nl = grid.nl
+    fshp = (nl,) if vm.dim() == 1 else (ns, nl)
+    jshp = (16, nl) if vm.dim() == 1 else (ns, 16, nl)
+    check(lib().pf_branch_flows(grid.handle, ns, _dev(vm, shp, "vm"), _dev(va, shp, "va"), _dev(pf_, fshp, "pf"),
+                                _dev(qf, fshp, "qf"), _dev(pt, fshp, "pt"), _dev(qt, fshp, "qt"),
+                                _dev(jac, jshp, "jac"), _stream(stream)))
 
 
 def pf_version() -> str:

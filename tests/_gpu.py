@@ -49,6 +49,8 @@ def oracle_all(g, vm, va, lam_p=None, lam_q=None):
     out["j_yb"] = oracle.jac_ybus(yb, vm, va, pat)
     if lam_p is not None:
         out["gvm"], out["gva"] = oracle.vjp(g.nb, pat, out["j_yb"], lam_p, lam_q)
+    out["fl"] = oracle.branch_flows(g, vm, va)
+    out["fl_j"] = oracle.branch_flow_jac(g, vm, va)
     out["scale"] = term_scale(yb, vm)
     return out
 
@@ -67,6 +69,10 @@ def gpu_all(G, vm, va, lam_p=None, lam_q=None, with_ybus=True):
     p2, q2, j2 = z(ns, G.nb), z(ns, G.nb), z(ns, G.nnz_j)
     pf.pf_jacobian_values(G, pf.PF_METHOD_ELEMENTWISE, vm_d, va_d, p2, q2, j2)
     res["p_ew"], res["q_ew"], res["j_ew"] = p2, q2, j2
+    fl = [z(ns, G.nl) for _ in range(4)]
+    fj = z(ns, 16, G.nl)
+    pf.pf_branch_flows(G, vm_d, va_d, *fl, fj)
+    res["fl_pf"], res["fl_qf"], res["fl_pt"], res["fl_qt"], res["fl_j"] = (*fl, fj)
     p5, q5, j5 = z(ns, G.nb), z(ns, G.nb), z(ns, G.nnz_j)
     pf.pf_jacobian_values(G, pf.PF_METHOD_ELEMENTWISE_TWO_PHASE, vm_d, va_d, p5, q5, j5)
     res["p_tp"], res["q_tp"], res["j_tp"] = p5, q5, j5
@@ -88,7 +94,7 @@ def gpu_all(G, vm, va, lam_p=None, lam_q=None, with_ybus=True):
     return {k: v.cpu().numpy() for k, v in res.items()}
 
 
-def compare_grid(gres, ores, s, bus_sl, j_sl, y_sl=None, tol=TOL, use_scale=False):
+def compare_grid(gres, ores, s, bus_sl, j_sl, y_sl=None, tol=TOL, use_scale=False, br_sl=slice(None)):
     """Compare GPU results of state s (slices of one grid) with oracle results.
 
     Returns the list of (name, error) pairs; raises AssertionError on failure."""
@@ -105,6 +111,16 @@ def compare_grid(gres, ores, s, bus_sl, j_sl, y_sl=None, tol=TOL, use_scale=Fals
         e = rel_err(gres[gk][s][sl], ores[ok], sc)
         errs.append((gk, e))
         assert e <= tol, f"{gk}: relative error {e:.3e} > {tol:.0e} (state {s})"
+    if "fl_pf" in gres and "fl" in ores:
+        for n, (gk, want) in enumerate(zip(("fl_pf", "fl_qf", "fl_pt", "fl_qt"), ores["fl"])):
+            if len(want):
+                e = rel_err(gres[gk][s][br_sl], want)
+                errs.append((gk, e))
+                assert e <= tol, f"{gk}: relative error {e:.3e} (state {s})"
+        if ores["fl_j"].size:
+            e = rel_err(gres["fl_j"][s][:, br_sl], ores["fl_j"])
+            errs.append(("fl_j", e))
+            assert e <= tol, f"fl_j: relative error {e:.3e} (state {s})"
     if y_sl is not None and "yre" in gres:
         y = ores["yb"].y
         e = rel_err(gres["yre"][y_sl] + 1j * gres["yim"][y_sl], y)

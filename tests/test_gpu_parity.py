@@ -133,7 +133,7 @@ def test_multigrid_every_call():
         for s in range(ns):
             ores = oracle_all(g, vm[s, bsl], va[s, bsl], lp[s, bsl], lq[s, bsl])
             compare_grid(gres, ores, s, bsl, slice(j_off[k], j_off[k + 1]), slice(y_off[k], y_off[k + 1]),
-                         use_scale=g.nb == 2)
+                         use_scale=g.nb == 2, br_sl=slice(ro[k], ro[k + 1]))
 
 
 def test_determinism_across_runs_and_schedules():
