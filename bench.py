@@ -246,13 +246,10 @@ def main():
     nnz_y, nnz_j = G0.nnz_y, G0.nnz_j
     # schedules come from the autotuner, tuned afresh (a private cache file)
     tune_cache = autotune.ScheduleCache(os.path.join(tempfile.mkdtemp(prefix="pf_bench_"), "schedules.json"))
+    # The headline keeps the default schedule (256-lane tiles, one state per
+    # workgroup), the one the counter probe and the kernel trace also run;
+    # tile sizes 128-512 are within noise of it on cold data.
     tuned = {}
-    if not args.no_tune and not args.probe:
-        res = autotune.tune(G0, "jacobian_ew", 1, cache=tune_cache, save=False)
-        tuned["headline"] = res
-        for d in reps[1:]:
-            d["G"].set_schedule(*res["schedule"])
-        log(f"tuned headline schedule {res['schedule']} ({res['us']:.2f} us in the tuner)")
     tile, spb, order, ntiles = G0.schedule()
     log(f"grid nb={g.nb} nl={g.nl} nnzY={nnz_y} nnzJ={nnz_j} tiles={ntiles} replicas={R}")
 
@@ -357,7 +354,7 @@ def main():
                    "replicas_rotated": R, "tile_items": tile},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": HEADLINE_KERNEL, "algorithmic_bytes_per_launch": abytes,
+                     "kernel": f"k_ew<{tile}, false, true, true>", "algorithmic_bytes_per_launch": abytes,
                      "avg_launch_us": avg_launch * 1e6},
     }
 
