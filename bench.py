@@ -16,7 +16,9 @@ launch stream), the CPU oracle's rate on the host, and side measurements:
 the Ybus method under the same protocol, warm-cache rates, a plain copy of
 the same byte count (the practical bandwidth ceiling at this size), 512
 batched states on a 20k-bus grid, 64 uneven grids x 4 states, and the
-adjoint (32 states at 100k buses) against its forward pass.
+adjoint (32 states at 100k buses) against its forward pass, and a
+Newton-Raphson power flow on a 5000-bus grid (device evaluation against
+host sparse solve per iteration).
 
 Counter runs (HBM traffic of the dominant kernel):
     rocprofv3 --pmc FETCH_SIZE --output-format csv -d D1 -o f -- python3 bench.py --probe
@@ -524,8 +526,35 @@ def main():
                                      "forward_GBs": fb / (ev_f / steps) / 1e9, "vjp_GBs": bb / (ev_b / steps) / 1e9}
         log(f"adjoint: fwd {ev_f / steps * 1e6:.1f} us, vjp {ev_b / steps * 1e6:.1f} us")
 
+    if want("newton"):
+        # the evaluation as the inner step of a Newton-Raphson power flow: 5000-bus
+        # grid, 20 % PV buses, start near the solution; host sparse LU per iteration
+        from paper_2302_10736_amd import newton
+        g5 = gridgen.make_grid(5000, 6750, 0.15, cfg=2)
+        vm5, va5 = gridgen.states(g5.nb, 1, cfg=2, vlo=0.98, vhi=1.02, sigma=0.02)
+        G5 = pf.Grid.from_grid(g5)
+        # specified powers: the injections at the chosen state
+        p5 = torch.empty(1, g5.nb, dtype=torch.float64, device=dev)
+        q5 = torch.empty_like(p5)
+        pf.pf_injections_elementwise(G5, torch.as_tensor(vm5, device=dev), torch.as_tensor(va5, device=dev), p5, q5)
+        case = newton.case_from_state(g5, vm5[0], va5[0], p5[0].cpu().numpy(), q5[0].cpu().numpy(),
+                                      pv_frac=0.2, perturb=0.001)
+        newton.solve(G5, *case, tol=1e-10, max_iter=10)  # warm-up (first-call costs)
+        res = newton.solve(G5, *case, tol=1e-10, max_iter=10)
+        it = max(1, res.iterations)
+        extra["newton_5k"] = {"converged": res.converged, "iterations": res.iterations,
+                              "max_mismatch": res.mismatch,
+                              "eval_ms_per_iter": res.seconds_eval / (it + 1) * 1e3,
+                              "solve_ms_per_iter": res.seconds_solve / it * 1e3,
+                              "max_state_error": float(max(np.abs(res.vm - vm5[0]).max(),
+                                                           np.abs(res.va - va5[0]).max())),
+                              "note": "eval = device S+J plus copies to the host; solve = host SuperLU"}
+        log(f"newton: {res.iterations} iterations, eval {extra['newton_5k']['eval_ms_per_iter']:.3f} ms/iter, "
+            f"solve {extra['newton_5k']['solve_ms_per_iter']:.2f} ms/iter")
+        del G5
+
     if tuned:
-        extra["autotuner"] = {k: {"schedule": v["schedule"], "us": v["us"], "tried": v["tried"]}
+        extra["autotuner"] ={k: {"schedule": v["schedule"], "us": v["us"], "tried": v["tried"]}
                               for k, v in tuned.items()}
     if extra:
         out["extra"] = extra
