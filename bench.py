@@ -16,7 +16,9 @@ launch stream), the CPU oracle's rate on the host, and side measurements:
 the Ybus method under the same protocol, warm-cache rates, a plain copy of
 the same byte count (the practical bandwidth ceiling at this size), 512
 batched states on a 20k-bus grid, 64 uneven grids x 4 states, and the
-adjoint (32 states at 100k buses) against its forward pass, and a
+adjoint (32 states at 100k buses) against its forward pass, the Ybus
+injections with a separate phasor step in split and interleaved storage
+(Table I's comparison) against the fused kernel, and a
 Newton-Raphson power flow on a 5000-bus grid (device evaluation against
 host sparse solve per iteration).
 
@@ -443,6 +445,49 @@ def main():
             ev, wall = timed(yb_s, K, W)
             extra["ybus_s_only"] = {"evals_per_s": K / wall, "avg_launch_us": ev / K * 1e6}
         log("warm/S-only done")
+
+    if want("phasor"):
+        # Table I's comparison on the GPU: Ybus injections with the phasor step
+        # separate (split or interleaved storage) against the fused kernel
+        for d in reps:
+            pf.pf_ybus(d["G"])
+            d["ph"] = torch.empty(4 * g.nb, dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+
+        def yb_fused_s(k, st):
+            d = reps[k % R]
+            pf.pf_injections_ybus(d["G"], d["vm"], d["va"], d["p"], d["q"], stream=st)
+        ev, _ = timed(yb_fused_s, K, W)
+        res = {"fused_on_the_fly": {"total_us": ev / K * 1e6}}
+        for name, lay in (("split", pf.PF_PHASOR_SPLIT), ("interleaved", pf.PF_PHASOR_INTERLEAVED)):
+            def ph_step(k, st, lay=lay):
+                d = reps[k % R]
+                pf.pf_phasors(d["G"], lay, d["vm"], d["va"], d["ph"], stream=st)
+
+            def pw_step(k, st, lay=lay):
+                d = reps[k % R]
+                pf.pf_ybus_from_phasors(d["G"], lay, 1, d["ph"], d["p"], d["q"], stream=st)
+
+            def both(k, st, lay=lay):
+                ph_step(k, st, lay)
+                pw_step(k, st, lay)
+
+            def both_j(k, st, lay=lay):
+                ph_step(k, st, lay)
+                d = reps[k % R]
+                pf.pf_ybus_from_phasors(d["G"], lay, 1, d["ph"], d["p"], d["q"], d["j"], stream=st)
+            e_ph, _ = timed(ph_step, K, W)
+            e_pw, _ = timed(pw_step, K, W)
+            e_t, _ = timed(both, K, W)
+            e_tj, _ = timed(both_j, K, W)
+            res[name] = {"phasor_us": e_ph / K * 1e6, "power_us": e_pw / K * 1e6, "total_us": e_t / K * 1e6,
+                         "total_with_jacobian_us": e_tj / K * 1e6}
+        if "ybus_sj" in extra:
+            res["fused_on_the_fly"]["total_with_jacobian_us"] = extra["ybus_sj"]["avg_launch_us"]
+        extra["ybus_phasor_storage"] = res
+        for d in reps:
+            del d["ph"]
+        log("phasor storage: " + ", ".join(f"{k} {v['total_us']:.2f} us" for k, v in res.items()))
 
     del reps
     torch.cuda.empty_cache()

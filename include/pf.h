@@ -180,6 +180,28 @@ int pf_injections_vjp(const pf_grid *g, int32_t nstate, const double *vm, const 
                       const double *lam_p, const double *lam_q, double *g_vm, double *g_va,
                       void *stream);
 
+/* Ybus method from stored phasors: the paper's two separate steps of the
+ * injection computation (Section IV.B.1 and Table I: phasor calculation,
+ * then the sparse product), with the phasors kept in one of the two storage
+ * layouts it compares.  Ablation of the fused pf_injections_ybus /
+ * pf_jacobian_values(PF_METHOD_YBUS), which form the phasors on the fly;
+ * all three give bit-identical results.
+ *   layout  PF_PHASOR_SPLIT: real and imaginary parts in separate arrays,
+ *           ph = [Re V | Im V | Re U | Im U], four f64[nstate][nb] planes;
+ *           PF_PHASOR_INTERLEAVED: {re, im} pairs, ph = nstate*nb pairs of
+ *           V followed by nstate*nb pairs of U (16-byte aligned).
+ *   ph      f64[4 nstate nb] device buffer, caller-owned.
+ * pf_phasors writes V = v e^{j theta} and U = e^{j theta}.
+ * pf_ybus_from_phasors reads them (U only when jval is non-NULL) and writes
+ * p, q (f64[nstate][nb]; required when jval is NULL, else both may be NULL)
+ * and jval (f64[nstate][nnz_j], CSR order, may be NULL); PF_ESTATE before
+ * pf_ybus.  One launch each. */
+enum { PF_PHASOR_SPLIT = 1, PF_PHASOR_INTERLEAVED = 2 };
+int pf_phasors(const pf_grid *g, int32_t layout, int32_t nstate, const double *vm, const double *va,
+               double *ph, void *stream);
+int pf_ybus_from_phasors(const pf_grid *g, int32_t layout, int32_t nstate, const double *ph, double *p,
+                         double *q, double *jval, void *stream);
+
 /* Branch flows, eqs. (5)-(6): for every branch l (input order, grid after
  * grid) the power entering the branch at its from end, S_hk = pf + j qf,
  * and at its to end, S_kh = pt + j qt; f64[nstate][nl] device (nl over all

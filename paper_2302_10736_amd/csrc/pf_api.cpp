@@ -908,6 +908,49 @@ int pf_jacobian_values(const pf_grid *g, int32_t method, int32_t nstate, const d
     return run(g, L, stream);
 }
 
+int pf_phasors(const pf_grid *g, int32_t layout, int32_t nstate, const double *vm, const double *va, double *ph,
+               void *stream) {
+    g_err.clear();
+    int st = check_eval(g, nstate);
+    if (st) return st;
+    if (layout != PF_PHASOR_SPLIT && layout != PF_PHASOR_INTERLEAVED) return fail(PF_EINVAL, "unknown phasor layout");
+    if (nstate == 0) return PF_OK;
+    if (!vm || !va || !ph) return fail(PF_EINVAL, "NULL state or phasor pointer");
+    if (layout == PF_PHASOR_INTERLEAVED && reinterpret_cast<uintptr_t>(ph) % 16)
+        return fail(PF_EINVAL, "interleaved phasors must be 16-byte aligned");
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (cur != g->device) return fail(PF_EINVAL, "current HIP device differs from the handle's device");
+    e = pf::launch_phasor(layout, (int64_t)nstate * g->nb, vm, va, ph, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return PF_OK;
+}
+
+int pf_ybus_from_phasors(const pf_grid *g, int32_t layout, int32_t nstate, const double *ph, double *p, double *q,
+                         double *jval, void *stream) {
+    g_err.clear();
+    int st = check_eval(g, nstate);
+    if (st) return st;
+    if (layout != PF_PHASOR_SPLIT && layout != PF_PHASOR_INTERLEAVED) return fail(PF_EINVAL, "unknown phasor layout");
+    if (!g->ybus_valid) return fail(PF_ESTATE, "pf_ybus has not been called on this handle");
+    if ((p == nullptr) != (q == nullptr)) return fail(PF_EINVAL, "p and q must both be given or both be NULL");
+    if (nstate > 0 && !ph) return fail(PF_EINVAL, "NULL phasor pointer");
+    if (nstate > 0 && !jval && !p) return fail(PF_EINVAL, "nothing to write: p, q and jval are NULL");
+    if (layout == PF_PHASOR_INTERLEAVED && reinterpret_cast<uintptr_t>(ph) % 16)
+        return fail(PF_EINVAL, "interleaved phasors must be 16-byte aligned");
+    if (reinterpret_cast<uintptr_t>(jval) % 16) return fail(PF_EINVAL, "jval must be 16-byte aligned");
+    pf::Launch L{};
+    L.kind = jval ? pf::K_YB_SJ : pf::K_YB_S;
+    L.nstate = nstate;
+    L.phasor = layout;
+    L.ph = ph;
+    L.p = p;
+    L.q = q;
+    L.jval = jval;
+    return run(g, L, stream);
+}
+
 int pf_branch_flows(const pf_grid *g, int32_t nstate, const double *vm, const double *va, double *pf, double *qf,
                     double *pt, double *qt, double *jac, void *stream) {
     g_err.clear();

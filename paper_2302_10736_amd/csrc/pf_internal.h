@@ -128,6 +128,8 @@ struct Launch {
     bool has_parallel;
     const double *vm, *va, *lp, *lq;
     double *p, *q, *jval, *gvm, *gva;
+    int phasor;        // Ybus kinds: 0 on the fly from vm, va; 1 split, 2 interleaved stored phasors in ph
+    const double *ph;  // stored phasors (layout of launch_phasor)
 };
 
 hipError_t launch_eval(const DevGrid &g, const Launch &L, hipStream_t stream);
@@ -139,6 +141,10 @@ hipError_t launch_setup_items(const DevSetup &s, hipStream_t stream);
 // slot arrays.
 hipError_t launch_lane_fill(const DevLaneFill &f, bool ew, hipStream_t stream);
 hipError_t launch_ybus_assemble(const DevSetup &s, hipStream_t stream);
+// V = v e^{j theta} and U = e^{j theta} of n (state, bus) entries into ph:
+// layout 1 = four planes [Re V | Im V | Re U | Im U] of n doubles, layout 2 =
+// n pairs {Re V, Im V} then n pairs {Re U, Im U}.
+hipError_t launch_phasor(int32_t layout, int64_t n, const double *vm, const double *va, double *ph, hipStream_t stream);
 // Branch flows (and, if jac is not NULL, their 16 partials) of every branch
 // at every state.
 hipError_t launch_flows(const DevTwoPhase &d, int32_t nstate, const double *vm, const double *va, double *pf,

@@ -419,20 +419,101 @@ __global__ void __launch_bounds__(NT)
 }
 
 // ===================================================================
+// Stored phasors (Section IV.B.1 step 1): V = v e^{j theta}, U = e^{j theta}
+// for n = nstate * nb (state, bus) entries.  PH_SPLIT: four planes of n
+// doubles [Re V | Im V | Re U | Im U]; PH_INTERLEAVED: n pairs {Re V, Im V}
+// followed by n pairs {Re U, Im U}.
+enum { PH_FLY = 0, PH_SPLIT = 1, PH_INTERLEAVED = 2 };
+
+template <int PH>
+__global__ void k_phasor(int64_t n, const double *__restrict__ vm, const double *__restrict__ va, double *__restrict__ ph) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double sn, cs;
+    sincos_dev(va[i], &sn, &cs);
+    const double v = vm[i];
+    if constexpr (PH == PH_SPLIT) {
+        ph[i] = v * cs;
+        ph[n + i] = v * sn;
+        ph[2 * n + i] = cs;
+        ph[3 * n + i] = sn;
+    } else {
+        double2 *p2 = reinterpret_cast<double2 *>(ph);
+        p2[i] = make_double2(v * cs, v * sn);
+        p2[n + i] = make_double2(cs, sn);
+    }
+}
+
+// Per-state inputs of one Ybus nonzero: (v, theta) for PH_FLY, else the
+// stored V (and U when the Jacobian needs it).
+struct YbIn {
+    double a, b, c, d;
+};
+
+template <int PH, bool WANT_U>
+__device__ __forceinline__ void yb_load(const double *vm, const double *va, const double *ph, size_t n, size_t idx,
+                                        YbIn &x) {
+    if constexpr (PH == PH_FLY) {
+        x.a = vm[idx];
+        x.b = va[idx];
+    } else if constexpr (PH == PH_SPLIT) {
+        x.a = ph[idx];
+        x.b = ph[n + idx];
+        if constexpr (WANT_U) {
+            x.c = ph[2 * n + idx];
+            x.d = ph[3 * n + idx];
+        } else {
+            x.c = x.d = 0.0;
+        }
+    } else {
+        const double2 *p2 = reinterpret_cast<const double2 *>(ph);
+        const double2 v = p2[idx];
+        x.a = v.x;
+        x.b = v.y;
+        if constexpr (WANT_U) {
+            const double2 u = p2[n + idx];
+            x.c = u.x;
+            x.d = u.y;
+        } else {
+            x.c = x.d = 0.0;
+        }
+    }
+}
+
+// V and U of loaded inputs.
+template <int PH>
+__device__ __forceinline__ void yb_phasor(const YbIn &x, Cx &V, Cx &U) {
+    if constexpr (PH == PH_FLY) {
+        double sn, cs;
+        sincos_dev(x.b, &sn, &cs);
+        U = {cs, sn};
+        V = {x.a * cs, x.a * sn};
+    } else {
+        V = {x.a, x.b};
+        U = {x.c, x.d};
+    }
+}
+
+// ===================================================================
 // Ybus method: I = Ybus V, S = V conj(I) (eq. (1)) and, with WITH_J, the
 // two-pass Jacobian of eqs. (3)-(4) done row-wise on the CSR matrix:
 // pass 1 forms Y_ij V_j and the row sums I_i, pass 2 turns each nonzero into
 //   dS_i/dtheta_j = j V_i (delta_ij conj(I_i) - conj(Y_ij V_j))
 //   dS_i/dv_j     = V_i conj(Y_ij U_j) + delta_ij conj(I_i) U_i
 // and writes the four real parts in place into J (Section IV.B.2).
-// U = e^{j theta} and V = v U are formed on the fly from (vm, va); a row's
-// own V_i and U_i reach the other threads of the row through LDS.
+// With PH = PH_FLY, U = e^{j theta} and V = v U are formed on the fly from
+// (vm, va); the stored-phasor variants (Section V.B.1, Table I) read V and U
+// written beforehand by k_phasor, either as separate real / imaginary planes
+// (PH_SPLIT) or as interleaved {re, im} pairs (PH_INTERLEAVED).  k_phasor
+// computes the same products as the on-the-fly path, so all three give
+// bit-identical results.  A row's own V_i and U_i reach the other threads of
+// the row through LDS.
 // The single-state instantiation is held to 6 waves per SIMD (<= 80 VGPRs),
 // so a 100k-bus grid's workgroups are all resident at once.
-template <int NT, bool WITH_J, bool ONE>
+template <int NT, bool WITH_J, bool ONE, int PH>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? 6 : 1, 8)))
     k_ybus(DevGrid g, int nstate, int spb, int nchunk, bool state_major, const double *__restrict__ vm, const double *__restrict__ va,
-           double *__restrict__ P, double *__restrict__ Q, double *__restrict__ J) {
+           const double *__restrict__ ph, double *__restrict__ P, double *__restrict__ Q, double *__restrict__ J) {
     constexpr int NBUF = ONE ? 1 : 2;
     __shared__ double s_yv[NBUF][2][NT];  // Y_ij V_j
     __shared__ double s_vu[NBUF][4][NT];  // per row: V_i, U_i (re, im)
@@ -456,18 +537,19 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? 6
         // ---- one long row: pass 1 sums I_i in chunks (thread 0, in slot order), pass 2 writes J.
         const int i = c.r0;
         const int d = c.ns;
+        const size_t n = (size_t)nstate * nb;
         for (int s = sb; s < se; ++s) {
-            const double *vms = vm + (size_t)s * nb;
-            const double *vas = va + (size_t)s * nb;
+            const size_t so = (size_t)s * nb;
             Cx I = {0.0, 0.0};
             for (int base = 0; base < d; base += NT) {
                 if (base + k < d) {
                     const int p = c.s0 + base + k;
                     const int jc = g.ycol[p];
-                    double sn, cs;
-                    sincos_dev(vas[jc], &sn, &cs);
-                    const double v = vms[jc];
-                    const Cx yv = cmul({g.yre[p], g.yim[p]}, {v * cs, v * sn});
+                    YbIn x;
+                    yb_load<PH, false>(vm, va, ph, n, so + jc, x);
+                    Cx Vj, Uj;
+                    yb_phasor<PH>(x, Vj, Uj);
+                    const Cx yv = cmul({g.yre[p], g.yim[p]}, Vj);
                     s_yv[0][0][k] = yv.re;
                     s_yv[0][1][k] = yv.im;
                 }
@@ -483,11 +565,10 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? 6
                 }
                 __syncthreads();
             }
-            double sn, cs;
-            sincos_dev(vas[i], &sn, &cs);
-            const Cx Ui = {cs, sn};
-            const double vi = vms[i];
-            const Cx Vi = {vi * cs, vi * sn};
+            YbIn xi;
+            yb_load<PH, true>(vm, va, ph, n, so + i, xi);
+            Cx Vi, Ui;
+            yb_phasor<PH>(xi, Vi, Ui);
             const Cx Ic = {s_vu[0][0][0], -s_vu[0][1][0]};  // conj(I_i)
             if (k == 0 && P) {
                 const Cx S = cmul(Vi, Ic);
@@ -499,12 +580,12 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? 6
                 for (int lp = k; lp < d; lp += NT) {
                     const int p = c.s0 + lp;
                     const int jc = g.ycol[p];
-                    double snj, csj;
-                    sincos_dev(vas[jc], &snj, &csj);
-                    const double v = vms[jc];
+                    YbIn xj;
+                    yb_load<PH, true>(vm, va, ph, n, so + jc, xj);
+                    Cx Vj, Uj;
+                    yb_phasor<PH>(xj, Vj, Uj);
                     const Cx Y = {g.yre[p], g.yim[p]};
-                    const Cx Uj = {csj, snj};
-                    const Cx yv = cmul(Y, {v * csj, v * snj});
+                    const Cx yv = cmul(Y, Vj);
                     const bool dg = jc == i;
                     const Cx x = {(dg ? Ic.re : 0.0) - yv.re, (dg ? Ic.im : 0.0) + yv.im};  // delta conj(I) - conj(YV)
                     const Cx dst = cmul({-Vi.im, Vi.re}, x);                                  // j V_i x
@@ -530,13 +611,9 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? 6
     const Cx Y = {yl.x, yl.y};
     const bool rowt = k < c.nrows;
     const int ir = c.r0 + (rowt ? k : 0);
-    struct In {
-        double v, th;
-    };
-    auto load = [&](int s, In &x) {
-        x.v = vm[(size_t)s * nb + j];
-        x.th = va[(size_t)s * nb + j];
-    };
+    const size_t n = (size_t)nstate * nb;
+    using In = YbIn;
+    auto load = [&](int s, In &x) { yb_load<PH, WITH_J>(vm, va, ph, n, (size_t)s * nb + j, x); };
     In first;  // first state's gathers before the row loads, as in k_ew
     load(sb, first);
     const int irr = rowt ? ir : g.nb;
@@ -547,17 +624,18 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? 6
     // As in k_ew: every lane computes, only stores depend on the lane's role
     // (inert lanes have Y = 0 and a valid bus).
     auto proc = [&](int s, int p, const In &x) {
-        double sn, cs;
-        sincos_dev(x.th, &sn, &cs);
-        const Cx Uj = {cs, sn};
-        const Cx yv = cmul(Y, {x.v * cs, x.v * sn});
+        Cx Vj, Uj;
+        yb_phasor<PH>(x, Vj, Uj);
+        const Cx yv = cmul(Y, Vj);
         s_yv[p][0][k] = yv.re;
         s_yv[p][1][k] = yv.im;
         if (diag) {  // the diagonal nonzero carries the row's own phasor
-            s_vu[p][0][row] = x.v * cs;
-            s_vu[p][1][row] = x.v * sn;
-            s_vu[p][2][row] = cs;
-            s_vu[p][3][row] = sn;
+            s_vu[p][0][row] = Vj.re;
+            s_vu[p][1][row] = Vj.im;
+            if constexpr (WITH_J || PH == PH_FLY) {
+                s_vu[p][2][row] = Uj.re;
+                s_vu[p][3][row] = Uj.im;
+            }
         }
         lds_barrier();
         Cx I;
@@ -1001,6 +1079,35 @@ __global__ void k_lane_fill(DevLaneFill f, bool ew) {
     }
 }
 
+template <int NT, bool ONE, bool WITH_J>
+void launch_ybus_ph(const DevGrid &g, const Launch &L, dim3 grid, dim3 block, int spb, int nchunk, hipStream_t st) {
+    double *J = WITH_J ? L.jval : nullptr;
+    switch (L.phasor) {
+        case PH_SPLIT:
+            hipLaunchKernelGGL((k_ybus<NT, WITH_J, ONE, PH_SPLIT>), grid, block, 0, st, g, L.nstate, spb, nchunk, L.state_major,
+                               L.vm, L.va, L.ph, L.p, L.q, J);
+            break;
+        case PH_INTERLEAVED:
+            hipLaunchKernelGGL((k_ybus<NT, WITH_J, ONE, PH_INTERLEAVED>), grid, block, 0, st, g, L.nstate, spb, nchunk,
+                               L.state_major, L.vm, L.va, L.ph, L.p, L.q, J);
+            break;
+        default:
+            hipLaunchKernelGGL((k_ybus<NT, WITH_J, ONE, PH_FLY>), grid, block, 0, st, g, L.nstate, spb, nchunk, L.state_major,
+                               L.vm, L.va, L.ph, L.p, L.q, J);
+            break;
+    }
+}
+
+template <int NT, bool ONE>
+hipError_t launch_ybus(const DevGrid &g, const Launch &L, dim3 grid, dim3 block, int spb, int nchunk, hipStream_t st) {
+    if (L.phasor != PH_FLY && L.phasor != PH_SPLIT && L.phasor != PH_INTERLEAVED) return hipErrorInvalidValue;
+    if (L.kind == K_YB_SJ)
+        launch_ybus_ph<NT, ONE, true>(g, L, grid, block, spb, nchunk, st);
+    else
+        launch_ybus_ph<NT, ONE, false>(g, L, grid, block, spb, nchunk, st);
+    return hipGetLastError();
+}
+
 template <int NT, bool ONE>
 hipError_t launch_nt(const DevGrid &g, const Launch &L, hipStream_t st) {
     const int spb = L.states_per_block;
@@ -1028,13 +1135,8 @@ hipError_t launch_nt(const DevGrid &g, const Launch &L, hipStream_t st) {
                                    L.p, L.q, L.jval);
             break;
         case K_YB_S:
-            hipLaunchKernelGGL((k_ybus<NT, false, ONE>), grid, block, 0, st, g, L.nstate, spb, nchunk, L.state_major, L.vm, L.va, L.p, L.q,
-                               nullptr);
-            break;
         case K_YB_SJ:
-            hipLaunchKernelGGL((k_ybus<NT, true, ONE>), grid, block, 0, st, g, L.nstate, spb, nchunk, L.state_major, L.vm, L.va, L.p, L.q,
-                               L.jval);
-            break;
+            return launch_ybus<NT, ONE>(g, L, grid, block, spb, nchunk, st);
         case K_EW_VJP:
             hipLaunchKernelGGL((k_ew_vjp<NT, ONE>), grid, block, 0, st, g, L.nstate, spb, nchunk, L.state_major, L.vm, L.va, L.lp, L.lq,
                                L.gvm, L.gva);
@@ -1060,10 +1162,10 @@ int occupancy_nt(int kind, bool par) {
                   : reinterpret_cast<const void *>(&k_ew<NT, false, true, ONE>));
             break;
         case K_YB_S:
-            q(reinterpret_cast<const void *>(&k_ybus<NT, false, ONE>));
+            q(reinterpret_cast<const void *>(&k_ybus<NT, false, ONE, PH_FLY>));
             break;
         case K_YB_SJ:
-            q(reinterpret_cast<const void *>(&k_ybus<NT, true, ONE>));
+            q(reinterpret_cast<const void *>(&k_ybus<NT, true, ONE, PH_FLY>));
             break;
         case K_EW_VJP:
             q(reinterpret_cast<const void *>(&k_ew_vjp<NT, ONE>));
@@ -1169,6 +1271,19 @@ hipError_t launch_flows(const DevTwoPhase &d, int32_t nstate, const double *vm, 
         hipLaunchKernelGGL(k_flows<true>, grid, dim3(256), 0, stream, d, nstate, vm, va, pf, qf, pt, qt, jac);
     else
         hipLaunchKernelGGL(k_flows<false>, grid, dim3(256), 0, stream, d, nstate, vm, va, pf, qf, pt, qt, jac);
+    return hipGetLastError();
+}
+
+hipError_t launch_phasor(int32_t layout, int64_t n, const double *vm, const double *va, double *ph, hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    const int64_t blocks = (n + 255) / 256;
+    if (blocks > INT32_MAX) return hipErrorInvalidConfiguration;
+    if (layout == PH_SPLIT)
+        hipLaunchKernelGGL(k_phasor<PH_SPLIT>, dim3((unsigned)blocks), dim3(256), 0, stream, n, vm, va, ph);
+    else if (layout == PH_INTERLEAVED)
+        hipLaunchKernelGGL(k_phasor<PH_INTERLEAVED>, dim3((unsigned)blocks), dim3(256), 0, stream, n, vm, va, ph);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

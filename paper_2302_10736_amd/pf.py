@@ -21,11 +21,12 @@ PF_OK, PF_EINVAL, PF_ENOMEM, PF_EHIP, PF_ESTATE, PF_EUNSUP = range(6)
 PF_METHOD_ELEMENTWISE, PF_METHOD_YBUS, PF_METHOD_ELEMENTWISE_TWO_PHASE = 0, 1, 2
 PF_BUILD_HOST_ONLY = 1
 PF_ORDER_AUTO, PF_ORDER_TILE_MAJOR, PF_ORDER_STATE_MAJOR = 0, 1, 2
+PF_PHASOR_SPLIT, PF_PHASOR_INTERLEAVED = 1, 2
 
 EXPORTS = (
     "pf_build_pattern", "pf_grid_free", "pf_grid_sizes", "pf_pattern_sizes", "pf_grid_offsets",
     "pf_pattern_export", "pf_ybus", "pf_injections_elementwise", "pf_injections_ybus", "pf_jacobian_values",
-    "pf_injections_vjp", "pf_branch_flows", "pf_set_schedule", "pf_get_schedule", "pf_graph_create", "pf_graph_launch",
+    "pf_injections_vjp", "pf_branch_flows", "pf_phasors", "pf_ybus_from_phasors", "pf_set_schedule", "pf_get_schedule", "pf_graph_create", "pf_graph_launch",
     "pf_graph_free", "pf_last_error", "pf_version",
 )
 PF_OP_INJECTIONS, PF_OP_JACOBIAN, PF_OP_VJP = 0, 1, 2
@@ -70,6 +71,8 @@ def lib() -> C.CDLL:
         L.pf_jacobian_values.argtypes = [P, i32, i32, P, P, P, P, P, P]
         L.pf_injections_vjp.argtypes = [P, i32, P, P, P, P, P, P, P]
         L.pf_branch_flows.argtypes = [P, i32, P, P, P, P, P, P, P, P]
+        L.pf_phasors.argtypes = [P, i32, i32, P, P, P, P]
+        L.pf_ybus_from_phasors.argtypes = [P, i32, i32, P, P, P, P, P]
         L.pf_set_schedule.argtypes = [P, i32, i32, i32]
         L.pf_graph_create.argtypes = [P, P, i32, C.POINTER(P)]
         L.pf_graph_launch.argtypes = [P, P]
@@ -247,6 +250,31 @@ def pf_branch_flows(grid: Grid, vm, va, pf_, qf, pt, qt, jac=None, stream=None):
     check(lib().pf_branch_flows(grid.handle, ns, _dev(vm, shp, "vm"), _dev(va, shp, "va"), _dev(pf_, fshp, "pf"),
                                 _dev(qf, fshp, "qf"), _dev(pt, fshp, "pt"), _dev(qt, fshp, "qt"),
                                 _dev(jac, jshp, "jac"), _stream(stream)))
+
+
+def pf_phasors(grid: Grid, layout: int, vm, va, ph, stream=None):
+    """V and U of every state into ``ph`` (float64, 4 * nstate * nb values,
+    any shape): see include/pf.h for the two layouts."""
+    ns = _nstate(vm, grid.nb)
+    shp = tuple(vm.shape)
+    if ph.numel() != 4 * ns * grid.nb:
+        raise ValueError("ph must hold 4 * nstate * nb values")
+    check(lib().pf_phasors(grid.handle, int(layout), ns, _dev(vm, shp, "vm"), _dev(va, shp, "va"),
+                           _dev(ph, None, "ph"), _stream(stream)))
+
+
+def pf_ybus_from_phasors(grid: Grid, layout: int, nstate: int, ph, p=None, q=None, jval=None, stream=None):
+    """Ybus injections (and Jacobian values if ``jval`` is given) from the
+    phasors ``pf_phasors`` wrote; ``nstate`` states, outputs [nstate, nb] /
+    [nstate, nnz_j] (or 1-D for one state)."""
+    if ph.numel() != 4 * nstate * grid.nb:
+        raise ValueError("ph must hold 4 * nstate * nb values")
+    ref = p if p is not None else jval
+    flat = ref is not None and ref.dim() == 1
+    shp = (grid.nb,) if flat else (nstate, grid.nb)
+    jshp = (grid.nnz_j,) if flat else (nstate, grid.nnz_j)
+    check(lib().pf_ybus_from_phasors(grid.handle, int(layout), int(nstate), _dev(ph, None, "ph"), _dev(p, shp, "p"),
+                                     _dev(q, shp, "q"), _dev(jval, jshp, "jval"), _stream(stream)))
 
 
 def pf_version() -> str:

@@ -187,6 +187,8 @@ def test_eval_on_host_only_handle_is_state_error():
     assert L.pf_injections_elementwise(G.handle, 1, None, None, None, None, None) == pf.PF_ESTATE
     assert L.pf_jacobian_values(G.handle, 0, 1, None, None, None, None, None, None) == pf.PF_ESTATE
     assert L.pf_injections_vjp(G.handle, 1, None, None, None, None, None, None, None) == pf.PF_ESTATE
+    assert L.pf_phasors(G.handle, 1, 1, None, None, None, None) == pf.PF_ESTATE
+    assert L.pf_ybus_from_phasors(G.handle, 1, 1, None, None, None, None, None) == pf.PF_ESTATE
     assert "HOST_ONLY" in L.pf_last_error().decode()
     assert L.pf_injections_elementwise(None, 1, None, None, None, None, None) == pf.PF_EINVAL
 
