@@ -393,6 +393,19 @@ def main():
                                     "fused_speedup": (ev / K) / avg_launch}
         log(f"two-phase S+J: {ev / K * 1e6:.2f} us/eval")
 
+    if want("csc"):
+        # the same evaluation with J written in CSC order (what sparse direct solvers take)
+        def ew_csc(k, st):
+            d = reps[k % R]
+            pf.pf_jacobian_values(d["G"], pf.PF_METHOD_ELEMENTWISE | pf.PF_JAC_CSC, d["vm"], d["va"], d["p"], d["q"],
+                                  d["j"], stream=st)
+        ev, wall = timed(ew_csc, K, W)
+        cb = abytes + 32 * g.nl  # + the opposite end's coupling, 16 B per branch end (lane table)
+        extra["ew_sj_csc"] = {"evals_per_s": K / wall, "avg_launch_us": ev / K * 1e6,
+                              "achieved_GBs": abytes / (ev / K) / 1e9, "over_csr_time": (ev / K) / avg_launch,
+                              "kernel": f"k_ew_csc<{tile}, false, true>", "bytes_read_extra": cb - abytes}
+        log(f"element-wise S+J, CSC order: {ev / K * 1e6:.2f} us/launch")
+
     if want("flows"):
         # branch flows and their 16 partials (line-limit constraints), same grid and protocol
         for d in reps:

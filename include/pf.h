@@ -167,8 +167,16 @@ int pf_injections_ybus(const pf_grid *g, int32_t nstate, const double *vm, const
  *           PF_METHOD_YBUS: eqs. (3)-(4) by the row-wise two-pass scheme
  *           (Section IV.B.2), written in place into J (PF_ESTATE before
  *           pf_ybus).
+ *           PF_METHOD_ELEMENTWISE | PF_JAC_CSC: jval in column-major (CSC)
+ *           order, the storage sparse direct solvers take (the paper keeps J
+ *           in CSC, Section IV.A).  The pattern is structurally symmetric, so
+ *           the CSC column pointers and row indices are the exported j_rowptr
+ *           and j_col: value k of column c is J(j_col[k], c).  One launch, as
+ *           for CSR; PF_EUNSUP with the other methods.
  *   p, q    f64[nstate][nb] device outputs, or NULL to skip
- *   jval    f64[nstate][nnz_j] device output in the exported CSR order. */
+ *   jval    f64[nstate][nnz_j] device output in the exported CSR order
+ *           (CSC with PF_JAC_CSC). */
+enum { PF_JAC_CSC = 0x100 };
 int pf_jacobian_values(const pf_grid *g, int32_t method, int32_t nstate, const double *vm,
                        const double *va, double *p, double *q, double *jval, void *stream);
 

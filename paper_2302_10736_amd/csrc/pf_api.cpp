@@ -876,8 +876,12 @@ int pf_jacobian_values(const pf_grid *g, int32_t method, int32_t nstate, const d
     g_err.clear();
     int st = check_eval(g, nstate);
     if (st) return st;
+    const bool csc = (method & PF_JAC_CSC) != 0;
+    method &= ~PF_JAC_CSC;
     if (method != PF_METHOD_ELEMENTWISE && method != PF_METHOD_YBUS && method != PF_METHOD_ELEMENTWISE_TWO_PHASE)
         return fail(PF_EINVAL, "unknown method");
+    if (csc && method != PF_METHOD_ELEMENTWISE)
+        return fail(PF_EUNSUP, "the CSC order is available with PF_METHOD_ELEMENTWISE only");
     if (method == PF_METHOD_YBUS && !g->ybus_valid)
         return fail(PF_ESTATE, "pf_ybus has not been called on this handle");
     if (nstate > 0 && (!vm || !va || !jval)) return fail(PF_EINVAL, "NULL state or Jacobian pointer");
@@ -898,7 +902,7 @@ int pf_jacobian_values(const pf_grid *g, int32_t method, int32_t nstate, const d
         return PF_OK;
     }
     pf::Launch L{};
-    L.kind = method == PF_METHOD_ELEMENTWISE ? pf::K_EW_SJ : pf::K_YB_SJ;
+    L.kind = method == PF_METHOD_ELEMENTWISE ? (csc ? pf::K_EW_SJ_CSC : pf::K_EW_SJ) : pf::K_YB_SJ;
     L.nstate = nstate;
     L.vm = vm;
     L.va = va;
@@ -1004,6 +1008,7 @@ int op_kind(const pf_op &o) {
         case PF_OP_INJECTIONS:
             return o.method == PF_METHOD_YBUS ? pf::K_YB_S : pf::K_EW_S;
         case PF_OP_JACOBIAN:
+            if (o.method & PF_JAC_CSC) return pf::K_EW_SJ_CSC;
             return o.method == PF_METHOD_YBUS ? pf::K_YB_SJ : pf::K_EW_SJ;
         default:
             return pf::K_EW_VJP;

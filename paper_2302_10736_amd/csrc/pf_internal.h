@@ -117,7 +117,7 @@ struct DevTwoPhase {
     double *scr;                            // [10][nrec]
 };
 
-enum Kind { K_EW_S = 0, K_EW_SJ = 1, K_YB_S = 2, K_YB_SJ = 3, K_EW_VJP = 4 };
+enum Kind { K_EW_S = 0, K_EW_SJ = 1, K_YB_S = 2, K_YB_SJ = 3, K_EW_VJP = 4, K_EW_SJ_CSC = 5 };
 
 struct Launch {
     int kind;

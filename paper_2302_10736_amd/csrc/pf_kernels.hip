@@ -179,10 +179,12 @@ __device__ __forceinline__ void row_sum2(const double *x, const double *y, int a
     sy = v;
 }
 
-// One element-wise record (see the file header).
+// One element-wise record (see the file header): its row-sum terms and the
+// four values of its off-diagonal J slot in staging order (P rows: theta
+// part, v part; Q rows: theta part, v part).
 struct EwRec {
-    double a, b;                // v_j alpha, v_j beta (row sums)
-    double rpt, rpv, rqt, rqv;  // remote partials: dP/dtheta_j, dP/dv_j, dQ/dtheta_j, dQ/dv_j
+    double a, b;  // v_j alpha, v_j beta (row sums)
+    double o[4];  // CSR: dP_i/dtheta_j, dP_i/dv_j, dQ_i/dtheta_j, dQ_i/dv_j
 };
 
 __device__ __forceinline__ EwRec ew_record(double vi, double ti, double vj, double tj, double G, double B) {
@@ -193,10 +195,39 @@ __device__ __forceinline__ EwRec ew_record(double vi, double ti, double vj, doub
     EwRec r;
     r.a = vj * al;
     r.b = vj * be;
-    r.rpt = vi * r.b;
-    r.rpv = vi * al;
-    r.rqt = -(vi * r.a);
-    r.rqv = vi * be;
+    r.o[0] = vi * r.b;
+    r.o[1] = vi * al;
+    r.o[2] = -(vi * r.a);
+    r.o[3] = vi * be;
+    return r;
+}
+
+// The record for J in column-major (CSC) order.  The pattern is structurally
+// symmetric, so column theta_i (v_i) of J occupies the positions of row P_i
+// (Q_i) and lists rows P_k, then Q_k, for the same sorted k; the record's slot
+// therefore receives the partials of the opposite end of the branch (bus j
+// towards i: coupling Gr + jBr, angle -t) with respect to bus i:
+//   dP_j/dtheta_i = v_j v_i beta',  dQ_j/dtheta_i = -v_j v_i alpha',
+//   dP_j/dv_i     = v_j alpha',     dQ_j/dv_i     = v_j beta',
+// alpha' = Gr cos t - Br sin t, beta' = -Gr sin t - Br cos t.  sin is odd and
+// cos even bit for bit (sincos_rad), and the products round as the opposite
+// record's CSR evaluation rounds them, so CSC values are the CSR values
+// transposed exactly.
+__device__ __forceinline__ EwRec ew_record_csc(double vi, double ti, double vj, double tj, double G, double B,
+                                               double Gr, double Br) {
+    double sn, cs;
+    sincos_dev(ti - tj, &sn, &cs);
+    const double al = fma(G, cs, B * sn);
+    const double be = fma(G, sn, -(B * cs));
+    const double al2 = fma(Gr, cs, -(Br * sn));
+    const double be2 = fma(-Gr, sn, -(Br * cs));
+    EwRec r;
+    r.a = vj * al;
+    r.b = vj * be;
+    r.o[0] = vj * (vi * be2);
+    r.o[1] = -(vj * (vi * al2));
+    r.o[2] = vj * al2;
+    r.o[3] = vj * be2;
     return r;
 }
 
@@ -217,10 +248,15 @@ __device__ __forceinline__ EwRow ew_row(double vi, double dA, double dC, double 
 
 // ===================================================================
 // Element-wise injections (WITH_J = false) and injections + Jacobian values.
-template <int NT, bool PAR, bool WITH_J, bool ONE>
-__global__ void __launch_bounds__(NT)
-    k_ew(DevGrid g, int nstate, int spb, int nchunk, bool state_major, const double *__restrict__ vm, const double *__restrict__ va,
-         double *__restrict__ P, double *__restrict__ Q, double *__restrict__ J) {
+// The body is shared by k_ew and k_ew_csc: CSC = true writes J in
+// column-major order (WITH_J only) with the same tiles and staging, each
+// record's slot filled by ew_record_csc and the diagonal entries
+// dQ_i/dtheta_i and dP_i/dv_i trading places.
+template <int NT, bool PAR, bool WITH_J, bool ONE, bool CSC>
+__device__ __forceinline__ void ew_eval(const DevGrid &g, int nstate, int spb, int nchunk, bool state_major,
+                                        const double *__restrict__ vm, const double *__restrict__ va,
+                                        double *__restrict__ P, double *__restrict__ Q, double *__restrict__ J) {
+    static_assert(WITH_J || !CSC, "the CSC order concerns J values");
     constexpr int NR = (WITH_J && PAR) ? NT : 1;  // remote partials kept for slot sums
     constexpr int NBUF = ONE ? 1 : 2;             // LDS buffers alternate between states
     constexpr int NS = kEwSlots(NT);              // Ybus slots per tile
@@ -242,6 +278,8 @@ __global__ void __launch_bounds__(NT)
     const int j = g.lane_j[lane];
     const int pk = g.lane_pk[lane];
     const double2 gb = g.lane_gb[lane];
+    double2 grbr = make_double2(0.0, 0.0);
+    if constexpr (CSC) grbr = g.lane_grbr[lane];
     const Tile c = tile_of(g, t);
     const size_t nb = (size_t)g.nb;
 
@@ -262,15 +300,19 @@ __global__ void __launch_bounds__(NT)
                 if (base + k < c.n) {
                     const int e = c.i0 + base + k;
                     const int je = g.nbr[e];
-                    const EwRec r = ew_record(vi, ti, vms[je], vas[je], g.G[e], g.B[e]);
+                    EwRec r;
+                    if constexpr (CSC)
+                        r = ew_record_csc(vi, ti, vms[je], vas[je], g.G[e], g.B[e], g.Gr[e], g.Br[e]);
+                    else
+                        r = ew_record(vi, ti, vms[je], vas[je], g.G[e], g.B[e]);
                     s_ab[0][0][k] = r.a;
                     s_ab[0][1][k] = r.b;
                     if constexpr (WITH_J) {
-                        // the J stage holds the remote partials of the chunk
-                        s_J[0][0 * NT + k] = r.rpt;
-                        s_J[0][1 * NT + k] = r.rpv;
-                        s_J[0][2 * NT + k] = r.rqt;
-                        s_J[0][3 * NT + k] = r.rqv;
+                        // the J stage holds the slot values of the chunk's records
+                        s_J[0][0 * NT + k] = r.o[0];
+                        s_J[0][1 * NT + k] = r.o[1];
+                        s_J[0][2 * NT + k] = r.o[2];
+                        s_J[0][3 * NT + k] = r.o[3];
                         const int ls = (PAR ? g.slot[e] : e) - c.s0;
                         s_ls[k] = ls;
                         if (je == i) s_dslot[0] = ls;
@@ -319,8 +361,8 @@ __global__ void __launch_bounds__(NT)
                     }
                     const int ld = s_dslot[0];
                     Js[c.jp + ld] = o.j11;
-                    Js[c.jp + d + ld] = o.j12;
-                    Js[c.jq + ld] = o.j21;
+                    Js[c.jp + d + ld] = CSC ? o.j21 : o.j12;
+                    Js[c.jq + ld] = CSC ? o.j12 : o.j21;
                     Js[c.jq + d + ld] = o.j22;
                 }
             }
@@ -367,20 +409,24 @@ __global__ void __launch_bounds__(NT)
     // consumed on the straight-line path and the loads of the next state stay
     // in flight.  Stores come last: no load is waited for after a store.
     auto proc = [&](int s, int p, const In &x) {
-        const EwRec r = ew_record(x.vi, x.ti, x.vj, x.tj, gb.x, gb.y);
+        EwRec r;
+        if constexpr (CSC)
+            r = ew_record_csc(x.vi, x.ti, x.vj, x.tj, gb.x, gb.y, grbr.x, grbr.y);
+        else
+            r = ew_record(x.vi, x.ti, x.vj, x.tj, gb.x, gb.y);
         s_ab[p][0][k] = r.a;
         s_ab[p][1][k] = r.b;
         if constexpr (WITH_J) {
             if constexpr (PAR) {
-                s_rem[p][0][k] = r.rpt;
-                s_rem[p][1][k] = r.rpv;
-                s_rem[p][2][k] = r.rqt;
-                s_rem[p][3][k] = r.rqv;
+                s_rem[p][0][k] = r.o[0];
+                s_rem[p][1][k] = r.o[1];
+                s_rem[p][2][k] = r.o[2];
+                s_rem[p][3][k] = r.o[3];
             } else {
-                s_J[p][o11] = r.rpt;
-                s_J[p][o12] = r.rpv;
-                s_J[p][kQ<NS> + o11] = r.rqt;
-                s_J[p][kQ<NS> + o12] = r.rqv;
+                s_J[p][o11] = r.o[0];
+                s_J[p][o12] = r.o[1];
+                s_J[p][kQ<NS> + o11] = r.o[2];
+                s_J[p][kQ<NS> + o12] = r.o[3];
             }
         }
         lds_barrier();
@@ -389,8 +435,8 @@ __global__ void __launch_bounds__(NT)
         const EwRow o = ew_row(x.vr, dA, dC, as, bs);
         if constexpr (WITH_J) {
             s_J[p][d11] = o.j11;
-            s_J[p][d12] = o.j12;
-            s_J[p][kQ<NS> + d11] = o.j21;
+            s_J[p][d12] = CSC ? o.j21 : o.j12;
+            s_J[p][kQ<NS> + d11] = CSC ? o.j12 : o.j21;
             s_J[p][kQ<NS> + d12] = o.j22;
             if constexpr (PAR) {  // the first record of a slot sums the slot, in record order
                 double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
@@ -416,6 +462,21 @@ __global__ void __launch_bounds__(NT)
         }
     };
     pipelined_states<In, ONE>(sb, se, first, load, proc);
+}
+
+template <int NT, bool PAR, bool WITH_J, bool ONE>
+__global__ void __launch_bounds__(NT)
+    k_ew(DevGrid g, int nstate, int spb, int nchunk, bool state_major, const double *__restrict__ vm, const double *__restrict__ va,
+         double *__restrict__ P, double *__restrict__ Q, double *__restrict__ J) {
+    ew_eval<NT, PAR, WITH_J, ONE, false>(g, nstate, spb, nchunk, state_major, vm, va, P, Q, J);
+}
+
+// Injections and J values in CSC order.
+template <int NT, bool PAR, bool ONE>
+__global__ void __launch_bounds__(NT)
+    k_ew_csc(DevGrid g, int nstate, int spb, int nchunk, bool state_major, const double *__restrict__ vm,
+             const double *__restrict__ va, double *__restrict__ P, double *__restrict__ Q, double *__restrict__ J) {
+    ew_eval<NT, PAR, true, ONE, true>(g, nstate, spb, nchunk, state_major, vm, va, P, Q, J);
 }
 
 // ===================================================================
@@ -1134,6 +1195,14 @@ hipError_t launch_nt(const DevGrid &g, const Launch &L, hipStream_t st) {
                 hipLaunchKernelGGL((k_ew<NT, false, true, ONE>), grid, block, 0, st, g, L.nstate, spb, nchunk, L.state_major, L.vm, L.va,
                                    L.p, L.q, L.jval);
             break;
+        case K_EW_SJ_CSC:
+            if (L.has_parallel)
+                hipLaunchKernelGGL((k_ew_csc<NT, true, ONE>), grid, block, 0, st, g, L.nstate, spb, nchunk, L.state_major, L.vm,
+                                   L.va, L.p, L.q, L.jval);
+            else
+                hipLaunchKernelGGL((k_ew_csc<NT, false, ONE>), grid, block, 0, st, g, L.nstate, spb, nchunk, L.state_major, L.vm,
+                                   L.va, L.p, L.q, L.jval);
+            break;
         case K_YB_S:
         case K_YB_SJ:
             return launch_ybus<NT, ONE>(g, L, grid, block, spb, nchunk, st);
@@ -1160,6 +1229,10 @@ int occupancy_nt(int kind, bool par) {
         case K_EW_SJ:
             q(par ? reinterpret_cast<const void *>(&k_ew<NT, true, true, ONE>)
                   : reinterpret_cast<const void *>(&k_ew<NT, false, true, ONE>));
+            break;
+        case K_EW_SJ_CSC:
+            q(par ? reinterpret_cast<const void *>(&k_ew_csc<NT, true, ONE>)
+                  : reinterpret_cast<const void *>(&k_ew_csc<NT, false, ONE>));
             break;
         case K_YB_S:
             q(reinterpret_cast<const void *>(&k_ybus<NT, false, ONE, PH_FLY>));
@@ -1202,8 +1275,8 @@ hipError_t launch_eval(const DevGrid &g, const Launch &L, hipStream_t stream) {
 int resident_blocks_per_cu(int kind, int tile_items, bool has_parallel) {
     // One value per (kind, tile size, parallel flag): a property of the
     // compiled kernel and the device, so concurrent first calls agree.
-    static std::atomic<int> cache[5][4][2] = {};
-    if (kind < 0 || kind > 4) return 0;
+    static std::atomic<int> cache[6][4][2] = {};
+    if (kind < 0 || kind > 5) return 0;
     const int ti = tile_items == 64 ? 0 : tile_items == 128 ? 1 : tile_items == 256 ? 2 : tile_items == 512 ? 3 : -1;
     if (ti < 0) return 0;
     std::atomic<int> &slot = cache[kind][ti][has_parallel ? 1 : 0];

@@ -4,6 +4,10 @@ Stored phasors (Table I): pf_phasors + pf_ybus_from_phasors, in the split
 and the interleaved layout, must give bit-identical P, Q and J values to the
 fused Ybus calls (which form the phasors on the fly with the same
 arithmetic), and therefore the oracle's values within the parity gate.
+
+CSC order (PF_JAC_CSC): the element-wise Jacobian written column by column
+must be the CSR values transposed, bit for bit, and the oracle's J
+transposed within the parity gate.
 """
 from __future__ import annotations
 
@@ -116,3 +120,104 @@ def test_phasor_argument_checks():
     assert L.pf_phasors(G.handle, 1, 0, None, None, None, None) == pf.PF_OK  # zero states
     assert L.pf_ybus_from_phasors(G.handle, 1, 0, None, None, None, None, None) == pf.PF_OK
     torch.cuda.synchronize()
+
+
+# ---------------------------------------------------------------- CSC order
+def _csc_perm(jr, jc):
+    """For each CSC position of the (structurally symmetric) pattern, the CSR
+    position of the same entry."""
+    import scipy.sparse as sp
+    n = len(jr) - 1
+    A = sp.csr_matrix((np.arange(1, len(jc) + 1, dtype=np.float64), jc, jr), shape=(n, n))
+    T = A.T.tocsr()
+    T.sort_indices()
+    assert np.array_equal(T.indptr, jr) and np.array_equal(T.indices, jc)  # symmetric pattern
+    return T.data.astype(np.int64) - 1
+
+
+def _grid_perms(G, bus_off=None):
+    """CSC -> CSR position map of every grid of a handle, in global J numbering
+    (the exported pattern lists each grid's 2 nb_g + 1 row pointers, then the
+    next grid's)."""
+    _, _, jr, jc = G.pattern()
+    _, joff = G.offsets()
+    bo = np.array([0, G.nb]) if bus_off is None else np.asarray(bus_off)
+    perm = np.empty(G.nnz_j, np.int64)
+    r0 = 0
+    for k in range(G.ngrids):
+        a, b = int(joff[k]), int(joff[k + 1])
+        rows = jr[r0:r0 + 2 * int(bo[k + 1] - bo[k]) + 1]
+        assert rows[0] == 0 and rows[-1] == b - a
+        perm[a:b] = a + _csc_perm(rows, jc[a:b])
+        r0 += len(rows)
+    assert r0 == len(jr)
+    return perm
+
+
+def _csc_case(g, vm, va, tile, spb, bus_off=None, br_off=None):
+    import torch
+    G = pf.Grid.from_grid(g, bus_off, br_off)
+    G.set_schedule(tile, spb)
+    ns = vm.shape[0]
+    vmd, vad = to_dev(vm), to_dev(va)
+    p0, q0 = torch.empty_like(vmd), torch.empty_like(vmd)
+    j0 = torch.empty(ns, G.nnz_j, dtype=torch.float64, device="cuda:0")
+    pf.pf_jacobian_values(G, pf.PF_METHOD_ELEMENTWISE, vmd, vad, p0, q0, j0)
+    p1, q1 = torch.full_like(vmd, np.nan), torch.full_like(vmd, np.nan)
+    j1 = torch.full_like(j0, np.nan)
+    pf.pf_jacobian_values(G, pf.PF_METHOD_ELEMENTWISE | pf.PF_JAC_CSC, vmd, vad, p1, q1, j1)
+    torch.cuda.synchronize()
+    perm = _grid_perms(G, bus_off)
+    j0h, j1h = j0.cpu().numpy(), j1.cpu().numpy()
+    assert np.array_equal(p1.cpu().numpy(), p0.cpu().numpy()) and np.array_equal(q1.cpu().numpy(), q0.cpu().numpy())
+    for s in range(ns):
+        assert np.array_equal(j1h[s], j0h[s][perm]), s  # the CSR values transposed, bit for bit
+    return G, j1h
+
+
+def test_csc_config0_against_oracle():
+    import scipy.sparse as sp
+    g = gridgen.config0()
+    vm, va = gridgen.states(g.nb, 2, cfg=0)
+    G, jcsc = _csc_case(g, vm, va, 256, 0)
+    yr, yc, jr, jc = G.pattern()
+    yb = oracle.ybus(g)
+    pat = oracle.jac_pattern(yb)
+    for s in range(2):
+        jo = oracle.jac_ew(g, vm[s], va[s], pat)
+        A = sp.csr_matrix((jo, pat[1], pat[0]), shape=(2 * g.nb, 2 * g.nb))
+        # CSC values = column by column: the CSR data of the transpose
+        T = A.T.tocsr()
+        T.sort_indices()
+        assert rel_err(jcsc[s], T.data) <= TOL
+
+
+@pytest.mark.parametrize("tile", [64, 256, 512])
+def test_csc_edge_grids(tile):
+    for g in (_grids.random_small(80, 150, 21, parallel=9, isolated=4), star_grid(700, seed=1),
+              star_grid(600, seed=2, parallel=40), _grids.two_bus(0.01, 0.1, 0.02, 1.03, 0.04, flip=True)):
+        vm, va = _grids.random_state(g.nb, 3)
+        _csc_case(g, vm[None, :], va[None, :], tile, 1)
+
+
+def test_csc_batched_and_multigrid():
+    g = gridgen.config0()
+    vm, va = gridgen.states(g.nb, 11, cfg=0)
+    _csc_case(g, vm, va, 128, 3)
+    grids = [_grids.random_small(n, int(n * 1.4), 70 + n, parallel=n % 4) for n in (5, 40, 300, 17, 2)]
+    grids.append(star_grid(530, seed=9))
+    big, bo, ro = gridgen.concat(grids)
+    vm, va = _grids.random_state(big.nb, 7)
+    _csc_case(big, vm[None, :], va[None, :], 256, 0, bo, ro)
+
+
+def test_csc_other_methods_unsupported():
+    import torch
+    G = pf.Grid.from_grid(gridgen.config0())
+    pf.pf_ybus(G)
+    vm = torch.ones(G.nb, dtype=torch.float64, device="cuda:0")
+    j = torch.empty(G.nnz_j, dtype=torch.float64, device="cuda:0")
+    for m in (pf.PF_METHOD_YBUS, pf.PF_METHOD_ELEMENTWISE_TWO_PHASE):
+        with pytest.raises(pf.PFError) as e:
+            pf.pf_jacobian_values(G, m | pf.PF_JAC_CSC, vm, vm, None, None, j)
+        assert e.value.code == pf.PF_EUNSUP
