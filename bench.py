@@ -393,6 +393,18 @@ def main():
                                     "fused_speedup": (ev / K) / avg_launch}
         log(f"two-phase S+J: {ev / K * 1e6:.2f} us/eval")
 
+    if want("copy_add"):
+        # copy-add with atomic adds: zero J, shunt terms, one thread per branch adding both ends
+        def ca_sj(k, st):
+            d = reps[k % R]
+            pf.pf_jacobian_values(d["G"], pf.PF_METHOD_ELEMENTWISE_ATOMIC, d["vm"], d["va"], d["p"], d["q"], d["j"],
+                                  stream=st)
+        ev, wall = timed(ca_sj, K, W)
+        extra["ew_copy_add_atomic_sj"] = {"evals_per_s": K / wall, "avg_eval_us": ev / K * 1e6,
+                                          "achieved_GBs": abytes / (ev / K) / 1e9, "launches_per_eval": 3,
+                                          "fused_speedup": (ev / K) / avg_launch}
+        log(f"copy-add (atomic) S+J: {ev / K * 1e6:.2f} us/eval")
+
     if want("csc"):
         # the same evaluation with J written in CSC order (what sparse direct solvers take)
         def ew_csc(k, st):

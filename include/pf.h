@@ -88,7 +88,15 @@ typedef enum pf_method {
      * pf_jacobian_values only.  Its first call on a handle allocates the
      * scratch (10 doubles per record, kept until pf_grid_free); states run
      * one after another, two launches each. */
-    PF_METHOD_ELEMENTWISE_TWO_PHASE = 2
+    PF_METHOD_ELEMENTWISE_TWO_PHASE = 2,
+    /* Element-wise with the paper's copy-add reduction (Section IV.C.2) done
+     * by atomic adds: J set to zero and P, Q and the diagonal entries to the
+     * bus-shunt terms, then one thread per branch adds both ends' values.
+     * Another baseline; pf_jacobian_values only, three launches for all
+     * states.  The additions run in no fixed order: results agree with the
+     * other methods to rounding, not bit for bit, and may differ between
+     * runs.  jval must be 16-byte aligned. */
+    PF_METHOD_ELEMENTWISE_ATOMIC = 3
 } pf_method;
 
 enum {

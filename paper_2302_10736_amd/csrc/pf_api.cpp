@@ -878,7 +878,8 @@ int pf_jacobian_values(const pf_grid *g, int32_t method, int32_t nstate, const d
     if (st) return st;
     const bool csc = (method & PF_JAC_CSC) != 0;
     method &= ~PF_JAC_CSC;
-    if (method != PF_METHOD_ELEMENTWISE && method != PF_METHOD_YBUS && method != PF_METHOD_ELEMENTWISE_TWO_PHASE)
+    if (method != PF_METHOD_ELEMENTWISE && method != PF_METHOD_YBUS && method != PF_METHOD_ELEMENTWISE_TWO_PHASE &&
+        method != PF_METHOD_ELEMENTWISE_ATOMIC)
         return fail(PF_EINVAL, "unknown method");
     if (csc && method != PF_METHOD_ELEMENTWISE)
         return fail(PF_EUNSUP, "the CSC order is available with PF_METHOD_ELEMENTWISE only");
@@ -887,6 +888,18 @@ int pf_jacobian_values(const pf_grid *g, int32_t method, int32_t nstate, const d
     if (nstate > 0 && (!vm || !va || !jval)) return fail(PF_EINVAL, "NULL state or Jacobian pointer");
     if ((p == nullptr) != (q == nullptr)) return fail(PF_EINVAL, "p and q must both be given or both be NULL");
     if (reinterpret_cast<uintptr_t>(jval) % 16) return fail(PF_EINVAL, "jval must be 16-byte aligned");
+    if (method == PF_METHOD_ELEMENTWISE_ATOMIC) {
+        if (nstate == 0) return PF_OK;
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+        if (cur != g->device) return fail(PF_EINVAL, "current HIP device differs from the handle's device");
+        pf::DevTwoPhase d = g->tp;
+        d.ydslot = g->lanes.ydslot;
+        e = pf::launch_copy_add(d, nstate, 4 * g->nnz_y, vm, va, p, q, jval, static_cast<hipStream_t>(stream));
+        if (e != hipSuccess) return hip_fail(e, "kernel launch");
+        return PF_OK;
+    }
     if (method == PF_METHOD_ELEMENTWISE_TWO_PHASE) {
         if (nstate == 0) return PF_OK;
         int cur = -1;

@@ -149,6 +149,10 @@ hipError_t launch_phasor(int32_t layout, int64_t n, const double *vm, const doub
 // at every state.
 hipError_t launch_flows(const DevTwoPhase &d, int32_t nstate, const double *vm, const double *va, double *pf,
                         double *qf, double *pt, double *qt, double *jac, hipStream_t stream);
+// Copy-add with atomic adds: three launches for all states (zero J, bus
+// shunt terms, per-branch adds); jval 16-byte aligned.
+hipError_t launch_copy_add(const DevTwoPhase &d, int32_t nstate, int64_t nnz_j, const double *vm, const double *va,
+                           double *p, double *q, double *jval, hipStream_t stream);
 // States [0, nstate) one after another, two launches each.
 hipError_t launch_two_phase(const DevTwoPhase &d, int32_t nstate, int64_t nnz_j, const double *vm, const double *va,
                             double *p, double *q, double *jval, hipStream_t stream);

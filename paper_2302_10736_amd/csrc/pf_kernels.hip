@@ -1119,6 +1119,74 @@ __global__ void k_tp_reduce(DevTwoPhase d, const double *__restrict__ vm, double
     }
 }
 
+// ===================================================================
+// Copy-add on the GPU: the reduction the paper calls copy-add (Section
+// IV.C.2, the J elements added into the pre-built pattern), with atomic adds
+// in place of its sequential adds.  The outputs are first set to the bus
+// shunt terms (P, Q and the diagonal dP/dv, dQ/dv entries) and to zero (the
+// rest of J); then one thread per branch adds both ends' power and eight
+// partials into P, Q and the J slots.  The additions happen in no fixed
+// order, so results match the other methods to rounding only.
+__global__ void k_ca_zero(int64_t n2, double2 *__restrict__ J) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += (int64_t)gridDim.x * blockDim.x)
+        J[i] = make_double2(0.0, 0.0);
+}
+
+__global__ void k_ca_bus(DevTwoPhase d, int nstate, int64_t nnz_j, const double *__restrict__ vm,
+                         double *__restrict__ P, double *__restrict__ Q, double *__restrict__ J) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= d.nb) return;
+    const double gg = d.gs[i], bb = d.bs[i];
+    const int y0 = d.yrow[i], deg = d.yrow[i + 1] - y0, dp = d.ydslot[i] - y0;
+    const int64_t jp = d.jpq[i].x, jq = d.jpq[i].y;
+    for (int s = blockIdx.y; s < nstate; s += gridDim.y) {
+        const double v = vm[(size_t)s * d.nb + i];
+        if (P) {
+            P[(size_t)s * d.nb + i] = (v * v) * gg;
+            Q[(size_t)s * d.nb + i] = -((v * v) * bb);
+        }
+        double *Js = J + (size_t)s * (size_t)nnz_j;
+        Js[jp + deg + dp] = (2.0 * v) * gg;
+        Js[jq + deg + dp] = -((2.0 * v) * bb);
+    }
+}
+
+// Adds one branch end (record e at bus i) into P, Q and row i's J slots.
+__device__ __forceinline__ void ca_add_end(const DevTwoPhase &d, int e, int i, const EndVals &o, double *P, double *Q,
+                                           double *Js) {
+    const int y0 = d.yrow[i], deg = d.yrow[i + 1] - y0;
+    const int so = d.slot[e] - y0, dp = d.ydslot[i] - y0;
+    const int64_t jp = d.jpq[i].x, jq = d.jpq[i].y;
+    if (P) {
+        unsafeAtomicAdd(P + i, o.p);
+        unsafeAtomicAdd(Q + i, o.q);
+    }
+    unsafeAtomicAdd(Js + jp + dp, o.dpti);
+    unsafeAtomicAdd(Js + jp + deg + dp, o.dpvi);
+    unsafeAtomicAdd(Js + jq + dp, o.dqti);
+    unsafeAtomicAdd(Js + jq + deg + dp, o.dqvi);
+    unsafeAtomicAdd(Js + jp + so, o.dptj);
+    unsafeAtomicAdd(Js + jp + deg + so, o.dpvj);
+    unsafeAtomicAdd(Js + jq + so, o.dqtj);
+    unsafeAtomicAdd(Js + jq + deg + so, o.dqvj);
+}
+
+__global__ void k_ca_branch(DevTwoPhase d, int nstate, int64_t nnz_j, const double *__restrict__ vm,
+                            const double *__restrict__ va, double *P, double *Q, double *J) {
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= d.nl) return;
+    const int h = d.br_from[l], k = d.br_to[l];
+    const int ef = d.br_rec[2 * l], et = d.br_rec[2 * l + 1];
+    for (int s = blockIdx.y; s < nstate; s += gridDim.y) {
+        const size_t sb = (size_t)s * d.nb;
+        EndVals f, t;
+        branch_ends(d, l, vm + sb, va + sb, f, t);
+        double *Js = J + (size_t)s * (size_t)nnz_j;
+        ca_add_end(d, ef, h, f, P ? P + sb : nullptr, Q ? Q + sb : nullptr, Js);
+        ca_add_end(d, et, k, t, P ? P + sb : nullptr, Q ? Q + sb : nullptr, Js);
+    }
+}
+
 // Lane values: copies of the record constants (element-wise) or Ybus values
 // in lane order; inert lanes get zeros.
 __global__ void k_lane_fill(DevLaneFill f, bool ew) {
@@ -1334,6 +1402,24 @@ hipError_t launch_two_phase(const DevTwoPhase &d, int32_t nstate, int64_t nnz_j,
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+hipError_t launch_copy_add(const DevTwoPhase &d, int32_t nstate, int64_t nnz_j, const double *vm, const double *va,
+                           double *p, double *q, double *jval, hipStream_t stream) {
+    if (nstate == 0) return hipSuccess;
+    const unsigned ys = (unsigned)std::min<int32_t>(nstate, 65535);
+    const int64_t n2 = (int64_t)nstate * nnz_j / 2;  // nnz_j = 4 nnz_y is even
+    if (n2 > 0) {
+        const int64_t blocks = std::min<int64_t>((n2 + 255) / 256, 65536);
+        hipLaunchKernelGGL(k_ca_zero, dim3((unsigned)blocks), dim3(256), 0, stream, n2, reinterpret_cast<double2 *>(jval));
+    }
+    if (d.nb > 0)
+        hipLaunchKernelGGL(k_ca_bus, dim3((unsigned)((d.nb + 255) / 256), ys), dim3(256), 0, stream, d, nstate, nnz_j, vm, p,
+                           q, jval);
+    if (d.nl > 0)
+        hipLaunchKernelGGL(k_ca_branch, dim3((unsigned)((d.nl + 255) / 256), ys), dim3(256), 0, stream, d, nstate, nnz_j, vm,
+                           va, p, q, jval);
+    return hipGetLastError();
 }
 
 hipError_t launch_flows(const DevTwoPhase &d, int32_t nstate, const double *vm, const double *va, double *pf,

@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpf.so")
 
 PF_OK, PF_EINVAL, PF_ENOMEM, PF_EHIP, PF_ESTATE, PF_EUNSUP = range(6)
-PF_METHOD_ELEMENTWISE, PF_METHOD_YBUS, PF_METHOD_ELEMENTWISE_TWO_PHASE = 0, 1, 2
+PF_METHOD_ELEMENTWISE, PF_METHOD_YBUS, PF_METHOD_ELEMENTWISE_TWO_PHASE, PF_METHOD_ELEMENTWISE_ATOMIC = 0, 1, 2, 3
 PF_BUILD_HOST_ONLY = 1
 PF_ORDER_AUTO, PF_ORDER_TILE_MAJOR, PF_ORDER_STATE_MAJOR = 0, 1, 2
 PF_PHASOR_SPLIT, PF_PHASOR_INTERLEAVED = 1, 2

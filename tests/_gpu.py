@@ -76,6 +76,9 @@ def gpu_all(G, vm, va, lam_p=None, lam_q=None, with_ybus=True):
     p5, q5, j5 = z(ns, G.nb), z(ns, G.nb), z(ns, G.nnz_j)
     pf.pf_jacobian_values(G, pf.PF_METHOD_ELEMENTWISE_TWO_PHASE, vm_d, va_d, p5, q5, j5)
     res["p_tp"], res["q_tp"], res["j_tp"] = p5, q5, j5
+    p6, q6, j6 = z(ns, G.nb), z(ns, G.nb), z(ns, G.nnz_j)
+    pf.pf_jacobian_values(G, pf.PF_METHOD_ELEMENTWISE_ATOMIC, vm_d, va_d, p6, q6, j6)
+    res["p_ca"], res["q_ca"], res["j_ca"] = p6, q6, j6  # free order of additions: not bitwise reproducible
     if with_ybus:
         yre, yim = z(G.nnz_y), z(G.nnz_y)
         pf.pf_ybus(G, yre, yim)
@@ -104,6 +107,7 @@ def compare_grid(gres, ores, s, bus_sl, j_sl, y_sl=None, tol=TOL, use_scale=Fals
              ("q_ew_s", "q_ew", bus_sl), ("j_ew", "j_ew", j_sl), ("p_yb", "p_yb", bus_sl), ("q_yb", "q_yb", bus_sl),
              ("p_yb_s", "p_yb", bus_sl), ("q_yb_s", "q_yb", bus_sl), ("j_yb", "j_yb", j_sl),
              ("p_tp", "p_ew", bus_sl), ("q_tp", "q_ew", bus_sl), ("j_tp", "j_ew", j_sl),
+             ("p_ca", "p_ew", bus_sl), ("q_ca", "q_ew", bus_sl), ("j_ca", "j_ew", j_sl),
              ("gvm", "gvm", bus_sl), ("gva", "gva", bus_sl)]
     for gk, ok, sl in pairs:
         if gk not in gres or ok not in ores:

@@ -145,16 +145,18 @@ def test_determinism_across_runs_and_schedules():
     lp, lq = rng.normal(size=vm.shape), rng.normal(size=vm.shape)
     G = pf.Grid.from_grid(g)
     ref = gpu_all(G, vm, va, lp, lq)
+    # every method but copy-add (atomic adds in no fixed order) is bitwise reproducible
+    fixed = [k for k in ref if not k.endswith("_ca")]
     for _ in range(3):
         again = gpu_all(G, vm, va, lp, lq)
-        for k in ref:
+        for k in fixed:
             assert np.array_equal(ref[k], again[k]), k
     for tile in (64, 128, 512):
         for spb in (1, 2):
             for order in (pf.PF_ORDER_TILE_MAJOR, pf.PF_ORDER_STATE_MAJOR):
                 G.set_schedule(tile, spb, order)
                 other = gpu_all(G, vm, va, lp, lq)
-                for k in ref:
+                for k in fixed:
                     assert np.array_equal(ref[k], other[k]), (k, tile, spb, order)
 
 
