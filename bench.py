@@ -388,10 +388,17 @@ def main():
             pf.pf_jacobian_values(d["G"], pf.PF_METHOD_ELEMENTWISE_TWO_PHASE, d["vm"], d["va"], d["p"], d["q"], d["j"],
                                   stream=st)
         ev, wall = timed(tp_sj, K, W)
+
+        def tp_pre(k, st):
+            d = reps[k % R]
+            pf.pf_jacobian_values(d["G"], pf.PF_METHOD_ELEMENTWISE_TWO_PHASE | pf.PF_EW_PRECOMPUTED, d["vm"], d["va"],
+                                  d["p"], d["q"], d["j"], stream=st)
+        ev_pre, _ = timed(tp_pre, K, W)
         extra["ew_two_phase_sj"] = {"evals_per_s": K / wall, "avg_eval_us": ev / K * 1e6,
                                     "achieved_GBs": abytes / (ev / K) / 1e9, "launches_per_eval": 2,
-                                    "fused_speedup": (ev / K) / avg_launch}
-        log(f"two-phase S+J: {ev / K * 1e6:.2f} us/eval")
+                                    "fused_speedup": (ev / K) / avg_launch,
+                                    "precomputed_constants_us": ev_pre / K * 1e6}
+        log(f"two-phase S+J: {ev / K * 1e6:.2f} us/eval (precomputed constants {ev_pre / K * 1e6:.2f})")
 
     if want("copy_add"):
         # copy-add with atomic adds: zero J, shunt terms, one thread per branch adding both ends
@@ -400,10 +407,17 @@ def main():
             pf.pf_jacobian_values(d["G"], pf.PF_METHOD_ELEMENTWISE_ATOMIC, d["vm"], d["va"], d["p"], d["q"], d["j"],
                                   stream=st)
         ev, wall = timed(ca_sj, K, W)
+
+        def ca_pre(k, st):
+            d = reps[k % R]
+            pf.pf_jacobian_values(d["G"], pf.PF_METHOD_ELEMENTWISE_ATOMIC | pf.PF_EW_PRECOMPUTED, d["vm"], d["va"],
+                                  d["p"], d["q"], d["j"], stream=st)
+        ev_pre, _ = timed(ca_pre, K, W)
         extra["ew_copy_add_atomic_sj"] = {"evals_per_s": K / wall, "avg_eval_us": ev / K * 1e6,
                                           "achieved_GBs": abytes / (ev / K) / 1e9, "launches_per_eval": 3,
-                                          "fused_speedup": (ev / K) / avg_launch}
-        log(f"copy-add (atomic) S+J: {ev / K * 1e6:.2f} us/eval")
+                                          "fused_speedup": (ev / K) / avg_launch,
+                                          "precomputed_constants_us": ev_pre / K * 1e6}
+        log(f"copy-add (atomic) S+J: {ev / K * 1e6:.2f} us/eval (precomputed constants {ev_pre / K * 1e6:.2f})")
 
     if want("csc"):
         # the same evaluation with J written in CSC order (what sparse direct solvers take)

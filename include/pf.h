@@ -185,6 +185,14 @@ int pf_injections_ybus(const pf_grid *g, int32_t nstate, const double *vm, const
  *   jval    f64[nstate][nnz_j] device output in the exported CSR order
  *           (CSC with PF_JAC_CSC). */
 enum { PF_JAC_CSC = 0x100 };
+/* OR-ed into PF_METHOD_ELEMENTWISE_TWO_PHASE or PF_METHOD_ELEMENTWISE_ATOMIC:
+ * the branch kernel reads per-branch constants precomputed at build time
+ * (coupling y_hk/m and both ends' own-end admittances, six doubles, the
+ * paper's precomputation, Section IV.C.1) instead of deriving them from
+ * r, x, b, tap on the fly.  Same values; PF_EUNSUP with the other methods
+ * (the fused element-wise kernel always reads precomputed per-record
+ * constants). */
+enum { PF_EW_PRECOMPUTED = 0x200 };
 int pf_jacobian_values(const pf_grid *g, int32_t method, int32_t nstate, const double *vm,
                        const double *va, double *p, double *q, double *jval, void *stream);
 

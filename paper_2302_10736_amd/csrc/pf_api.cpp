@@ -513,7 +513,7 @@ int pf_build_pattern(int32_t nb, int32_t nl, const int32_t *fbus, const int32_t 
         size_t o_gs = ar.take<double>(nb), o_bs = ar.take<double>(nb);
         // two-phase tables
         size_t o_bf = ar.take<int32_t>(nl), o_bt = ar.take<int32_t>(nl), o_brec = ar.take<int32_t>(2 * (size_t)nl),
-               o_jpq = ar.take<int2>(nb);
+               o_jpq = ar.take<int2>(nb), o_bc = ar.take<double>(6 * (size_t)nl);
         e = hipMalloc(&g->dmem, ar.off);
         if (e != hipSuccess) {
             g->dmem = nullptr;
@@ -635,7 +635,9 @@ int pf_build_pattern(int32_t nb, int32_t nl, const int32_t *fbus, const int32_t 
         tp.slot = d.slot;
         tp.yrow = d.yrow;
         tp.jpq = reinterpret_cast<const int2 *>(base + o_jpq);
+        tp.bc = F64(o_bc);
         e = pf::launch_setup_items(s, nullptr);
+        if (e == hipSuccess) e = pf::launch_branch_consts(tp, F64(o_bc), nullptr);
         if (e == hipSuccess) e = hipDeviceSynchronize();
         if (e != hipSuccess) {
             int rc = hip_fail(e, "record constants kernel");
@@ -877,12 +879,15 @@ int pf_jacobian_values(const pf_grid *g, int32_t method, int32_t nstate, const d
     int st = check_eval(g, nstate);
     if (st) return st;
     const bool csc = (method & PF_JAC_CSC) != 0;
-    method &= ~PF_JAC_CSC;
+    const bool pre = (method & PF_EW_PRECOMPUTED) != 0;
+    method &= ~(PF_JAC_CSC | PF_EW_PRECOMPUTED);
     if (method != PF_METHOD_ELEMENTWISE && method != PF_METHOD_YBUS && method != PF_METHOD_ELEMENTWISE_TWO_PHASE &&
         method != PF_METHOD_ELEMENTWISE_ATOMIC)
         return fail(PF_EINVAL, "unknown method");
     if (csc && method != PF_METHOD_ELEMENTWISE)
         return fail(PF_EUNSUP, "the CSC order is available with PF_METHOD_ELEMENTWISE only");
+    if (pre && method != PF_METHOD_ELEMENTWISE_TWO_PHASE && method != PF_METHOD_ELEMENTWISE_ATOMIC)
+        return fail(PF_EUNSUP, "PF_EW_PRECOMPUTED applies to the two-phase and copy-add methods");
     if (method == PF_METHOD_YBUS && !g->ybus_valid)
         return fail(PF_ESTATE, "pf_ybus has not been called on this handle");
     if (nstate > 0 && (!vm || !va || !jval)) return fail(PF_EINVAL, "NULL state or Jacobian pointer");
@@ -896,7 +901,7 @@ int pf_jacobian_values(const pf_grid *g, int32_t method, int32_t nstate, const d
         if (cur != g->device) return fail(PF_EINVAL, "current HIP device differs from the handle's device");
         pf::DevTwoPhase d = g->tp;
         d.ydslot = g->lanes.ydslot;
-        e = pf::launch_copy_add(d, nstate, 4 * g->nnz_y, vm, va, p, q, jval, static_cast<hipStream_t>(stream));
+        e = pf::launch_copy_add(d, nstate, 4 * g->nnz_y, vm, va, p, q, jval, pre, static_cast<hipStream_t>(stream));
         if (e != hipSuccess) return hip_fail(e, "kernel launch");
         return PF_OK;
     }
@@ -910,7 +915,7 @@ int pf_jacobian_values(const pf_grid *g, int32_t method, int32_t nstate, const d
         if (st) return st;
         pf::DevTwoPhase d = g->tp;
         d.ydslot = g->lanes.ydslot;
-        e = pf::launch_two_phase(d, nstate, 4 * g->nnz_y, vm, va, p, q, jval, static_cast<hipStream_t>(stream));
+        e = pf::launch_two_phase(d, nstate, 4 * g->nnz_y, vm, va, p, q, jval, pre, static_cast<hipStream_t>(stream));
         if (e != hipSuccess) return hip_fail(e, "kernel launch");
         return PF_OK;
     }
@@ -1063,7 +1068,8 @@ int pf_graph_create(const pf_grid *g, const pf_op *ops, int32_t nops, pf_graph *
     // kernel launches happens while the stream is captured.
     for (int32_t k = 0; k < nops; ++k) {
         if (ops[k].nstate > 0) auto_states_per_block(g, op_kind(ops[k]), ops[k].nstate);
-        if (ops[k].op == PF_OP_JACOBIAN && ops[k].method == PF_METHOD_ELEMENTWISE_TWO_PHASE) {
+        if (ops[k].op == PF_OP_JACOBIAN &&
+            (ops[k].method & ~(PF_JAC_CSC | PF_EW_PRECOMPUTED)) == PF_METHOD_ELEMENTWISE_TWO_PHASE) {
             const int st0 = ensure_two_phase_scratch(g);
             if (st0) return st0;
         }

@@ -115,6 +115,7 @@ struct DevTwoPhase {
     const int32_t *irow, *item_br, *slot, *yrow, *ydslot;
     const int2 *jpq;                        // [nb] offsets of row i's P and Q parts in one state's J
     double *scr;                            // [10][nrec]
+    const double *bc;                       // [6][nl] precomputed G, B, A_from, C_from, A_to, C_to
 };
 
 enum Kind { K_EW_S = 0, K_EW_SJ = 1, K_YB_S = 2, K_YB_SJ = 3, K_EW_VJP = 4, K_EW_SJ_CSC = 5 };
@@ -152,9 +153,11 @@ hipError_t launch_flows(const DevTwoPhase &d, int32_t nstate, const double *vm, 
 // Copy-add with atomic adds: three launches for all states (zero J, bus
 // shunt terms, per-branch adds); jval 16-byte aligned.
 hipError_t launch_copy_add(const DevTwoPhase &d, int32_t nstate, int64_t nnz_j, const double *vm, const double *va,
-                           double *p, double *q, double *jval, hipStream_t stream);
+                           double *p, double *q, double *jval, bool pre, hipStream_t stream);
+// Precomputed branch constants (d.bc's layout) into bc.
+hipError_t launch_branch_consts(const DevTwoPhase &d, double *bc, hipStream_t stream);
 // States [0, nstate) one after another, two launches each.
 hipError_t launch_two_phase(const DevTwoPhase &d, int32_t nstate, int64_t nnz_j, const double *vm, const double *va,
-                            double *p, double *q, double *jval, hipStream_t stream);
+                            double *p, double *q, double *jval, bool pre, hipStream_t stream);
 
 }  // namespace pf

@@ -997,19 +997,55 @@ __device__ __forceinline__ EndVals branch_end(double vi, double vj, double d, do
     return o;
 }
 
-// Both ends of branch l (from end first) at one state.
+// The constants of branch l's two ends from its parameters (r, x, b, tap,
+// shift): coupling G + jB = y_hk / m and the own-end terms A + jC of the
+// from end ((y_h + y_hk)/m^2) and of the to end (y_k + y_hk), with
+// y_hk = 1/(r + jx) and y_h = y_k = jb/2.
+struct BranchConsts {
+    double G, B, Af, Cf, At, Ct;
+};
+
+__device__ __forceinline__ BranchConsts branch_consts(double r, double x, double b, double tap) {
+    const double den = fma(r, r, x * x);
+    const double gsr = r / den, bsr = -x / den;
+    const double m = tap == 0.0 ? 1.0 : tap;
+    const double bh = 0.5 * b;
+    return {gsr / m, bsr / m, gsr / (m * m), (bh + bsr) / (m * m), gsr, bh + bsr};
+}
+
+// Precomputed branch constants, [6][nl]: the planes of BranchConsts (the
+// paper's precomputation of the per-branch constants, Section IV.C.1).
+__global__ void k_branch_consts(DevTwoPhase d, double *__restrict__ bc) {
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= d.nl) return;
+    const BranchConsts c = branch_consts(d.r[l], d.x[l], d.b[l], d.tap[l]);
+    const size_t n = (size_t)d.nl;
+    bc[0 * n + l] = c.G;
+    bc[1 * n + l] = c.B;
+    bc[2 * n + l] = c.Af;
+    bc[3 * n + l] = c.Cf;
+    bc[4 * n + l] = c.At;
+    bc[5 * n + l] = c.Ct;
+}
+
+// Both ends of branch l (from end first) at one state.  PRE reads the
+// precomputed constants (56 bytes per branch with the shift) instead of
+// deriving them from the parameters (40 bytes); the values are the same.
+template <bool PRE = false>
 __device__ __forceinline__ void branch_ends(const DevTwoPhase &d, int l, const double *vm, const double *va,
                                             EndVals &f, EndVals &t) {
     const int h = d.br_from[l], k = d.br_to[l];
-    const double r = d.r[l], x = d.x[l];
-    const double den = fma(r, r, x * x);
-    const double gsr = r / den, bsr = -x / den;
-    const double m = d.tap[l] == 0.0 ? 1.0 : d.tap[l];
-    const double bh = 0.5 * d.b[l], phi = d.shift[l];
+    BranchConsts c;
+    if constexpr (PRE) {
+        const size_t n = (size_t)d.nl;
+        c = {d.bc[l], d.bc[n + l], d.bc[2 * n + l], d.bc[3 * n + l], d.bc[4 * n + l], d.bc[5 * n + l]};
+    } else {
+        c = branch_consts(d.r[l], d.x[l], d.b[l], d.tap[l]);
+    }
+    const double phi = d.shift[l];
     const double vh = vm[h], th = va[h], vk = vm[k], tk = va[k];
-    const double G = gsr / m, B = bsr / m;
-    f = branch_end(vh, vk, th - tk - phi, gsr / (m * m), (bh + bsr) / (m * m), G, B);
-    t = branch_end(vk, vh, tk - th + phi, gsr, bh + bsr, G, B);
+    f = branch_end(vh, vk, th - tk - phi, c.Af, c.Cf, c.G, c.B);
+    t = branch_end(vk, vh, tk - th + phi, c.At, c.Ct, c.G, c.B);
 }
 
 __device__ __forceinline__ void tp_store(double *sc, int64_t stride, int e, const EndVals &o) {
@@ -1025,11 +1061,12 @@ __device__ __forceinline__ void tp_store(double *sc, int64_t stride, int e, cons
     sc[9 * stride + e] = o.dqvj;
 }
 
+template <bool PRE>
 __global__ void k_tp_branch(DevTwoPhase d, const double *__restrict__ vm, const double *__restrict__ va) {
     const int l = blockIdx.x * blockDim.x + threadIdx.x;
     if (l >= d.nl) return;
     EndVals f, t;
-    branch_ends(d, l, vm, va, f, t);
+    branch_ends<PRE>(d, l, vm, va, f, t);
     tp_store(d.scr, d.nrec, d.br_rec[2 * l], f);
     tp_store(d.scr, d.nrec, d.br_rec[2 * l + 1], t);
 }
@@ -1171,6 +1208,7 @@ __device__ __forceinline__ void ca_add_end(const DevTwoPhase &d, int e, int i, c
     unsafeAtomicAdd(Js + jq + deg + so, o.dqvj);
 }
 
+template <bool PRE>
 __global__ void k_ca_branch(DevTwoPhase d, int nstate, int64_t nnz_j, const double *__restrict__ vm,
                             const double *__restrict__ va, double *P, double *Q, double *J) {
     const int l = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1180,7 +1218,7 @@ __global__ void k_ca_branch(DevTwoPhase d, int nstate, int64_t nnz_j, const doub
     for (int s = blockIdx.y; s < nstate; s += gridDim.y) {
         const size_t sb = (size_t)s * d.nb;
         EndVals f, t;
-        branch_ends(d, l, vm + sb, va + sb, f, t);
+        branch_ends<PRE>(d, l, vm + sb, va + sb, f, t);
         double *Js = J + (size_t)s * (size_t)nnz_j;
         ca_add_end(d, ef, h, f, P ? P + sb : nullptr, Q ? Q + sb : nullptr, Js);
         ca_add_end(d, et, k, t, P ? P + sb : nullptr, Q ? Q + sb : nullptr, Js);
@@ -1391,11 +1429,16 @@ hipError_t launch_lane_fill(const DevLaneFill &f, bool ew, hipStream_t stream) {
 }
 
 hipError_t launch_two_phase(const DevTwoPhase &d, int32_t nstate, int64_t nnz_j, const double *vm, const double *va,
-                            double *p, double *q, double *jval, hipStream_t stream) {
+                            double *p, double *q, double *jval, bool pre, hipStream_t stream) {
     const unsigned gb = (unsigned)((d.nl + 255) / 256), gr = (unsigned)((d.nb + 255) / 256);
     for (int32_t s = 0; s < nstate; ++s) {
         const size_t so = (size_t)s * d.nb;
-        if (d.nl > 0) hipLaunchKernelGGL(k_tp_branch, dim3(gb), dim3(256), 0, stream, d, vm + so, va + so);
+        if (d.nl > 0) {
+            if (pre)
+                hipLaunchKernelGGL(k_tp_branch<true>, dim3(gb), dim3(256), 0, stream, d, vm + so, va + so);
+            else
+                hipLaunchKernelGGL(k_tp_branch<false>, dim3(gb), dim3(256), 0, stream, d, vm + so, va + so);
+        }
         hipLaunchKernelGGL(k_tp_reduce, dim3(gr), dim3(256), 0, stream, d, vm + so, p ? p + so : nullptr,
                            q ? q + so : nullptr, jval + (size_t)s * (size_t)nnz_j);
         const hipError_t e = hipGetLastError();
@@ -1405,7 +1448,7 @@ hipError_t launch_two_phase(const DevTwoPhase &d, int32_t nstate, int64_t nnz_j,
 }
 
 hipError_t launch_copy_add(const DevTwoPhase &d, int32_t nstate, int64_t nnz_j, const double *vm, const double *va,
-                           double *p, double *q, double *jval, hipStream_t stream) {
+                           double *p, double *q, double *jval, bool pre, hipStream_t stream) {
     if (nstate == 0) return hipSuccess;
     const unsigned ys = (unsigned)std::min<int32_t>(nstate, 65535);
     const int64_t n2 = (int64_t)nstate * nnz_j / 2;  // nnz_j = 4 nnz_y is even
@@ -1416,9 +1459,13 @@ hipError_t launch_copy_add(const DevTwoPhase &d, int32_t nstate, int64_t nnz_j, 
     if (d.nb > 0)
         hipLaunchKernelGGL(k_ca_bus, dim3((unsigned)((d.nb + 255) / 256), ys), dim3(256), 0, stream, d, nstate, nnz_j, vm, p,
                            q, jval);
-    if (d.nl > 0)
-        hipLaunchKernelGGL(k_ca_branch, dim3((unsigned)((d.nl + 255) / 256), ys), dim3(256), 0, stream, d, nstate, nnz_j, vm,
-                           va, p, q, jval);
+    if (d.nl > 0) {
+        const dim3 grid((unsigned)((d.nl + 255) / 256), ys);
+        if (pre)
+            hipLaunchKernelGGL(k_ca_branch<true>, grid, dim3(256), 0, stream, d, nstate, nnz_j, vm, va, p, q, jval);
+        else
+            hipLaunchKernelGGL(k_ca_branch<false>, grid, dim3(256), 0, stream, d, nstate, nnz_j, vm, va, p, q, jval);
+    }
     return hipGetLastError();
 }
 
@@ -1443,6 +1490,12 @@ hipError_t launch_phasor(int32_t layout, int64_t n, const double *vm, const doub
         hipLaunchKernelGGL(k_phasor<PH_INTERLEAVED>, dim3((unsigned)blocks), dim3(256), 0, stream, n, vm, va, ph);
     else
         return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_branch_consts(const DevTwoPhase &d, double *bc, hipStream_t stream) {
+    if (d.nl == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_branch_consts, dim3((unsigned)((d.nl + 255) / 256)), dim3(256), 0, stream, d, bc);
     return hipGetLastError();
 }
 

@@ -23,6 +23,7 @@ PF_BUILD_HOST_ONLY = 1
 PF_ORDER_AUTO, PF_ORDER_TILE_MAJOR, PF_ORDER_STATE_MAJOR = 0, 1, 2
 PF_PHASOR_SPLIT, PF_PHASOR_INTERLEAVED = 1, 2
 PF_JAC_CSC = 0x100  # OR into the method of pf_jacobian_values: J values in CSC order
+PF_EW_PRECOMPUTED = 0x200  # OR into the two-phase / copy-add methods: precomputed branch constants
 
 EXPORTS = (
     "pf_build_pattern", "pf_grid_free", "pf_grid_sizes", "pf_pattern_sizes", "pf_grid_offsets",

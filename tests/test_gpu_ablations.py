@@ -221,3 +221,69 @@ def test_csc_other_methods_unsupported():
         with pytest.raises(pf.PFError) as e:
             pf.pf_jacobian_values(G, m | pf.PF_JAC_CSC, vm, vm, None, None, j)
         assert e.value.code == pf.PF_EUNSUP
+
+
+# ------------------------------------------------- precomputed branch constants
+@pytest.mark.parametrize("case", ["config0x3", "parallel_isolated", "hub_600_parallel"])
+def test_precomputed_constants_same_values(case):
+    """PF_EW_PRECOMPUTED reads the constants the branch kernel would derive:
+    the two-phase results are bit-identical, copy-add stays within the gate."""
+    import torch
+    if case == "config0x3":
+        g = gridgen.config0()
+        vm, va = gridgen.states(g.nb, 3, cfg=0)
+    else:
+        g = (_grids.random_small(80, 150, 21, parallel=9, isolated=4) if case == "parallel_isolated"
+             else star_grid(600, seed=2, parallel=40))
+        vm, va = _grids.random_state(g.nb, 3)
+        vm, va = vm[None, :], va[None, :]
+    G = pf.Grid.from_grid(g)
+    ns = vm.shape[0]
+    vmd, vad = to_dev(vm), to_dev(va)
+    out = {}
+    for name, m in (("tp", pf.PF_METHOD_ELEMENTWISE_TWO_PHASE),
+                    ("tp_pre", pf.PF_METHOD_ELEMENTWISE_TWO_PHASE | pf.PF_EW_PRECOMPUTED),
+                    ("ca_pre", pf.PF_METHOD_ELEMENTWISE_ATOMIC | pf.PF_EW_PRECOMPUTED)):
+        p, q = torch.full_like(vmd, np.nan), torch.full_like(vmd, np.nan)
+        j = torch.full((ns, G.nnz_j), np.nan, dtype=torch.float64, device="cuda:0")
+        pf.pf_jacobian_values(G, m, vmd, vad, p, q, j)
+        torch.cuda.synchronize()
+        out[name] = (p.cpu().numpy(), q.cpu().numpy(), j.cpu().numpy())
+    for a, b in zip(out["tp"], out["tp_pre"]):
+        assert np.array_equal(a, b)
+    yb = oracle.ybus(g)
+    pat = oracle.jac_pattern(yb)
+    scale = None
+    for s in range(ns):
+        po, qo = oracle.inject_ew(g, vm[s], va[s])
+        jo = oracle.jac_ew(g, vm[s], va[s], pat)
+        p, q, j = (x[s] for x in out["ca_pre"])
+        assert rel_err(p, po, scale) <= TOL and rel_err(q, qo, scale) <= TOL and rel_err(j, jo, scale) <= TOL
+
+
+def test_precomputed_flag_scope_and_graphs():
+    import torch
+    G = pf.Grid.from_grid(gridgen.config0())
+    pf.pf_ybus(G)
+    vm = to_dev(np.ones((2, G.nb)))
+    va = to_dev(np.zeros((2, G.nb)))
+    j = torch.empty(2, G.nnz_j, dtype=torch.float64, device="cuda:0")
+    for m in (pf.PF_METHOD_ELEMENTWISE, pf.PF_METHOD_YBUS):
+        with pytest.raises(pf.PFError) as e:
+            pf.pf_jacobian_values(G, m | pf.PF_EW_PRECOMPUTED, vm, va, None, None, j)
+        assert e.value.code == pf.PF_EUNSUP
+    # a recorded two-phase evaluation with precomputed constants (its scratch is
+    # allocated before recording) replays to the eager result
+    vm = to_dev(gridgen.states(G.nb, 2, cfg=0)[0])
+    va = to_dev(gridgen.states(G.nb, 2, cfg=0)[1])
+    m = pf.PF_METHOD_ELEMENTWISE_TWO_PHASE | pf.PF_EW_PRECOMPUTED
+    j_eager = torch.empty_like(j)
+    pf.pf_jacobian_values(G, m, vm, va, None, None, j_eager)
+    G2 = pf.Grid.from_grid(gridgen.config0())  # fresh handle: no scratch yet
+    gr = pf.Graph(G2, [dict(op=pf.PF_OP_JACOBIAN, method=m, vm=vm, va=va, jval=j)])
+    for _ in range(3):
+        j.fill_(float("nan"))
+        gr.launch()
+        torch.cuda.synchronize()
+        assert torch.equal(j, j_eager)
+    gr.close()
