@@ -44,6 +44,19 @@ def _reduced_index(nb, bus_type):
     return pvpq, pq, rows, cols
 
 
+def _reduced_map(jr, jc, rows, cols):
+    """The reduced matrix (rows and columns of the unknowns) keeps one
+    sparsity pattern: where each of its CSC entries sits in the full CSR
+    value array, and its CSC index arrays.  Every iteration then forms it
+    with one gather."""
+    import scipy.sparse as sp
+    n = len(jr) - 1
+    idx = sp.csr_matrix((np.arange(1, len(jc) + 1, dtype=np.float64), jc, jr), shape=(n, n))
+    red = idx[rows][:, cols].tocsc()
+    red.sort_indices()
+    return red.data.astype(np.int64) - 1, red.indices, red.indptr, red.shape
+
+
 def solve(grid: "pf.Grid", bus_type, p_spec, q_spec, vm0, va0, method: int = pf.PF_METHOD_ELEMENTWISE,
           tol: float = 1e-10, max_iter: int = 20) -> NewtonResult:
     """Solve S(v, theta) = p_spec + j q_spec on the PV and PQ rows.
@@ -67,6 +80,7 @@ def solve(grid: "pf.Grid", bus_type, p_spec, q_spec, vm0, va0, method: int = pf.
         raise ValueError("one grid per handle (the pattern export is grid-local)")
     pvpq, pq, rows, cols = _reduced_index(nb, bus_type)
     n1 = len(pvpq)
+    take, r_ind, r_ptr, r_shape = _reduced_map(jr, jc, rows, cols)
     vm = torch.as_tensor(np.asarray(vm0, dtype=np.float64), device=dev).clone()
     va = torch.as_tensor(np.asarray(va0, dtype=np.float64), device=dev).clone()
     p = torch.empty(nb, dtype=torch.float64, device=dev)
@@ -89,8 +103,7 @@ def solve(grid: "pf.Grid", bus_type, p_spec, q_spec, vm0, va0, method: int = pf.
             break
         if it == max_iter:
             break
-        J = sp.csr_matrix((jv, jc, jr), shape=(2 * nb, 2 * nb))
-        Jr = J[rows][:, cols].tocsc()
+        Jr = sp.csc_matrix((jv[take], r_ind, r_ptr), shape=r_shape)
         dx = spla.spsolve(Jr, -F)
         res.seconds_solve += time.perf_counter() - t1
         upd_a = np.zeros(nb)

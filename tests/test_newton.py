@@ -16,6 +16,23 @@ def test_reduced_index():
     assert rows.tolist() == [1, 2, 3, 5, 7] and cols.tolist() == [1, 2, 3, 5, 7]
 
 
+def test_reduced_map_matches_slicing():
+    import scipy.sparse as sp
+    g = gridgen.config0()
+    yb = oracle.ybus(g)
+    jr, jc = oracle.jac_pattern(yb)
+    vm, va = gridgen.states(g.nb, 1, cfg=0)
+    jv = oracle.jac_ew(g, vm[0], va[0], (jr, jc))
+    bt = np.full(g.nb, newton.PQ)
+    bt[::5] = newton.PV
+    bt[0] = newton.SLACK
+    _, _, rows, cols = newton._reduced_index(g.nb, bt)
+    take, ind, ptr, shape = newton._reduced_map(jr, jc, rows, cols)
+    A = sp.csc_matrix((jv[take], ind, ptr), shape=shape)
+    B = sp.csr_matrix((jv, jc, jr), shape=(2 * g.nb, 2 * g.nb))[rows][:, cols].tocsc()
+    assert A.shape == B.shape and A.nnz == B.nnz and abs(A - B).max() == 0.0
+
+
 def test_case_from_state():
     g = gridgen.config0()
     vm, va = gridgen.states(g.nb, 1, cfg=0)
