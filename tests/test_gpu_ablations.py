@@ -287,3 +287,16 @@ def test_precomputed_flag_scope_and_graphs():
         torch.cuda.synchronize()
         assert torch.equal(j, j_eager)
     gr.close()
+
+
+def test_variants_config1_full_size():
+    """The 100k-bus benchmark grid: CSC output and both stored-phasor layouts
+    against the fused kernels, bit for bit, and the fused kernels' oracle
+    parity (covered in test_gpu_parity) carries over."""
+    g = gridgen.config1()
+    vm, va = gridgen.states(g.nb, 1, cfg=1)
+    _csc_case(g, vm, va, 256, 0)
+    for layout in LAYOUTS:
+        r = _phasor_case(g, vm, va, 256, 0, layout)
+        assert np.array_equal(r["p1"], r["p0"]) and np.array_equal(r["q1"], r["q0"])
+        assert np.array_equal(r["j1"], r["j0"]) and np.array_equal(r["p2"], r["ps"])
