@@ -241,13 +241,15 @@ int pf_branch_flows(const pf_grid *g, int32_t nstate, const double *vm, const do
  *                     element-wise work tile, Ybus nonzeros per Ybus tile
  *   states_per_block  voltage states one workgroup evaluates in turn, with
  *                     the tile's constants held in registers (>= 1; 0 =
- *                     automatic)
+ *                     automatic: at most 2 for Jacobian launches, at most 8
+ *                     for injections and the adjoint, fewer when the tiles
+ *                     alone do not fill the GPU)
  *   order             order of the (tile, state chunk) work items over the
- *                     workgroups: PF_ORDER_AUTO, PF_ORDER_TILE_MAJOR (the
- *                     state chunks of one tile are adjacent) or
- *                     PF_ORDER_STATE_MAJOR (the tiles of one state chunk are
- *                     adjacent, so concurrent workgroups write neighbouring
- *                     parts of J)
+ *                     workgroups: PF_ORDER_TILE_MAJOR (the state chunks of
+ *                     one tile are adjacent), PF_ORDER_STATE_MAJOR (the tiles
+ *                     of one state chunk are adjacent, so concurrent
+ *                     workgroups write neighbouring parts of J) or
+ *                     PF_ORDER_AUTO (= state-major)
  * Changing the schedule never changes results.  Rebuilds the tile list on
  * the host and device; not for use while work on the handle is in flight.
  * Graphs recorded before the call must be recorded again. */

@@ -767,21 +767,27 @@ int check_eval(const pf_grid *g, int32_t nstate) {
 
 // States per workgroup.  A workgroup keeps its tile's record constants in
 // registers and walks its states one after another, so fewer, longer
-// workgroups read the constants fewer times.  The automatic choice fills the
-// GPU with exactly one round of resident workgroups (no tail), i.e. it
-// splits the states of each tile into about (resident capacity / tiles)
-// chunks.
+// workgroups read the constants fewer times, while more, shorter workgroups
+// keep more of every state's output stream in flight.  The automatic choice
+// takes at most 2 states per workgroup for Jacobian launches (their time is
+// the J stream: 8 nnzJ bytes per state against a few bytes of constants) and
+// at most 8 for injections and the adjoint (small per-state outputs, so
+// reusing the constants pays), and fewer when the tiles alone would leave
+// part of one round of resident workgroups empty (it then splits each tile's
+// states into about resident capacity / tiles chunks).
 int auto_states_per_block(const pf_grid *g, int kind, int32_t nstate) {
     if (g->states_per_block > 0) return std::min<int32_t>(g->states_per_block, std::max(nstate, 1));
     if (nstate <= 1) return 1;
     const bool yb = kind == pf::K_YB_S || kind == pf::K_YB_SJ;
+    const bool with_j = kind == pf::K_EW_SJ || kind == pf::K_YB_SJ || kind == pf::K_EW_SJ_CSC;
     const int64_t nt = std::max<int64_t>(1, (int64_t)(yb ? g->ytiles : g->tiles).size());
     int per_cu = pf::resident_blocks_per_cu(kind, g->tile_items, g->has_parallel);
     if (per_cu <= 0) per_cu = 4;
     const int64_t capacity = (int64_t)std::max(g->num_cus, 1) * per_cu;
     int64_t chunks = std::max<int64_t>(1, capacity / nt);
     chunks = std::min<int64_t>(chunks, nstate);
-    return (int)((nstate + chunks - 1) / chunks);
+    const int fill = (int)((nstate + chunks - 1) / chunks);
+    return std::min(fill, with_j ? 2 : 8);
 }
 
 // Scratch of the two-phase element-wise method: ten values per record,
@@ -804,7 +810,7 @@ int run(const pf_grid *g, pf::Launch &L, void *stream) {
     L.tile_items = g->tile_items;
     L.has_parallel = g->has_parallel;
     L.states_per_block = auto_states_per_block(g, L.kind, L.nstate);
-    L.state_major = g->order == PF_ORDER_STATE_MAJOR;
+    L.state_major = g->order != PF_ORDER_TILE_MAJOR;  // automatic = state-major (one state's J written together)
     if (L.nstate == 0) return PF_OK;
     int cur = -1;
     hipError_t e = hipGetDevice(&cur);

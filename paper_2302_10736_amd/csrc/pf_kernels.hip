@@ -117,16 +117,24 @@ __device__ __forceinline__ Cx cmul(Cx a, Cx b) {
 __device__ __forceinline__ Cx cconj(Cx a) { return {a.re, -a.im}; }
 __device__ __forceinline__ Cx cadd(Cx a, Cx b) { return {a.re + b.re, a.im + b.im}; }
 
+// Results are written once and never read back by the kernel that writes
+// them.  Streaming (nontemporal) stores pass them on towards memory at once
+// instead of leaving them dirty in L2, where the write-back at the end of the
+// kernel would only start after the last workgroup has finished.
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void st_out(double *p, double v) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void st_out2(dvec2 *p, dvec2 v) { __builtin_nontemporal_store(v, p); }
+
 // Copy a staged tile of J rows (LDS, slot capacity NS) to global memory
 // with 16-byte stores.
 template <int NT, int NS>
 __device__ __forceinline__ void write_jrows(const Tile &c, const double *s_J, double *Js) {
-    const double2 *src = reinterpret_cast<const double2 *>(s_J);
-    double2 *dp = reinterpret_cast<double2 *>(Js + c.jp);
-    double2 *dq = reinterpret_cast<double2 *>(Js + c.jq);
+    const dvec2 *src = reinterpret_cast<const dvec2 *>(s_J);
+    dvec2 *dp = reinterpret_cast<dvec2 *>(Js + c.jp);
+    dvec2 *dq = reinterpret_cast<dvec2 *>(Js + c.jq);
     for (int q = threadIdx.x; q < c.ns; q += NT) {
-        dp[q] = src[q];
-        dq[q] = src[kQ<NS> / 2 + q];
+        st_out2(dp + q, src[q]);
+        st_out2(dq + q, src[kQ<NS> / 2 + q]);
     }
 }
 
@@ -329,10 +337,10 @@ __device__ __forceinline__ void ew_eval(const DevGrid &g, int nstate, int spb, i
                             if (ls != cur) {
                                 // a finished slot; the diagonal slot's zeros are overwritten below
                                 if (cur >= 0) {
-                                    Js[c.jp + cur] = racc[0];
-                                    Js[c.jp + d + cur] = racc[1];
-                                    Js[c.jq + cur] = racc[2];
-                                    Js[c.jq + d + cur] = racc[3];
+                                    st_out(Js + c.jp + cur, racc[0]);
+                                    st_out(Js + c.jp + d + cur, racc[1]);
+                                    st_out(Js + c.jq + cur, racc[2]);
+                                    st_out(Js + c.jq + d + cur, racc[3]);
                                 }
                                 cur = ls;
                                 racc[0] = racc[1] = racc[2] = racc[3] = 0.0;
@@ -349,21 +357,21 @@ __device__ __forceinline__ void ew_eval(const DevGrid &g, int nstate, int spb, i
             if (k == 0) {
                 const EwRow o = ew_row(vi, dA, dC, as, bs);
                 if (P) {
-                    P[(size_t)s * nb + i] = o.p;
-                    Q[(size_t)s * nb + i] = o.q;
+                    st_out(P + (size_t)s * nb + i, o.p);
+                    st_out(Q + (size_t)s * nb + i, o.q);
                 }
                 if constexpr (WITH_J) {
                     if (cur >= 0) {
-                        Js[c.jp + cur] = racc[0];
-                        Js[c.jp + d + cur] = racc[1];
-                        Js[c.jq + cur] = racc[2];
-                        Js[c.jq + d + cur] = racc[3];
+                        st_out(Js + c.jp + cur, racc[0]);
+                        st_out(Js + c.jp + d + cur, racc[1]);
+                        st_out(Js + c.jq + cur, racc[2]);
+                        st_out(Js + c.jq + d + cur, racc[3]);
                     }
                     const int ld = s_dslot[0];
-                    Js[c.jp + ld] = o.j11;
-                    Js[c.jp + d + ld] = CSC ? o.j21 : o.j12;
-                    Js[c.jq + ld] = CSC ? o.j12 : o.j21;
-                    Js[c.jq + d + ld] = o.j22;
+                    st_out(Js + c.jp + ld, o.j11);
+                    st_out(Js + c.jp + d + ld, CSC ? o.j21 : o.j12);
+                    st_out(Js + c.jq + ld, CSC ? o.j12 : o.j21);
+                    st_out(Js + c.jq + d + ld, o.j22);
                 }
             }
             __syncthreads();
@@ -453,8 +461,8 @@ __device__ __forceinline__ void ew_eval(const DevGrid &g, int nstate, int spb, i
             }
         }
         if (P && rowt) {
-            P[(size_t)s * nb + ir] = o.p;
-            Q[(size_t)s * nb + ir] = o.q;
+            st_out(P + (size_t)s * nb + ir, o.p);
+            st_out(Q + (size_t)s * nb + ir, o.q);
         }
         if constexpr (WITH_J) {
             lds_barrier();
@@ -494,14 +502,14 @@ __global__ void k_phasor(int64_t n, const double *__restrict__ vm, const double 
     sincos_dev(va[i], &sn, &cs);
     const double v = vm[i];
     if constexpr (PH == PH_SPLIT) {
-        ph[i] = v * cs;
-        ph[n + i] = v * sn;
-        ph[2 * n + i] = cs;
-        ph[3 * n + i] = sn;
+        st_out(ph + i, v * cs);
+        st_out(ph + n + i, v * sn);
+        st_out(ph + 2 * n + i, cs);
+        st_out(ph + 3 * n + i, sn);
     } else {
-        double2 *p2 = reinterpret_cast<double2 *>(ph);
-        p2[i] = make_double2(v * cs, v * sn);
-        p2[n + i] = make_double2(cs, sn);
+        dvec2 *p2 = reinterpret_cast<dvec2 *>(ph);
+        st_out2(p2 + i, dvec2{v * cs, v * sn});
+        st_out2(p2 + n + i, dvec2{cs, sn});
     }
 }
 
@@ -633,8 +641,8 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? 6
             const Cx Ic = {s_vu[0][0][0], -s_vu[0][1][0]};  // conj(I_i)
             if (k == 0 && P) {
                 const Cx S = cmul(Vi, Ic);
-                P[(size_t)s * nb + i] = S.re;
-                Q[(size_t)s * nb + i] = S.im;
+                st_out(P + (size_t)s * nb + i, S.re);
+                st_out(Q + (size_t)s * nb + i, S.im);
             }
             if constexpr (WITH_J) {
                 double *Js = J + (size_t)s * (size_t)g.nnz_j;
@@ -652,10 +660,10 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? 6
                     const Cx dst = cmul({-Vi.im, Vi.re}, x);                                  // j V_i x
                     Cx dsv = cmul(Vi, cconj(cmul(Y, Uj)));
                     if (dg) dsv = cadd(dsv, cmul(Ic, Ui));
-                    Js[c.jp + lp] = dst.re;
-                    Js[c.jp + d + lp] = dsv.re;
-                    Js[c.jq + lp] = dst.im;
-                    Js[c.jq + d + lp] = dsv.im;
+                    st_out(Js + c.jp + lp, dst.re);
+                    st_out(Js + c.jp + d + lp, dsv.re);
+                    st_out(Js + c.jq + lp, dst.im);
+                    st_out(Js + c.jq + d + lp, dsv.im);
                 }
             }
             __syncthreads();
@@ -727,8 +735,8 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? 6
             s_J[p][kQ<NT> + o12] = dvo.im;
         }
         if (P && rowt) {  // stores last (see k_ew)
-            P[(size_t)s * nb + ir] = S.re;
-            Q[(size_t)s * nb + ir] = S.im;
+            st_out(P + (size_t)s * nb + ir, S.re);
+            st_out(Q + (size_t)s * nb + ir, S.im);
         }
         if constexpr (WITH_J) {
             lds_barrier();
@@ -830,8 +838,8 @@ __global__ void __launch_bounds__(NT)
             }
             if (k == 0) {
                 const double vi = vm[so + i];
-                gva[so + i] = acc_a;
-                gvm[so + i] = vjp_own(acc_v, vi, lp[so + i], lq[so + i], dA, dC);
+                st_out(gva + so + i, acc_a);
+                st_out(gvm + so + i, vjp_own(acc_v, vi, lp[so + i], lq[so + i], dA, dC));
             }
         }
         return;
@@ -870,8 +878,8 @@ __global__ void __launch_bounds__(NT)
         const double gm = vjp_own(v, in.vr, in.lpr, in.lqr, dA, dC);
         if (rowt) {
             const size_t so = (size_t)s * nb;
-            gva[so + ir] = a;
-            gvm[so + ir] = gm;
+            st_out(gva + so + ir, a);
+            st_out(gvm + so + ir, gm);
         }
     };
     pipelined_states<In, ONE>(sb, se, first, load, proc);
@@ -1048,6 +1056,7 @@ __device__ __forceinline__ void branch_ends(const DevTwoPhase &d, int l, const d
     t = branch_end(vk, vh, tk - th + phi, c.At, c.Ct, c.G, c.B);
 }
 
+// Plain stores: the reduction kernel reads the scratch right after, from cache.
 __device__ __forceinline__ void tp_store(double *sc, int64_t stride, int e, const EndVals &o) {
     sc[0 * stride + e] = o.p;
     sc[1 * stride + e] = o.q;
@@ -1084,17 +1093,17 @@ __global__ void k_flows(DevTwoPhase d, int nstate, const double *__restrict__ vm
         const size_t sb = (size_t)s * d.nb, sl = (size_t)s * d.nl;
         EndVals f, t;
         branch_ends(d, l, vm + sb, va + sb, f, t);
-        pf[sl + l] = f.p;
-        qf[sl + l] = f.q;
-        pt[sl + l] = t.p;
-        qt[sl + l] = t.q;
+        st_out(pf + sl + l, f.p);
+        st_out(qf + sl + l, f.q);
+        st_out(pt + sl + l, t.p);
+        st_out(qt + sl + l, t.q);
         if constexpr (WITH_J) {
             // rows d(Pf, Qf, Pt, Qt) / d(theta_from, theta_to, v_from, v_to)
             const double v[16] = {f.dpti, f.dptj, f.dpvi, f.dpvj, f.dqti, f.dqtj, f.dqvi, f.dqvj,
                                   t.dptj, t.dpti, t.dpvj, t.dpvi, t.dqtj, t.dqti, t.dqvj, t.dqvi};
             double *js = jac + (size_t)s * 16 * d.nl;
 #pragma unroll
-            for (int q = 0; q < 16; ++q) js[(size_t)q * d.nl + l] = v[q];
+            for (int q = 0; q < 16; ++q) st_out(js + (size_t)q * d.nl + l, v[q]);
         }
     }
 }
@@ -1113,10 +1122,10 @@ __global__ void k_tp_reduce(DevTwoPhase d, const double *__restrict__ vm, double
     int cur = -1;
     auto flush = [&]() {
         if (cur < 0) return;
-        J[jp + cur] = a0;
-        J[jp + deg + cur] = a1;
-        J[jq + cur] = a2;
-        J[jq + deg + cur] = a3;
+        st_out(J + jp + cur, a0);
+        st_out(J + jp + deg + cur, a1);
+        st_out(J + jq + cur, a2);
+        st_out(J + jq + deg + cur, a3);
     };
     for (int e = d.irow[i]; e < d.irow[i + 1]; ++e) {
         if (d.item_br[e] < 0) {  // the bus shunt, at its sorted place
@@ -1146,13 +1155,13 @@ __global__ void k_tp_reduce(DevTwoPhase d, const double *__restrict__ vm, double
     }
     flush();
     const int dp = d.ydslot[i] - y0;
-    J[jp + dp] = o0;
-    J[jp + deg + dp] = o1;
-    J[jq + dp] = o2;
-    J[jq + deg + dp] = o3;
+    st_out(J + jp + dp, o0);
+    st_out(J + jp + deg + dp, o1);
+    st_out(J + jq + dp, o2);
+    st_out(J + jq + deg + dp, o3);
     if (P) {
-        P[i] = p;
-        Q[i] = q;
+        st_out(P + i, p);
+        st_out(Q + i, q);
     }
 }
 
@@ -1166,7 +1175,7 @@ __global__ void k_tp_reduce(DevTwoPhase d, const double *__restrict__ vm, double
 // order, so results match the other methods to rounding only.
 __global__ void k_ca_zero(int64_t n2, double2 *__restrict__ J) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += (int64_t)gridDim.x * blockDim.x)
-        J[i] = make_double2(0.0, 0.0);
+        st_out2(reinterpret_cast<dvec2 *>(J + i), dvec2{0.0, 0.0});
 }
 
 __global__ void k_ca_bus(DevTwoPhase d, int nstate, int64_t nnz_j, const double *__restrict__ vm,
@@ -1179,12 +1188,12 @@ __global__ void k_ca_bus(DevTwoPhase d, int nstate, int64_t nnz_j, const double 
     for (int s = blockIdx.y; s < nstate; s += gridDim.y) {
         const double v = vm[(size_t)s * d.nb + i];
         if (P) {
-            P[(size_t)s * d.nb + i] = (v * v) * gg;
-            Q[(size_t)s * d.nb + i] = -((v * v) * bb);
+            st_out(P + (size_t)s * d.nb + i, (v * v) * gg);
+            st_out(Q + (size_t)s * d.nb + i, -((v * v) * bb));
         }
         double *Js = J + (size_t)s * (size_t)nnz_j;
-        Js[jp + deg + dp] = (2.0 * v) * gg;
-        Js[jq + deg + dp] = -((2.0 * v) * bb);
+        st_out(Js + jp + deg + dp, (2.0 * v) * gg);
+        st_out(Js + jq + deg + dp, -((2.0 * v) * bb));
     }
 }
 
