@@ -157,7 +157,7 @@ void build_tiles(pf_grid *g, int NT) {
 // row are adjacent, as are J21 and J22).
 struct HostLanes {
     std::vector<int32_t> lane_j, lane_rec, lane_pk, lane_run;
-    std::vector<int32_t> ylane_j, ylane_slot, ylane_pk;  // ylane_pk: pairs
+    std::vector<int32_t> ylane_j, ylane_slot, ylane_pk;
     std::vector<int32_t> row_ew, row_yb;                 // pairs per bus, + one inert entry at nb
     std::vector<int32_t> ydslot;                         // [nb] global Ybus slot of each diagonal
 };
@@ -173,7 +173,7 @@ HostLanes build_lanes(const pf_grid *g) {
     h.lane_run.assign(g->has_parallel ? nle : 1, 0);
     h.ylane_j.assign(nly, 0);
     h.ylane_slot.assign(nly, -1);
-    h.ylane_pk.assign(2 * nly, 0);
+    h.ylane_pk.assign(nly, pf::yb_pack(ypad, ypad, 0, false));
     // Entry nb is what lanes without a row read: empty ranges, pad targets.
     h.row_ew.assign(2 * ((size_t)g->nb + 1), 0);
     h.row_yb.assign(2 * ((size_t)g->nb + 1), 0);
@@ -218,10 +218,7 @@ HostLanes build_lanes(const pf_grid *g) {
     for (size_t t = 0; t < g->ytiles.size(); ++t) {
         const pf::TileDesc &c = g->ytiles[t];
         const size_t base = t * NT;
-        for (int k = 0; k < NT; ++k) {
-            h.ylane_j[base + k] = c.r0;
-            h.ylane_pk[2 * (base + k)] = ypad | (ypad << 16);
-        }
+        for (int k = 0; k < NT; ++k) h.ylane_j[base + k] = c.r0;
         if (c.ns > NT) continue;
         for (int32_t row = 0; row < c.nrows; ++row) {
             const int32_t i = c.r0 + row;
@@ -234,8 +231,7 @@ HostLanes build_lanes(const pf_grid *g) {
                 const bool dg = g->ycol[q] == i;
                 h.ylane_j[L] = g->ycol[q];
                 h.ylane_slot[L] = q;
-                h.ylane_pk[2 * L] = dg ? (ypad | (ypad << 16)) : ((ya + ls) | ((yz + ls) << 16));
-                h.ylane_pk[2 * L + 1] = row | ((dg ? 1 : 0) << 16);
+                h.ylane_pk[L] = dg ? pf::yb_pack(ypad, ypad, row, true) : pf::yb_pack(ya + ls, yz + ls, row, false);
             }
         }
     }
@@ -259,9 +255,9 @@ int upload_tiles(pf_grid *g) {
     const size_t o_lj = ar.take<int32_t>(nle), o_lrec = ar.take<int32_t>(nle), o_lpk = ar.take<int32_t>(nle);
     const size_t o_lrun = ar.take<int32_t>(nrun);
     const size_t o_lgb = ar.take<double2>(nle), o_lgr = ar.take<double2>(nle), o_rew = ar.take<int2>(g->nb + 1);
-    const size_t o_yj = ar.take<int32_t>(nly), o_yslot = ar.take<int32_t>(nly), o_ypk = ar.take<int2>(nly);
+    const size_t o_yj = ar.take<int32_t>(nly), o_yslot = ar.take<int32_t>(nly), o_ypk = ar.take<int32_t>(nly);
     const size_t o_yy = ar.take<double2>(nly), o_ryb = ar.take<int2>(g->nb + 1);
-    const size_t o_yds = ar.take<int32_t>(g->nb), o_ydg = ar.take<double2>(g->nb + 1);
+    const size_t o_yds = ar.take<int32_t>(g->nb);
     e = hipMalloc(&g->dtile, ar.off);
     if (e != hipSuccess) {
         g->dtile = nullptr;
@@ -282,7 +278,7 @@ int upload_tiles(pf_grid *g) {
     up(o_rew, h.row_ew.data(), ((size_t)g->nb + 1) * 8);
     up(o_yj, h.ylane_j.data(), nly * 4);
     up(o_yslot, h.ylane_slot.data(), nly * 4);
-    up(o_ypk, h.ylane_pk.data(), nly * 8);
+    up(o_ypk, h.ylane_pk.data(), nly * 4);
     up(o_ryb, h.row_yb.data(), ((size_t)g->nb + 1) * 8);
     up(o_yds, h.ydslot.data(), (size_t)g->nb * 4);
     if (ee != hipSuccess) return hip_fail(ee, "hipMemcpy(schedule)");
@@ -298,10 +294,9 @@ int upload_tiles(pf_grid *g) {
     d.lane_grbr = reinterpret_cast<const double2 *>(base + o_lgr);
     d.row_ew = reinterpret_cast<const int2 *>(base + o_rew);
     d.ylane_j = reinterpret_cast<const int32_t *>(base + o_yj);
-    d.ylane_pk = reinterpret_cast<const int2 *>(base + o_ypk);
+    d.ylane_pk = reinterpret_cast<const int32_t *>(base + o_ypk);
     d.ylane_y = reinterpret_cast<const double2 *>(base + o_yy);
     d.row_yb = reinterpret_cast<const int2 *>(base + o_ryb);
-    d.ydiag = reinterpret_cast<const double2 *>(base + o_ydg);
     pf::DevLaneFill &f = g->lanes;
     f.nlanes = (int64_t)nle;
     f.nylanes = (int64_t)nly;
@@ -318,7 +313,6 @@ int upload_tiles(pf_grid *g) {
     f.ylane_y = reinterpret_cast<double2 *>(base + o_yy);
     f.nb = g->nb;
     f.ydslot = reinterpret_cast<const int32_t *>(base + o_yds);
-    f.ydiag = reinterpret_cast<double2 *>(base + o_ydg);
     // Record constants exist once the setup kernels ran; Ybus values once
     // pf_ybus ran.  Until then the Ybus lanes stay unfilled and the Ybus
     // evaluation calls refuse to run.

@@ -28,6 +28,12 @@ constexpr int kEwSlots(int NT) { return NT + NT / 2; }
 // 2 kEwSlots(512) = 1536) and the tile row (9 bits, < 512).
 constexpr int32_t ew_pack(int32_t o11, int32_t o12, int32_t row) { return o11 | (o12 << 11) | (row << 22); }
 
+// Ybus lane word: LDS targets o11, o12 (11 bits each, at most 2 * 512 + 1),
+// the tile row (9 bits) and the diagonal flag (the sign bit).
+constexpr int32_t yb_pack(int32_t o11, int32_t o12, int32_t row, bool diag) {
+    return (int32_t)((uint32_t)o11 | ((uint32_t)o12 << 11) | ((uint32_t)row << 22) | (diag ? 0x80000000u : 0u));
+}
+
 // Device view of a handle, passed to kernels by value.
 //
 // Records ("items") are the unit of the element-wise method: one per branch
@@ -65,10 +71,9 @@ struct DevGrid {
     const double2 *lane_grbr;   // {Gr, Br}
     const int2 *row_ew;         // [nb+1] {ra | rz << 16, d11 | d12 << 16}; [nb] inert
     const int32_t *ylane_j;     // Ybus nonzero: column bus
-    const int2 *ylane_pk;       // {o11 | o12 << 16, row | diag << 16}
+    const int32_t *ylane_pk;    // yb_pack(o11, o12, row, diag)
     const double2 *ylane_y;     // {Re Y, Im Y}
     const int2 *row_yb;         // [nb+1] {ya | yz << 16, dls}; [nb] inert
-    const double2 *ydiag;       // [nb+1] Ybus diagonal of each bus; [nb] = 0
 };
 
 // Gather sources of the lane tables: record (element-wise) and slot (Ybus)
@@ -80,7 +85,6 @@ struct DevLaneFill {
     const int32_t *ydslot;  // [nb] global slot of each bus's diagonal
     const double *G, *B, *Gr, *Br, *yre, *yim;
     double2 *lane_gb, *lane_grbr, *ylane_y;
-    double2 *ydiag;  // [nb+1]
 };
 
 // Setup data, only read by the setup kernels.

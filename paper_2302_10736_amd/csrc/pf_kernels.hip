@@ -138,6 +138,11 @@ __device__ __forceinline__ void write_jrows(const Tile &c, const double *s_J, do
     }
 }
 
+// Fields of a Ybus lane word (yb_pack): LDS targets as ew_o11 / ew_o12,
+// then the tile row and the diagonal flag.
+__device__ __forceinline__ int yb_row(int v) { return (v >> 22) & 0x1ff; }
+__device__ __forceinline__ bool yb_diag(int v) { return v < 0; }
+
 // Fields of an element-wise lane word (ew_pack).
 __device__ __forceinline__ int ew_o11(int v) { return v & 0x7ff; }
 __device__ __forceinline__ int ew_o12(int v) { return (v >> 11) & 0x7ff; }
@@ -586,6 +591,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? 6
     constexpr int NBUF = ONE ? 1 : 2;
     __shared__ double s_yv[NBUF][2][NT];  // Y_ij V_j
     __shared__ double s_vu[NBUF][4][NT];  // per row: V_i, U_i (re, im)
+    __shared__ double s_yd[WITH_J ? 2 : 1][WITH_J ? NT : 1];  // per row: Y_ii (state-free, written once)
     __shared__ __align__(16) double s_J[NBUF][WITH_J ? kJStage<NT> : 2];
 
     const int W = g.nytiles * nchunk;
@@ -597,7 +603,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? 6
     const int k = threadIdx.x;
     const size_t lane = (size_t)t * NT + k;
     const int j = g.ylane_j[lane];
-    const int2 pk = g.ylane_pk[lane];
+    const int pk = g.ylane_pk[lane];
     const double2 yl = g.ylane_y[lane];
     const Tile c = g.ytiles[t];
     const size_t nb = (size_t)g.nb;
@@ -674,10 +680,16 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? 6
     // ---- packed tile: lane k holds nonzero c.s0 + k (inert past c.ns) with
     // its column bus, tile row, diagonal flag and LDS targets (the pad for
     // the diagonal nonzero, whose entries the row thread writes).
-    const int row = lo16(pk.y);
-    const bool diag = hi16(pk.y) != 0;
-    const int o11 = lo16(pk.x), o12 = hi16(pk.x);
+    const int row = yb_row(pk);
+    const bool diag = yb_diag(pk);
+    const int o11 = ew_o11(pk), o12 = ew_o12(pk);
     const Cx Y = {yl.x, yl.y};
+    if constexpr (WITH_J) {
+        if (diag) {  // the row's Ybus diagonal, for its diagonal J entries (ordered by the first barrier)
+            s_yd[0][row] = Y.re;
+            s_yd[1][row] = Y.im;
+        }
+    }
     const bool rowt = k < c.nrows;
     const int ir = c.r0 + (rowt ? k : 0);
     const size_t n = (size_t)nstate * nb;
@@ -687,8 +699,6 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? 6
     load(sb, first);
     const int irr = rowt ? ir : g.nb;
     const int2 rw = g.row_yb[irr];
-    const double2 ydg = g.ydiag[irr];
-    const Cx Yd = {ydg.x, ydg.y};
     const int ra = lo16(rw.x), rz = hi16(rw.x), dd11 = ra + rw.y, dd12 = rz + rw.y;
     // As in k_ew: every lane computes, only stores depend on the lane's role
     // (inert lanes have Y = 0 and a valid bus).
@@ -716,6 +726,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? 6
         if constexpr (WITH_J) {
             // diagonal entry of row k (Y_ii V_i recomputed from Y_ii and V_i)
             const Cx Ui = {s_vu[p][2][kr], s_vu[p][3][kr]};
+            const Cx Yd = {s_yd[0][kr], s_yd[1][kr]};
             const Cx yu = cmul(Yd, Ui);
             const Cx yvi = cmul(Yd, Vk);
             const Cx x2 = {Ic.re - yvi.re, Ic.im + yvi.im};
@@ -1248,10 +1259,6 @@ __global__ void k_lane_fill(DevLaneFill f, bool ew) {
             const int q = f.ylane_slot[l];
             f.ylane_y[l] = q >= 0 ? make_double2(f.yre[q], f.yim[q]) : make_double2(0.0, 0.0);
         }
-        if (l <= f.nb) {
-            const int q = l < f.nb ? f.ydslot[l] : -1;
-            f.ydiag[l] = q >= 0 ? make_double2(f.yre[q], f.yim[q]) : make_double2(0.0, 0.0);
-        }
     }
 }
 
@@ -1430,7 +1437,7 @@ hipError_t launch_setup_items(const DevSetup &s, hipStream_t stream) {
 }
 
 hipError_t launch_lane_fill(const DevLaneFill &f, bool ew, hipStream_t stream) {
-    const int64_t n = ew ? f.nlanes : std::max<int64_t>(f.nylanes, (int64_t)f.nb + 1);
+    const int64_t n = ew ? f.nlanes : f.nylanes;
     if (n == 0) return hipSuccess;
     const int64_t blocks = (n + 255) / 256;
     hipLaunchKernelGGL(k_lane_fill, dim3((unsigned)blocks), dim3(256), 0, stream, f, ew);
