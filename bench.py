@@ -559,6 +559,12 @@ def main():
         log(f"batched: {ev / steps * 1e6:.1f} us/launch")
         del vm2d, va2d, p2, q2, j2, G2
         torch.cuda.empty_cache()
+        ca = torch.ones(bb // 16, dtype=torch.float64, device=dev)
+        cb = torch.empty_like(ca)
+        evc, _ = timed(lambda k, st: cb.copy_(ca), 20, 3, period=10)
+        extra["batched_20k_x512"]["copy_same_bytes_us"] = evc / 20 * 1e6
+        del ca, cb
+        torch.cuda.empty_cache()
 
     if want("multigrid"):
         grids = gridgen.config3()
@@ -585,6 +591,12 @@ def main():
                                    "buses": big.nb, "branches": big.nl, "schedule": G3.schedule()}
         log(f"multigrid: {ev / steps * 1e6:.1f} us/launch")
         del vm3d, va3d, p3, q3, j3, G3
+        torch.cuda.empty_cache()
+        ca = torch.ones(mb // 16, dtype=torch.float64, device=dev)
+        cb = torch.empty_like(ca)
+        evc, _ = timed(lambda k, st: cb.copy_(ca), 20, 3, period=10)
+        extra["multigrid_64x4"]["copy_same_bytes_us"] = evc / 20 * 1e6
+        del ca, cb
         torch.cuda.empty_cache()
 
     if want("adjoint"):
