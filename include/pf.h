@@ -49,11 +49,14 @@
  *   caller, 8-byte aligned (16-byte for jval); outputs must not overlap
  *   inputs.  `stream` is a hipStream_t (NULL = default stream).
  * Evaluation calls enqueue work on `stream` and return: they allocate
- *   nothing, never synchronise and never read device data back, so they may
- *   be captured in a HIP graph.  The handle holds only read-only data during
- *   evaluation, so one handle may serve several streams at once.
+ *   nothing (the one exception: the first PF_METHOD_ELEMENTWISE_TWO_PHASE
+ *   call on a handle allocates that baseline's scratch), never synchronise
+ *   and never read device data back, so they may be captured in a HIP graph.
+ *   The handle holds only read-only data during evaluation (the two-phase
+ *   scratch aside), so one handle may serve several streams at once.
  * Results are deterministic: every sum runs in a fixed order set by the
- *   pattern (bus, then neighbour, then branch), independent of launch shape.
+ *   pattern (bus, then neighbour, then branch), independent of launch shape
+ *   (the copy-add baseline, PF_METHOD_ELEMENTWISE_ATOMIC, excepted).
  * Errors: every call returns a pf_status.  On a validation error nothing is
  *   written and nothing is launched; pf_last_error() describes it.  Faults of
  *   earlier asynchronous work surface as PF_EHIP on a later call.  No call
@@ -218,8 +221,10 @@ int pf_injections_vjp(const pf_grid *g, int32_t nstate, const double *vm, const 
  * pf_phasors writes V = v e^{j theta} and U = e^{j theta}.
  * pf_ybus_from_phasors reads them (U only when jval is non-NULL) and writes
  * p, q (f64[nstate][nb]; required when jval is NULL, else both may be NULL)
- * and jval (f64[nstate][nnz_j], CSR order, may be NULL); PF_ESTATE before
- * pf_ybus.  One launch each. */
+ * and jval (f64[nstate][nnz_j], CSR order, may be NULL).  One launch each.
+ * Errors: PF_EINVAL for an unknown layout, a NULL buffer, unaligned
+ * interleaved phasors or nothing to write; PF_ESTATE before pf_ybus
+ * (pf_ybus_from_phasors) or on a host-only handle. */
 enum { PF_PHASOR_SPLIT = 1, PF_PHASOR_INTERLEAVED = 2 };
 int pf_phasors(const pf_grid *g, int32_t layout, int32_t nstate, const double *vm, const double *va,
                double *ph, void *stream);
