@@ -621,6 +621,18 @@ def main():
                                      "vjp_over_forward": ev_b / ev_f,
                                      "forward_GBs": fb / (ev_f / steps) / 1e9, "vjp_GBs": bb / (ev_b / steps) / 1e9}
         log(f"adjoint: fwd {ev_f / steps * 1e6:.1f} us, vjp {ev_b / steps * 1e6:.1f} us")
+        # the headline evaluation (S + J) on the same 32 states in one launch
+        j4 = torch.empty(B, G4.nnz_j, dtype=torch.float64, device=dev)
+        ev_j, wall_j = timed(lambda k, st: pf.pf_jacobian_values(G4, pf.PF_METHOD_ELEMENTWISE, vm4d, va4d, p4, q4, j4,
+                                                                 stream=st), steps, 5, period=10)
+        jb = algorithmic_bytes(g.nb, g.nl, G4.nnz_y, B)
+        extra["ew_sj_100k_x32"] = {"state_evals_per_s": B * steps / wall_j, "avg_launch_us": ev_j / steps * 1e6,
+                                   "achieved_GBs": jb / (ev_j / steps) / 1e9,
+                                   "frac_hbm": jb / (ev_j / steps) / 1e9 / HBM_PEAK_GBS, "algorithmic_bytes": jb,
+                                   "schedule": G4.schedule()}
+        log(f"100k x 32 S+J: {ev_j / steps * 1e6:.1f} us/launch")
+        del j4, G4
+        torch.cuda.empty_cache()
 
     if want("newton"):
         # the evaluation as the inner step of a Newton-Raphson power flow: 5000-bus
