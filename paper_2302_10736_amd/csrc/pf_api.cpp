@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -66,6 +67,7 @@ struct pf_grid {
     pf::DevLaneFill lanes{};  // gather sources and targets of the lane values
     pf::DevTwoPhase tp{};     // two-phase element-wise tables (scratch allocated on first use)
     void *dscr = nullptr;
+    std::mutex scr_mu;        // first use of the scratch may come from several threads
 
     void *dmem = nullptr;   // grid data
     void *dtile = nullptr;  // schedule
@@ -788,6 +790,7 @@ int auto_states_per_block(const pf_grid *g, int kind, int32_t nstate) {
 // allocated on the first call that needs it.
 int ensure_two_phase_scratch(const pf_grid *g) {
     pf_grid *mg = const_cast<pf_grid *>(g);
+    std::lock_guard<std::mutex> lock(mg->scr_mu);
     if (mg->dscr) return PF_OK;
     const size_t bytes = 10 * (size_t)g->nitems * sizeof(double);
     hipError_t e = hipMalloc(&mg->dscr, bytes);
