@@ -470,6 +470,12 @@ def main():
         wall = eager_timed(ew_sj, K, W)
         extra["ew_sj_eager_python_calls"] = {"evals_per_s": K / wall, "us_per_call": wall / K * 1e6,
                                              "note": "one binding call per step; bound by host time"}
+        bound = [pf.bind(pf.pf_jacobian_values, d["G"], pf.PF_METHOD_ELEMENTWISE, d["vm"], d["va"], d["p"], d["q"],
+                         d["j"], stream=side) for d in reps]
+        wall = eager_timed(lambda k, st: bound[k % R](), K, W)
+        extra["ew_sj_eager_bound_calls"] = {"evals_per_s": K / wall, "us_per_call": wall / K * 1e6,
+                                            "note": "pf.bind: arguments marshalled once, one library call per step"}
+        del bound
 
         def ew_s(k, st):
             d = reps[k % R]

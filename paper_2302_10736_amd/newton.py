@@ -89,9 +89,10 @@ def solve(grid: "pf.Grid", bus_type, p_spec, q_spec, vm0, va0, method: int = pf.
     p_spec = np.asarray(p_spec, dtype=np.float64)
     q_spec = np.asarray(q_spec, dtype=np.float64)
     res = NewtonResult(vm=None, va=None, converged=False, iterations=0)
+    evaluate = pf.bind(pf.pf_jacobian_values, grid, method, vm, va, p, q, j)  # same buffers every iteration
     for it in range(max_iter + 1):
         t0 = time.perf_counter()
-        pf.pf_jacobian_values(grid, method, vm, va, p, q, j)
+        evaluate()
         ph, qh, jv = p.cpu().numpy(), q.cpu().numpy(), j.cpu().numpy()
         t1 = time.perf_counter()
         res.seconds_eval += t1 - t0

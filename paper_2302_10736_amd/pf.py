@@ -213,45 +213,99 @@ def pf_ybus(grid: Grid, y_re=None, y_im=None, stream=None):
                         _stream(stream)))
 
 
-def pf_injections_elementwise(grid: Grid, vm, va, p, q, stream=None):
+def _m_injections_elementwise(grid: Grid, vm, va, p, q, stream=None):
     ns = _nstate(vm, grid.nb)
     shp = tuple(vm.shape)
-    check(lib().pf_injections_elementwise(grid.handle, ns, _dev(vm, shp, "vm"), _dev(va, shp, "va"),
-                                          _dev(p, shp, "p"), _dev(q, shp, "q"), _stream(stream)))
+    return (grid.handle, ns, _dev(vm, shp, "vm"), _dev(va, shp, "va"), _dev(p, shp, "p"), _dev(q, shp, "q"),
+            _stream(stream))
 
 
-def pf_injections_ybus(grid: Grid, vm, va, p, q, stream=None):
-    ns = _nstate(vm, grid.nb)
-    shp = tuple(vm.shape)
-    check(lib().pf_injections_ybus(grid.handle, ns, _dev(vm, shp, "vm"), _dev(va, shp, "va"), _dev(p, shp, "p"),
-                                   _dev(q, shp, "q"), _stream(stream)))
+def _m_injections_ybus(grid: Grid, vm, va, p, q, stream=None):
+    return _m_injections_elementwise(grid, vm, va, p, q, stream)
 
 
-def pf_jacobian_values(grid: Grid, method: int, vm, va, p, q, jval, stream=None):
+def _m_jacobian_values(grid: Grid, method: int, vm, va, p, q, jval, stream=None):
     ns = _nstate(vm, grid.nb)
     shp = tuple(vm.shape)
     jshp = (grid.nnz_j,) if vm.dim() == 1 else (ns, grid.nnz_j)
-    check(lib().pf_jacobian_values(grid.handle, int(method), ns, _dev(vm, shp, "vm"), _dev(va, shp, "va"),
-                                   _dev(p, shp, "p"), _dev(q, shp, "q"), _dev(jval, jshp, "jval"), _stream(stream)))
+    return (grid.handle, int(method), ns, _dev(vm, shp, "vm"), _dev(va, shp, "va"), _dev(p, shp, "p"),
+            _dev(q, shp, "q"), _dev(jval, jshp, "jval"), _stream(stream))
 
 
-def pf_injections_vjp(grid: Grid, vm, va, lam_p, lam_q, g_vm, g_va, stream=None):
+def _m_injections_vjp(grid: Grid, vm, va, lam_p, lam_q, g_vm, g_va, stream=None):
     ns = _nstate(vm, grid.nb)
     shp = tuple(vm.shape)
-    check(lib().pf_injections_vjp(grid.handle, ns, _dev(vm, shp, "vm"), _dev(va, shp, "va"),
-                                  _dev(lam_p, shp, "lam_p"), _dev(lam_q, shp, "lam_q"), _dev(g_vm, shp, "g_vm"),
-                                  _dev(g_va, shp, "g_va"), _stream(stream)))
+    return (grid.handle, ns, _dev(vm, shp, "vm"), _dev(va, shp, "va"), _dev(lam_p, shp, "lam_p"),
+            _dev(lam_q, shp, "lam_q"), _dev(g_vm, shp, "g_vm"), _dev(g_va, shp, "g_va"), _stream(stream))
 
 
-def pf_branch_flows(grid: Grid, vm, va, pf_, qf, pt, qt, jac=None, stream=None):
+def _m_branch_flows(grid: Grid, vm, va, pf_, qf, pt, qt, jac=None, stream=None):
     ns = _nstate(vm, grid.nb)
     shp = tuple(vm.shape)
     nl = grid.nl
     fshp = (nl,) if vm.dim() == 1 else (ns, nl)
     jshp = (16, nl) if vm.dim() == 1 else (ns, 16, nl)
-    check(lib().pf_branch_flows(grid.handle, ns, _dev(vm, shp, "vm"), _dev(va, shp, "va"), _dev(pf_, fshp, "pf"),
-                                _dev(qf, fshp, "qf"), _dev(pt, fshp, "pt"), _dev(qt, fshp, "qt"),
-                                _dev(jac, jshp, "jac"), _stream(stream)))
+    return (grid.handle, ns, _dev(vm, shp, "vm"), _dev(va, shp, "va"), _dev(pf_, fshp, "pf"), _dev(qf, fshp, "qf"),
+            _dev(pt, fshp, "pt"), _dev(qt, fshp, "qt"), _dev(jac, jshp, "jac"), _stream(stream))
+
+
+def pf_injections_elementwise(grid: Grid, vm, va, p, q, stream=None):
+    check(lib().pf_injections_elementwise(*_m_injections_elementwise(grid, vm, va, p, q, stream)))
+
+
+def pf_injections_ybus(grid: Grid, vm, va, p, q, stream=None):
+    check(lib().pf_injections_ybus(*_m_injections_ybus(grid, vm, va, p, q, stream)))
+
+
+def pf_jacobian_values(grid: Grid, method: int, vm, va, p, q, jval, stream=None):
+    check(lib().pf_jacobian_values(*_m_jacobian_values(grid, method, vm, va, p, q, jval, stream)))
+
+
+def pf_injections_vjp(grid: Grid, vm, va, lam_p, lam_q, g_vm, g_va, stream=None):
+    check(lib().pf_injections_vjp(*_m_injections_vjp(grid, vm, va, lam_p, lam_q, g_vm, g_va, stream)))
+
+
+def pf_branch_flows(grid: Grid, vm, va, pf_, qf, pt, qt, jac=None, stream=None):
+    check(lib().pf_branch_flows(*_m_branch_flows(grid, vm, va, pf_, qf, pt, qt, jac, stream)))
+
+
+_MARSHAL = {
+    "pf_injections_elementwise": _m_injections_elementwise,
+    "pf_injections_ybus": _m_injections_ybus,
+    "pf_jacobian_values": _m_jacobian_values,
+    "pf_injections_vjp": _m_injections_vjp,
+    "pf_branch_flows": _m_branch_flows,
+}
+
+
+class Bound:
+    """One evaluation call with its arguments checked and marshalled once.
+
+    Calling the object only calls the library function with the stored
+    arguments: for loops that evaluate again and again on the same buffers
+    (their contents may change between calls), where the per-call argument
+    checks of the plain binding cost more host time than the kernel.  The
+    stream is fixed when binding (``stream=None``: torch's current stream at
+    that moment).  The object keeps the grid and the tensors alive."""
+
+    def __init__(self, fn, *args, **kw):
+        name = getattr(fn, "__name__", fn)
+        if name not in _MARSHAL:
+            raise ValueError(f"cannot bind {name!r}; one of {sorted(_MARSHAL)}")
+        self._f = getattr(lib(), name)
+        self._args = _MARSHAL[name](*args, **kw)
+        self._keep = (args, kw)
+
+    def __call__(self):
+        rc = self._f(*self._args)
+        if rc != PF_OK:
+            raise PFError(rc, lib().pf_last_error().decode())
+
+
+def bind(fn, *args, **kw) -> Bound:
+    """``bind(pf_jacobian_values, grid, method, vm, va, p, q, jval)`` returns a
+    :class:`Bound` call; the arguments are those of ``fn``."""
+    return Bound(fn, *args, **kw)
 
 
 def pf_phasors(grid: Grid, layout: int, vm, va, ph, stream=None):

@@ -230,3 +230,13 @@ def test_binding_refuses_host_arrays():
     with pytest.raises((TypeError, ValueError)):
         pf.pf_injections_elementwise(G, torch.zeros(6, dtype=torch.float64), torch.zeros(6, dtype=torch.float64),
                                      torch.zeros(6, dtype=torch.float64), torch.zeros(6, dtype=torch.float64))
+
+
+def test_bind_refuses_unknown_calls_and_host_arrays():
+    import torch
+    with pytest.raises(ValueError):
+        pf.bind("pf_ybus")
+    G = pf.Grid.from_grid(_grids.random_small(6, 8, 5), host_only=True)
+    z = torch.zeros(6, dtype=torch.float64)
+    with pytest.raises((TypeError, ValueError)):
+        pf.bind(pf.pf_injections_elementwise, G, z, z, z, z)

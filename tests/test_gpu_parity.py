@@ -373,3 +373,33 @@ def test_autograd_function():
     w = torch.linspace(-1, 1, g.nb, dtype=torch.float64, device="cuda:0")
     (P * w).sum().backward()
     assert vm_t.grad is not None and va_t.grad is not None
+
+
+def test_bound_calls_match_plain_calls():
+    """pf.bind: arguments marshalled once, each call only calls the library;
+    same results as the plain calls, also after the inputs change in place."""
+    import torch
+    g = gridgen.config0()
+    vm, va = gridgen.states(g.nb, 3, cfg=0)
+    G = pf.Grid.from_grid(g)
+    pf.pf_ybus(G)
+    vmd, vad = to_dev(vm), to_dev(va)
+    z = lambda *sh: torch.full(sh, float("nan"), dtype=torch.float64, device="cuda:0")
+    p1, q1, j1, p2, q2, j2 = z(3, G.nb), z(3, G.nb), z(3, G.nnz_j), z(3, G.nb), z(3, G.nb), z(3, G.nnz_j)
+    gv1, ga1, gv2, ga2 = z(3, G.nb), z(3, G.nb), z(3, G.nb), z(3, G.nb)
+    calls = [pf.bind(pf.pf_jacobian_values, G, pf.PF_METHOD_ELEMENTWISE, vmd, vad, p1, q1, j1),
+             pf.bind(pf.pf_injections_vjp, G, vmd, vad, p1, q1, gv1, ga1)]
+    for rep in range(2):
+        for c in calls:
+            c()
+        pf.pf_jacobian_values(G, pf.PF_METHOD_ELEMENTWISE, vmd, vad, p2, q2, j2)
+        pf.pf_injections_vjp(G, vmd, vad, p2, q2, gv2, ga2)
+        torch.cuda.synchronize()
+        for a, b in ((p1, p2), (q1, q2), (j1, j2), (gv1, gv2), (ga1, ga2)):
+            assert torch.equal(a, b), rep
+        vad.add_(0.01)  # new inputs in the same buffers
+    yb_call = pf.bind(pf.pf_injections_ybus, G, vmd, vad, p1, q1)
+    yb_call()
+    pf.pf_injections_ybus(G, vmd, vad, p2, q2)
+    torch.cuda.synchronize()
+    assert torch.equal(p1, p2) and torch.equal(q1, q2)
