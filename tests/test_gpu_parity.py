@@ -403,3 +403,26 @@ def test_bound_calls_match_plain_calls():
     pf.pf_injections_ybus(G, vmd, vad, p2, q2)
     torch.cuda.synchronize()
     assert torch.equal(p1, p2) and torch.equal(q1, q2)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_grids_and_schedules(seed):
+    """Randomised sweep: grid size and shape (parallel branches, isolated
+    buses, transformer share), tile size, states per workgroup, order and
+    batch size drawn per seed; every call against the oracle, state by state."""
+    rng = np.random.default_rng(1000 + seed)
+    nb = int(rng.integers(2, 900))
+    iso = int(rng.integers(0, min(5, nb - 2) + 1))
+    live = nb - iso
+    nl = int(rng.integers(live - 1, 2 * live + 2))
+    par = int(rng.integers(0, 6))
+    g = _grids.random_small(nb, max(nl, live - 1 + par), 2000 + seed, parallel=par, isolated=iso,
+                            xf_frac=float(rng.uniform(0, 0.6)))
+    ns = int(rng.integers(1, 6))
+    vm = rng.uniform(0.9, 1.1, (ns, g.nb))
+    va = rng.normal(0, 0.25, (ns, g.nb))
+    tile = int(rng.choice([64, 128, 256, 512]))
+    spb = int(rng.choice([0, 1, 2, 3]))
+    order = int(rng.choice([pf.PF_ORDER_AUTO, pf.PF_ORDER_TILE_MAJOR, pf.PF_ORDER_STATE_MAJOR]))
+    print(f"seed {seed}: nb {g.nb} nl {g.nl} parallel {par} isolated {iso} states {ns} schedule {tile},{spb},{order}")
+    check_single(g, vm, va, tile=tile, spb=spb, order=order, use_scale=g.nb <= 3)
