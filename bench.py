@@ -574,7 +574,20 @@ def main():
                                      "automatic_schedule": auto_sched,
                                      "automatic_schedule_us": ev_auto / max(10, K // 100) * 1e6}
         log(f"batched: {ev / steps * 1e6:.1f} us/launch")
-        del vm2d, va2d, p2, q2, j2, G2
+        # the Ybus method on the same states, tuned the same way (same grid, separate handle)
+        G2y = pf.Grid.from_grid(g2)
+        pf.pf_ybus(G2y)
+
+        def b_yb(k, st):
+            pf.pf_jacobian_values(G2y, pf.PF_METHOD_YBUS, vm2d, va2d, p2, q2, j2, stream=st)
+        if not args.no_tune:
+            tuned["batched_ybus"] = autotune.tune(G2y, "jacobian_ybus", B, cache=tune_cache, save=False)
+        ev_y, _ = timed(b_yb, steps, 5, period=10)
+        extra["batched_20k_x512"]["ybus_avg_launch_us"] = ev_y / steps * 1e6
+        extra["batched_20k_x512"]["ybus_schedule"] = G2y.schedule()
+        extra["batched_20k_x512"]["ew_speedup_vs_ybus"] = ev_y / ev
+        log(f"batched Ybus: {ev_y / steps * 1e6:.1f} us/launch")
+        del vm2d, va2d, p2, q2, j2, G2, G2y
         torch.cuda.empty_cache()
         ca = torch.ones(bb // 16, dtype=torch.float64, device=dev)
         cb = torch.empty_like(ca)
@@ -607,7 +620,19 @@ def main():
                                    "frac_hbm": mb / (ev / steps) / 1e9 / HBM_PEAK_GBS, "algorithmic_bytes": mb,
                                    "buses": big.nb, "branches": big.nl, "schedule": G3.schedule()}
         log(f"multigrid: {ev / steps * 1e6:.1f} us/launch")
-        del vm3d, va3d, p3, q3, j3, G3
+        G3y = pf.Grid.from_grid(big, bo, ro)
+        pf.pf_ybus(G3y)
+
+        def m_yb(k, st):
+            pf.pf_jacobian_values(G3y, pf.PF_METHOD_YBUS, vm3d, va3d, p3, q3, j3, stream=st)
+        if not args.no_tune:
+            tuned["multigrid_ybus"] = autotune.tune(G3y, "jacobian_ybus", 4, cache=tune_cache, cands=cands, save=False)
+        ev_y, _ = timed(m_yb, steps, 5, period=10)
+        extra["multigrid_64x4"]["ybus_avg_launch_us"] = ev_y / steps * 1e6
+        extra["multigrid_64x4"]["ybus_schedule"] = G3y.schedule()
+        extra["multigrid_64x4"]["ew_speedup_vs_ybus"] = ev_y / ev
+        log(f"multigrid Ybus: {ev_y / steps * 1e6:.1f} us/launch")
+        del vm3d, va3d, p3, q3, j3, G3, G3y
         torch.cuda.empty_cache()
         ca = torch.ones(mb // 16, dtype=torch.float64, device=dev)
         cb = torch.empty_like(ca)
