@@ -933,6 +933,9 @@ int pf_jacobian_values(const pf_grid *g, int32_t method, int32_t nstate, const d
     return run(g, L, stream);
 }
 
+static_assert(PF_PHASOR_SPLIT == pf::PH_SPLIT && PF_PHASOR_INTERLEAVED == pf::PH_INTERLEAVED,
+              "public phasor layouts name the kernels' phasor sources");
+
 int pf_phasors(const pf_grid *g, int32_t layout, int32_t nstate, const double *vm, const double *va, double *ph,
                void *stream) {
     g_err.clear();

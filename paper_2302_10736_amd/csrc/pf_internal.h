@@ -124,6 +124,11 @@ struct DevTwoPhase {
 
 enum Kind { K_EW_S = 0, K_EW_SJ = 1, K_YB_S = 2, K_YB_SJ = 3, K_EW_VJP = 4, K_EW_SJ_CSC = 5 };
 
+// Phasor source of the Ybus kernels: formed on the fly from (vm, va), or
+// read from stored split / interleaved phasors (the values of the public
+// PF_PHASOR_SPLIT and PF_PHASOR_INTERLEAVED).
+enum { PH_FLY = 0, PH_SPLIT = 1, PH_INTERLEAVED = 2 };
+
 struct Launch {
     int kind;
     int tile_items;        // workgroup size = records per tile

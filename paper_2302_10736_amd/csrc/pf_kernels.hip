@@ -496,8 +496,7 @@ __global__ void __launch_bounds__(NT)
 // Stored phasors (Section IV.B.1 step 1): V = v e^{j theta}, U = e^{j theta}
 // for n = nstate * nb (state, bus) entries.  PH_SPLIT: four planes of n
 // doubles [Re V | Im V | Re U | Im U]; PH_INTERLEAVED: n pairs {Re V, Im V}
-// followed by n pairs {Re U, Im U}.
-enum { PH_FLY = 0, PH_SPLIT = 1, PH_INTERLEAVED = 2 };
+// followed by n pairs {Re U, Im U} (PH_* in pf_internal.h).
 
 template <int PH>
 __global__ void k_phasor(int64_t n, const double *__restrict__ vm, const double *__restrict__ va, double *__restrict__ ph) {
