@@ -26,8 +26,9 @@ Counter runs (HBM traffic of the dominant kernel):
     rocprofv3 --pmc FETCH_SIZE --output-format csv -d D1 -o f -- python3 bench.py --probe
     rocprofv3 --pmc WRITE_SIZE --output-format csv -d D2 -o w -- python3 bench.py --probe
     python3 bench.py --traffic D1/.../f_counter_collection.csv D2/.../w_counter_collection.csv
-The probe runs the headline launches and one plain copy of a known byte
-count; each counter is scaled by known bytes / counted bytes of that copy.
+The probe runs the headline launches, as many Ybus S+J launches (their own
+traffic figure) and one plain copy of a known byte count; each counter is
+scaled by known bytes / counted bytes of that copy.
 """
 from __future__ import annotations
 
@@ -315,12 +316,20 @@ def main():
     if args.probe:
         for k in range(2 * R):
             ew_sj(k)
+        # the Ybus kernel on the same replicas, for its own traffic figure
+        for d in reps:
+            pf.pf_ybus(d["G"])
+        torch.cuda.synchronize()
+        for k in range(2 * R):
+            d = reps[k % R]
+            pf.pf_jacobian_values(d["G"], pf.PF_METHOD_YBUS, d["vm"], d["va"], d["p"], d["q"], d["j"])
         a = torch.ones(COPY_PROBE_DOUBLES, dtype=torch.float64, device=dev)
         b = torch.empty_like(a)
         torch.cuda.synchronize()
         b.copy_(a)
         torch.cuda.synchronize()
-        log(f"probe done: {2 * R} headline launches, one copy of {8 * COPY_PROBE_DOUBLES} bytes")
+        log(f"probe done: {2 * R} headline launches, {2 * R} Ybus S+J launches, one copy of "
+            f"{8 * COPY_PROBE_DOUBLES} bytes")
         return
 
     K, W = args.steps, args.warmup
