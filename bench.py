@@ -452,6 +452,42 @@ def main():
                               "kernel": f"k_ew_csc<{tile}, false, true>", "bytes_read_extra": cb - abytes}
         log(f"element-wise S+J, CSC order: {ev / K * 1e6:.2f} us/launch")
 
+    if want("scatter"):
+        # Algorithm 2's in-place copy into a larger pattern: J's entries plus the couplings of
+        # 1000 series devices between random bus pairs (all four blocks), CSR
+        _, _, jr0, jc0 = G0.pattern()
+        rows0 = np.repeat(np.arange(2 * g.nb, dtype=np.int64), np.diff(jr0))
+        rng_s = np.random.default_rng(17)
+        pr = rng_s.integers(0, g.nb, (1000, 2))
+        ex_r, ex_c = [], []
+        for a, b in ((0, 1), (1, 0)):
+            for rb in (0, g.nb):
+                for cb in (0, g.nb):
+                    ex_r.append(pr[:, a] + rb)
+                    ex_c.append(pr[:, b] + cb)
+        key = np.unique(np.concatenate([rows0 * (2 * g.nb) + jc0] +
+                                       [r * (2 * g.nb) + c for r, c in zip(ex_r, ex_c)]))
+        t_rows, t_cols = key // (2 * g.nb), (key % (2 * g.nb)).astype(np.int32)
+        t_ptr = np.zeros(2 * g.nb + 1, np.int64)
+        np.add.at(t_ptr, t_rows + 1, 1)
+        t_ptr = np.cumsum(t_ptr).astype(np.int32)
+        t0 = time.perf_counter()
+        jmap = pf.pf_jacobian_map(G0, pf.PF_LAYOUT_CSR, t_ptr, t_cols)
+        map_s = time.perf_counter() - t0
+        jmap_d = torch.as_tensor(jmap, device=dev)
+        outs = [torch.zeros(1, len(t_cols), dtype=torch.float64, device=dev) for _ in range(R)]
+
+        def scat(k, st):
+            d = reps[k % R]
+            pf.pf_jacobian_scatter(d["G"], d["j"], jmap_d, outs[k % R], stream=st)
+        ev, _ = timed(scat, K, W)
+        sb = 20 * G0.nnz_j  # J read, map read, values written
+        extra["jacobian_scatter_100k"] = {"avg_launch_us": ev / K * 1e6, "achieved_GBs": sb / (ev / K) / 1e9,
+                                          "target_nnz": int(len(t_cols)), "map_host_s": map_s,
+                                          "algorithmic_bytes": sb}
+        del outs, jmap_d
+        log(f"J scatter into a larger pattern: {ev / K * 1e6:.2f} us/launch (map on the host {map_s * 1e3:.0f} ms)")
+
     if want("flows"):
         # branch flows and their 16 partials (line-limit constraints), same grid and protocol
         for d in reps:

@@ -241,6 +241,30 @@ int pf_ybus_from_phasors(const pf_grid *g, int32_t layout, int32_t nstate, const
 int pf_branch_flows(const pf_grid *g, int32_t nstate, const double *vm, const double *va, double *pf,
                     double *qf, double *pt, double *qt, double *jac, void *stream);
 
+/* Jacobian values in another sparsity pattern (Algorithm 2, Section
+ * IV.B.2: indices into the target pattern found once by matching row and
+ * column, then an in-place copy by those indices).  For targets whose
+ * pattern holds J's entries and more, e.g. the extra couplings of series
+ * devices such as a TCSC.
+ * pf_jacobian_map (host): target pattern of size n x n, n = 2 nb, one grid
+ *   per handle; layout PF_LAYOUT_CSR (ptr = row pointers, idx = column
+ *   indices) or PF_LAYOUT_CSC (ptr = column pointers, idx = row indices);
+ *   host arrays int32 ptr[n+1], idx[ptr[n]].  Writes map int32[nnz_j] (host):
+ *   for J entry k in the exported CSR order its position in the target.
+ *   PF_EINVAL if the target lacks an entry of J (the message names it) or
+ *   is malformed; PF_EUNSUP for a multi-grid handle.  Works on host-only
+ *   handles.
+ * pf_jacobian_scatter (device): out[s * out_nnz + map[k]] =
+ *   jval[s * nnz_j + k] for every state s and entry k; jval f64[nstate][nnz_j],
+ *   map int32[nnz_j], out f64[nstate][out_nnz], all device; target entries
+ *   that J does not cover are left as they are; map values outside
+ *   [0, out_nnz) are skipped.  One launch. */
+enum { PF_LAYOUT_CSR = 0, PF_LAYOUT_CSC = 1 };
+int pf_jacobian_map(const pf_grid *g, int32_t layout, int32_t n, const int32_t *ptr, const int32_t *idx,
+                    int32_t *map);
+int pf_jacobian_scatter(const pf_grid *g, int32_t nstate, const double *jval, const int32_t *map, int64_t out_nnz,
+                        double *out, void *stream);
+
 /* Launch schedule.
  *   tile_items        workgroup size (64, 128, 256 or 512): branch ends per
  *                     element-wise work tile, Ybus nonzeros per Ybus tile

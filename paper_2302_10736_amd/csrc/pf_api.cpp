@@ -719,6 +719,63 @@ int pf_pattern_export(const pf_grid *g, int32_t *y_rowptr, int32_t *y_col, int32
     return PF_OK;
 }
 
+int pf_jacobian_map(const pf_grid *g, int32_t layout, int32_t n, const int32_t *ptr, const int32_t *idx,
+                    int32_t *map) {
+    g_err.clear();
+    if (!g) return fail(PF_EINVAL, "NULL handle");
+    if (g->ngrids != 1) return fail(PF_EUNSUP, "pf_jacobian_map takes a handle with one grid");
+    if (layout != PF_LAYOUT_CSR && layout != PF_LAYOUT_CSC) return fail(PF_EINVAL, "unknown layout");
+    const int32_t nb = g->nb;
+    if ((int64_t)n != 2 * (int64_t)nb) return fail(PF_EINVAL, "the target pattern must be 2 nb x 2 nb");
+    if (!ptr || !idx || !map) return fail(PF_EINVAL, "NULL pointer");
+    if (ptr[0] != 0) return fail(PF_EINVAL, "ptr[0] must be 0");
+    for (int32_t r = 0; r < n; ++r)
+        if (ptr[r + 1] < ptr[r]) return fail(PF_EINVAL, "ptr must not decrease");
+    bool sorted = true;
+    for (int32_t r = 0; r < n; ++r)
+        for (int32_t q = ptr[r]; q < ptr[r + 1]; ++q) {
+            if (idx[q] < 0 || idx[q] >= n) return fail(PF_EINVAL, "index out of range in the target pattern");
+            if (q > ptr[r] && idx[q] <= idx[q - 1]) sorted = false;
+        }
+    // Position of (major, minor) in the target: major = row (CSR) or column
+    // (CSC); binary search when every segment ascends, else a linear scan.
+    auto find = [&](int32_t major, int32_t minor) -> int32_t {
+        int32_t a = ptr[major], z = ptr[major + 1];
+        if (sorted) {
+            while (a < z) {
+                const int32_t m = a + (z - a) / 2;
+                if (idx[m] < minor)
+                    a = m + 1;
+                else
+                    z = m;
+            }
+            return (a < ptr[major + 1] && idx[a] == minor) ? a : -1;
+        }
+        for (int32_t q = a; q < z; ++q)
+            if (idx[q] == minor) return q;
+        return -1;
+    };
+    // Our entries in the exported CSR order: P rows then Q rows, each row's
+    // theta columns then its v columns.
+    int64_t k = 0;
+    for (int32_t half = 0; half < 2; ++half)
+        for (int32_t i = 0; i < nb; ++i) {
+            const int32_t r = half * nb + i;
+            for (int32_t part = 0; part < 2; ++part)
+                for (int32_t p = g->yrow[i]; p < g->yrow[i + 1]; ++p) {
+                    const int32_t c = g->ycol[p] + part * nb;
+                    const int32_t pos = layout == PF_LAYOUT_CSR ? find(r, c) : find(c, r);
+                    if (pos < 0) {
+                        char msg[96];
+                        std::snprintf(msg, sizeof msg, "the target pattern lacks J entry (%d, %d)", r, c);
+                        return fail(PF_EINVAL, msg);
+                    }
+                    map[k++] = pos;
+                }
+        }
+    return PF_OK;
+}
+
 int pf_set_schedule(pf_grid *g, int32_t tile_items, int32_t states_per_block, int32_t order) {
     g_err.clear();
     if (!g) return fail(PF_EINVAL, "NULL handle");
@@ -977,6 +1034,23 @@ int pf_ybus_from_phasors(const pf_grid *g, int32_t layout, int32_t nstate, const
     L.q = q;
     L.jval = jval;
     return run(g, L, stream);
+}
+
+int pf_jacobian_scatter(const pf_grid *g, int32_t nstate, const double *jval, const int32_t *map, int64_t out_nnz,
+                        double *out, void *stream) {
+    g_err.clear();
+    int st = check_eval(g, nstate);
+    if (st) return st;
+    if (out_nnz < 0 || out_nnz > INT32_MAX) return fail(PF_EINVAL, "out_nnz must lie in [0, 2^31 - 1]");
+    if (nstate == 0 || 4 * g->nnz_y == 0) return PF_OK;
+    if (!jval || !map || !out) return fail(PF_EINVAL, "NULL pointer");
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (cur != g->device) return fail(PF_EINVAL, "current HIP device differs from the handle's device");
+    e = pf::launch_jscatter(nstate, 4 * g->nnz_y, jval, map, out_nnz, out, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return PF_OK;
 }
 
 int pf_branch_flows(const pf_grid *g, int32_t nstate, const double *vm, const double *va, double *pf, double *qf,

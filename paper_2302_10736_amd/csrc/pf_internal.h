@@ -163,6 +163,10 @@ hipError_t launch_flows(const DevTwoPhase &d, int32_t nstate, const double *vm, 
 // shunt terms, per-branch adds); jval 16-byte aligned.
 hipError_t launch_copy_add(const DevTwoPhase &d, int32_t nstate, int64_t nnz_j, const double *vm, const double *va,
                            double *p, double *q, double *jval, bool pre, hipStream_t stream);
+// out[s * out_nnz + map[k]] = jval[s * nnz_j + k] for every state s and
+// entry k with 0 <= map[k] < out_nnz (other entries are skipped).
+hipError_t launch_jscatter(int32_t nstate, int64_t nnz_j, const double *jval, const int32_t *map, int64_t out_nnz,
+                           double *out, hipStream_t stream);
 // Precomputed branch constants (d.bc's layout) into bc.
 hipError_t launch_branch_consts(const DevTwoPhase &d, double *bc, hipStream_t stream);
 // States [0, nstate) one after another, two launches each.

@@ -1244,6 +1244,20 @@ __global__ void k_ca_branch(DevTwoPhase d, int nstate, int64_t nnz_j, const doub
     }
 }
 
+// Jacobian values into another pattern (Algorithm 2's in-place copy by
+// precomputed indices): one thread per J entry reads its target position
+// once and copies the entry of every state.  Positions outside the target
+// are skipped, so a wrong map cannot write out of bounds.
+__global__ void k_jscatter(int32_t nstate, int64_t nnz_j, const double *__restrict__ jval,
+                           const int32_t *__restrict__ map, int64_t out_nnz, double *__restrict__ out) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nnz_j) return;
+    const int32_t m = map[k];
+    if (m < 0 || m >= out_nnz) return;
+    for (int32_t s = blockIdx.y; s < nstate; s += gridDim.y)
+        st_out(out + (size_t)s * (size_t)out_nnz + m, jval[(size_t)s * (size_t)nnz_j + k]);
+}
+
 // Lane values: copies of the record constants (element-wise) or Ybus values
 // in lane order; inert lanes get zeros.
 __global__ void k_lane_fill(DevLaneFill f, bool ew) {
@@ -1505,6 +1519,16 @@ hipError_t launch_phasor(int32_t layout, int64_t n, const double *vm, const doub
         hipLaunchKernelGGL(k_phasor<PH_INTERLEAVED>, dim3((unsigned)blocks), dim3(256), 0, stream, n, vm, va, ph);
     else
         return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_jscatter(int32_t nstate, int64_t nnz_j, const double *jval, const int32_t *map, int64_t out_nnz,
+                           double *out, hipStream_t stream) {
+    if (nstate == 0 || nnz_j == 0) return hipSuccess;
+    const int64_t blocks = (nnz_j + 255) / 256;
+    if (blocks > INT32_MAX) return hipErrorInvalidConfiguration;
+    const dim3 grid((unsigned)blocks, (unsigned)std::min<int32_t>(nstate, 65535));
+    hipLaunchKernelGGL(k_jscatter, grid, dim3(256), 0, stream, nstate, nnz_j, jval, map, out_nnz, out);
     return hipGetLastError();
 }
 

@@ -23,12 +23,13 @@ PF_BUILD_HOST_ONLY = 1
 PF_ORDER_AUTO, PF_ORDER_TILE_MAJOR, PF_ORDER_STATE_MAJOR = 0, 1, 2
 PF_PHASOR_SPLIT, PF_PHASOR_INTERLEAVED = 1, 2
 PF_JAC_CSC = 0x100  # OR into the method of pf_jacobian_values: J values in CSC order
+PF_LAYOUT_CSR, PF_LAYOUT_CSC = 0, 1
 PF_EW_PRECOMPUTED = 0x200  # OR into the two-phase / copy-add methods: precomputed branch constants
 
 EXPORTS = (
     "pf_build_pattern", "pf_grid_free", "pf_grid_sizes", "pf_pattern_sizes", "pf_grid_offsets",
     "pf_pattern_export", "pf_ybus", "pf_injections_elementwise", "pf_injections_ybus", "pf_jacobian_values",
-    "pf_injections_vjp", "pf_branch_flows", "pf_phasors", "pf_ybus_from_phasors", "pf_set_schedule", "pf_get_schedule", "pf_graph_create", "pf_graph_launch",
+    "pf_injections_vjp", "pf_branch_flows", "pf_phasors", "pf_ybus_from_phasors", "pf_jacobian_map", "pf_jacobian_scatter", "pf_set_schedule", "pf_get_schedule", "pf_graph_create", "pf_graph_launch",
     "pf_graph_free", "pf_last_error", "pf_version",
 )
 PF_OP_INJECTIONS, PF_OP_JACOBIAN, PF_OP_VJP = 0, 1, 2
@@ -74,6 +75,8 @@ def lib() -> C.CDLL:
         L.pf_injections_vjp.argtypes = [P, i32, P, P, P, P, P, P, P]
         L.pf_branch_flows.argtypes = [P, i32, P, P, P, P, P, P, P, P]
         L.pf_phasors.argtypes = [P, i32, i32, P, P, P, P]
+        L.pf_jacobian_map.argtypes = [P, i32, i32, P, P, P]
+        L.pf_jacobian_scatter.argtypes = [P, i32, P, P, i64, P, P]
         L.pf_ybus_from_phasors.argtypes = [P, i32, i32, P, P, P, P, P]
         L.pf_set_schedule.argtypes = [P, i32, i32, i32]
         L.pf_graph_create.argtypes = [P, P, i32, C.POINTER(P)]
@@ -331,6 +334,36 @@ def pf_ybus_from_phasors(grid: Grid, layout: int, nstate: int, ph, p=None, q=Non
     jshp = (grid.nnz_j,) if flat else (nstate, grid.nnz_j)
     check(lib().pf_ybus_from_phasors(grid.handle, int(layout), int(nstate), _dev(ph, None, "ph"), _dev(p, shp, "p"),
                                      _dev(q, shp, "q"), _dev(jval, jshp, "jval"), _stream(stream)))
+
+
+def pf_jacobian_map(grid: Grid, layout: int, ptr, idx) -> np.ndarray:
+    """Positions of J's entries (exported CSR order) in a target pattern of
+    size 2 nb (host arrays; CSR row pointers and column indices, or CSC
+    column pointers and row indices); returns int32[nnz_j]."""
+    ptr = _host(ptr, np.int32)
+    idx = _host(idx, np.int32)
+    if ptr is None or idx is None or ptr.ndim != 1 or len(ptr) < 1:
+        raise ValueError("ptr and idx must be 1-D arrays")
+    out = np.empty(max(grid.nnz_j, 1), np.int32)
+    check(lib().pf_jacobian_map(grid.handle, int(layout), len(ptr) - 1, _hp(ptr), _hp(idx if len(idx) else np.zeros(1, np.int32)),
+                                _hp(out)))
+    return out[: grid.nnz_j]
+
+
+def pf_jacobian_scatter(grid: Grid, jval, jmap, out, stream=None):
+    """out[s, jmap[k]] = jval[s, k] (device tensors: jval float64 [nstate,
+    nnz_j] or [nnz_j], jmap int32 [nnz_j], out float64 [nstate, out_nnz] or
+    [out_nnz])."""
+    import torch
+    if not isinstance(jmap, torch.Tensor) or jmap.dtype != torch.int32 or not jmap.is_cuda \
+            or not jmap.is_contiguous() or tuple(jmap.shape) != (grid.nnz_j,):
+        raise ValueError("jmap must be a contiguous int32 CUDA tensor of nnz_j entries")
+    ns = 1 if jval.dim() == 1 else jval.shape[0]
+    jshp = (grid.nnz_j,) if jval.dim() == 1 else (ns, grid.nnz_j)
+    out_nnz = out.shape[-1]
+    oshp = (out_nnz,) if jval.dim() == 1 else (ns, out_nnz)
+    check(lib().pf_jacobian_scatter(grid.handle, ns, _dev(jval, jshp, "jval"), C.c_void_p(jmap.data_ptr()),
+                                    int(out_nnz), _dev(out, oshp, "out"), _stream(stream)))
 
 
 def pf_version() -> str:
