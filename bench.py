@@ -451,6 +451,18 @@ def main():
                               "achieved_GBs": abytes / (ev / K) / 1e9, "over_csr_time": (ev / K) / avg_launch,
                               "kernel": f"k_ew_csc<{tile}, false, true>", "bytes_read_extra": cb - abytes}
         log(f"element-wise S+J, CSC order: {ev / K * 1e6:.2f} us/launch")
+        for d in reps:
+            pf.pf_ybus(d["G"])
+        torch.cuda.synchronize()
+
+        def yb_csc(k, st):
+            d = reps[k % R]
+            pf.pf_jacobian_values(d["G"], pf.PF_METHOD_YBUS | pf.PF_JAC_CSC, d["vm"], d["va"], d["p"], d["q"], d["j"],
+                                  stream=st)
+        ev, wall = timed(yb_csc, K, W)
+        extra["ybus_sj_csc"] = {"evals_per_s": K / wall, "avg_launch_us": ev / K * 1e6,
+                                "kernel": f"k_ybus_csc<{tile}, true>"}
+        log(f"Ybus S+J, CSC order: {ev / K * 1e6:.2f} us/launch")
 
     if want("scatter"):
         # Algorithm 2's in-place copy into a larger pattern: J's entries plus the couplings of

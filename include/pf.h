@@ -178,12 +178,14 @@ int pf_injections_ybus(const pf_grid *g, int32_t nstate, const double *vm, const
  *           PF_METHOD_YBUS: eqs. (3)-(4) by the row-wise two-pass scheme
  *           (Section IV.B.2), written in place into J (PF_ESTATE before
  *           pf_ybus).
- *           PF_METHOD_ELEMENTWISE | PF_JAC_CSC: jval in column-major (CSC)
- *           order, the storage sparse direct solvers take (the paper keeps J
- *           in CSC, Section IV.A).  The pattern is structurally symmetric, so
- *           the CSC column pointers and row indices are the exported j_rowptr
- *           and j_col: value k of column c is J(j_col[k], c).  One launch, as
- *           for CSR; PF_EUNSUP with the other methods.
+ *           PF_METHOD_ELEMENTWISE or PF_METHOD_YBUS | PF_JAC_CSC: jval in
+ *           column-major (CSC) order, the storage sparse direct solvers take
+ *           (the paper keeps J in CSC, Section IV.A).  The pattern is
+ *           structurally symmetric, so the CSC column pointers and row
+ *           indices are the exported j_rowptr and j_col: value k of column c
+ *           is J(j_col[k], c); the values equal the CSR values transposed,
+ *           bit for bit.  One launch, as for CSR; PF_EUNSUP with the
+ *           two-phase and copy-add baselines.
  *   p, q    f64[nstate][nb] device outputs, or NULL to skip
  *   jval    f64[nstate][nnz_j] device output in the exported CSR order
  *           (CSC with PF_JAC_CSC). */

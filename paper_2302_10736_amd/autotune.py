@@ -23,7 +23,8 @@ from typing import Callable, Iterable, Optional, Sequence, Tuple
 
 from . import pf
 
-OPS = ("injections_ew", "injections_ybus", "jacobian_ew", "jacobian_ybus", "vjp", "jacobian_ew_csc")
+OPS = ("injections_ew", "injections_ybus", "jacobian_ew", "jacobian_ybus", "vjp", "jacobian_ew_csc",
+       "jacobian_ybus_csc")
 TILES = (64, 128, 256, 512)
 STATES_PER_BLOCK = (1, 2, 4, 8, 16, 32, 64)
 
@@ -140,6 +141,8 @@ def device_timer(grid: "pf.Grid", op: str, nstate: int, reps: int = 5, seed: int
             pf.pf_jacobian_values(grid, pf.PF_METHOD_YBUS, vm, va, a, b, j, stream=st)
         elif op == "jacobian_ew_csc":
             pf.pf_jacobian_values(grid, pf.PF_METHOD_ELEMENTWISE | pf.PF_JAC_CSC, vm, va, a, b, j, stream=st)
+        elif op == "jacobian_ybus_csc":
+            pf.pf_jacobian_values(grid, pf.PF_METHOD_YBUS | pf.PF_JAC_CSC, vm, va, a, b, j, stream=st)
         else:
             pf.pf_injections_vjp(grid, vm, va, lp, lq, a, b, stream=st)
 

@@ -162,6 +162,8 @@ struct HostLanes {
     std::vector<int32_t> ylane_j, ylane_slot, ylane_pk;
     std::vector<int32_t> row_ew, row_yb;                 // pairs per bus, + one inert entry at nb
     std::vector<int32_t> ydslot;                         // [nb] global Ybus slot of each diagonal
+    std::vector<int32_t> yt_slot;                        // [nnz_y] slot of the transposed entry
+    std::vector<int32_t> ylane_tslot;                    // transposed slot of each Ybus lane, -1 inert
 };
 
 HostLanes build_lanes(const pf_grid *g) {
@@ -188,6 +190,15 @@ HostLanes build_lanes(const pf_grid *g) {
         return g->yrow[i];  // every bus has its diagonal slot
     };
     for (int32_t i = 0; i < g->nb; ++i) h.ydslot[i] = diag_slot(i);
+    // (j, i) for every slot (i, j): the pattern is symmetric and columns ascend within a row
+    h.yt_slot.assign(g->nnz_y, 0);
+    for (int32_t i = 0; i < g->nb; ++i)
+        for (int32_t q = g->yrow[i]; q < g->yrow[i + 1]; ++q) {
+            const int32_t j = g->ycol[q];
+            const int32_t *a = g->ycol.data() + g->yrow[j], *z = g->ycol.data() + g->yrow[j + 1];
+            h.yt_slot[q] = (int32_t)(std::lower_bound(a, z, i) - g->ycol.data());
+        }
+    h.ylane_tslot.assign(nly, -1);
     for (size_t t = 0; t < g->tiles.size(); ++t) {
         const pf::TileDesc &c = g->tiles[t];
         const size_t base = t * NT;
@@ -233,6 +244,7 @@ HostLanes build_lanes(const pf_grid *g) {
                 const bool dg = g->ycol[q] == i;
                 h.ylane_j[L] = g->ycol[q];
                 h.ylane_slot[L] = q;
+                h.ylane_tslot[L] = h.yt_slot[q];
                 h.ylane_pk[L] = dg ? pf::yb_pack(ypad, ypad, row, true) : pf::yb_pack(ya + ls, yz + ls, row, false);
             }
         }
@@ -260,6 +272,7 @@ int upload_tiles(pf_grid *g) {
     const size_t o_yj = ar.take<int32_t>(nly), o_yslot = ar.take<int32_t>(nly), o_ypk = ar.take<int32_t>(nly);
     const size_t o_yy = ar.take<double2>(nly), o_ryb = ar.take<int2>(g->nb + 1);
     const size_t o_yds = ar.take<int32_t>(g->nb);
+    const size_t o_yts = ar.take<int32_t>(g->nnz_y), o_ylt = ar.take<int32_t>(nly), o_yyt = ar.take<double2>(nly);
     e = hipMalloc(&g->dtile, ar.off);
     if (e != hipSuccess) {
         g->dtile = nullptr;
@@ -283,6 +296,8 @@ int upload_tiles(pf_grid *g) {
     up(o_ypk, h.ylane_pk.data(), nly * 4);
     up(o_ryb, h.row_yb.data(), ((size_t)g->nb + 1) * 8);
     up(o_yds, h.ydslot.data(), (size_t)g->nb * 4);
+    up(o_yts, h.yt_slot.data(), (size_t)g->nnz_y * 4);
+    up(o_ylt, h.ylane_tslot.data(), nly * 4);
     if (ee != hipSuccess) return hip_fail(ee, "hipMemcpy(schedule)");
     pf::DevGrid &d = g->dev;
     d.tiles = reinterpret_cast<const pf::TileDesc *>(base + o_t);
@@ -299,6 +314,8 @@ int upload_tiles(pf_grid *g) {
     d.ylane_pk = reinterpret_cast<const int32_t *>(base + o_ypk);
     d.ylane_y = reinterpret_cast<const double2 *>(base + o_yy);
     d.row_yb = reinterpret_cast<const int2 *>(base + o_ryb);
+    d.yt_slot = reinterpret_cast<const int32_t *>(base + o_yts);
+    d.ylane_yt = reinterpret_cast<const double2 *>(base + o_yyt);
     pf::DevLaneFill &f = g->lanes;
     f.nlanes = (int64_t)nle;
     f.nylanes = (int64_t)nly;
@@ -313,6 +330,8 @@ int upload_tiles(pf_grid *g) {
     f.lane_gb = reinterpret_cast<double2 *>(base + o_lgb);
     f.lane_grbr = reinterpret_cast<double2 *>(base + o_lgr);
     f.ylane_y = reinterpret_cast<double2 *>(base + o_yy);
+    f.ylane_tslot = reinterpret_cast<const int32_t *>(base + o_ylt);
+    f.ylane_yt = reinterpret_cast<double2 *>(base + o_yyt);
     f.nb = g->nb;
     f.ydslot = reinterpret_cast<const int32_t *>(base + o_yds);
     // Record constants exist once the setup kernels ran; Ybus values once
@@ -831,8 +850,8 @@ int check_eval(const pf_grid *g, int32_t nstate) {
 int auto_states_per_block(const pf_grid *g, int kind, int32_t nstate) {
     if (g->states_per_block > 0) return std::min<int32_t>(g->states_per_block, std::max(nstate, 1));
     if (nstate <= 1) return 1;
-    const bool yb = kind == pf::K_YB_S || kind == pf::K_YB_SJ;
-    const bool with_j = kind == pf::K_EW_SJ || kind == pf::K_YB_SJ || kind == pf::K_EW_SJ_CSC;
+    const bool yb = kind == pf::K_YB_S || kind == pf::K_YB_SJ || kind == pf::K_YB_SJ_CSC;
+    const bool with_j = kind == pf::K_EW_SJ || kind == pf::K_YB_SJ || kind == pf::K_EW_SJ_CSC || kind == pf::K_YB_SJ_CSC;
     const int64_t nt = std::max<int64_t>(1, (int64_t)(yb ? g->ytiles : g->tiles).size());
     int per_cu = pf::resident_blocks_per_cu(kind, g->tile_items, g->has_parallel);
     if (per_cu <= 0) per_cu = 4;
@@ -944,8 +963,8 @@ int pf_jacobian_values(const pf_grid *g, int32_t method, int32_t nstate, const d
     if (method != PF_METHOD_ELEMENTWISE && method != PF_METHOD_YBUS && method != PF_METHOD_ELEMENTWISE_TWO_PHASE &&
         method != PF_METHOD_ELEMENTWISE_ATOMIC)
         return fail(PF_EINVAL, "unknown method");
-    if (csc && method != PF_METHOD_ELEMENTWISE)
-        return fail(PF_EUNSUP, "the CSC order is available with PF_METHOD_ELEMENTWISE only");
+    if (csc && method != PF_METHOD_ELEMENTWISE && method != PF_METHOD_YBUS)
+        return fail(PF_EUNSUP, "the CSC order is available with PF_METHOD_ELEMENTWISE and PF_METHOD_YBUS");
     if (pre && method != PF_METHOD_ELEMENTWISE_TWO_PHASE && method != PF_METHOD_ELEMENTWISE_ATOMIC)
         return fail(PF_EUNSUP, "PF_EW_PRECOMPUTED applies to the two-phase and copy-add methods");
     if (method == PF_METHOD_YBUS && !g->ybus_valid)
@@ -980,7 +999,8 @@ int pf_jacobian_values(const pf_grid *g, int32_t method, int32_t nstate, const d
         return PF_OK;
     }
     pf::Launch L{};
-    L.kind = method == PF_METHOD_ELEMENTWISE ? (csc ? pf::K_EW_SJ_CSC : pf::K_EW_SJ) : pf::K_YB_SJ;
+    L.kind = method == PF_METHOD_ELEMENTWISE ? (csc ? pf::K_EW_SJ_CSC : pf::K_EW_SJ)
+                                             : (csc ? pf::K_YB_SJ_CSC : pf::K_YB_SJ);
     L.nstate = nstate;
     L.vm = vm;
     L.va = va;
@@ -1106,7 +1126,8 @@ int op_kind(const pf_op &o) {
         case PF_OP_INJECTIONS:
             return o.method == PF_METHOD_YBUS ? pf::K_YB_S : pf::K_EW_S;
         case PF_OP_JACOBIAN:
-            if (o.method & PF_JAC_CSC) return pf::K_EW_SJ_CSC;
+            if (o.method & PF_JAC_CSC)
+                return (o.method & ~PF_JAC_CSC) == PF_METHOD_YBUS ? pf::K_YB_SJ_CSC : pf::K_EW_SJ_CSC;
             return o.method == PF_METHOD_YBUS ? pf::K_YB_SJ : pf::K_EW_SJ;
         default:
             return pf::K_EW_VJP;

@@ -74,6 +74,8 @@ struct DevGrid {
     const int32_t *ylane_pk;    // yb_pack(o11, o12, row, diag)
     const double2 *ylane_y;     // {Re Y, Im Y}
     const int2 *row_yb;         // [nb+1] {ya | yz << 16, dls}; [nb] inert
+    const double2 *ylane_yt;    // Ybus lane: {Re, Im} of the transposed entry Y_ji (CSC Jacobian)
+    const int32_t *yt_slot;     // [nnz_y] slot of the transposed entry (long rows, CSC Jacobian)
 };
 
 // Gather sources of the lane tables: record (element-wise) and slot (Ybus)
@@ -83,8 +85,9 @@ struct DevLaneFill {
     int32_t nb;
     const int32_t *lane_rec, *ylane_slot;
     const int32_t *ydslot;  // [nb] global slot of each bus's diagonal
+    const int32_t *ylane_tslot;  // transposed slot of each Ybus lane, -1 inert
     const double *G, *B, *Gr, *Br, *yre, *yim;
-    double2 *lane_gb, *lane_grbr, *ylane_y;
+    double2 *lane_gb, *lane_grbr, *ylane_y, *ylane_yt;
 };
 
 // Setup data, only read by the setup kernels.
@@ -122,7 +125,7 @@ struct DevTwoPhase {
     const double *bc;                       // [6][nl] precomputed G, B, A_from, C_from, A_to, C_to
 };
 
-enum Kind { K_EW_S = 0, K_EW_SJ = 1, K_YB_S = 2, K_YB_SJ = 3, K_EW_VJP = 4, K_EW_SJ_CSC = 5 };
+enum Kind { K_EW_S = 0, K_EW_SJ = 1, K_YB_S = 2, K_YB_SJ = 3, K_EW_VJP = 4, K_EW_SJ_CSC = 5, K_YB_SJ_CSC = 6 };
 
 // Phasor source of the Ybus kernels: formed on the fly from (vm, va), or
 // read from stored split / interleaved phasors (the values of the public

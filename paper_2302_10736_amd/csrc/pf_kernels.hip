@@ -583,10 +583,21 @@ __device__ __forceinline__ void yb_phasor(const YbIn &x, Cx &V, Cx &U) {
 // the row through LDS.
 // The single-state instantiation is held to 6 waves per SIMD (<= 80 VGPRs),
 // so a 100k-bus grid's workgroups are all resident at once.
-template <int NT, bool WITH_J, bool ONE, int PH>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? 6 : 1, 8)))
-    k_ybus(DevGrid g, int nstate, int spb, int nchunk, bool state_major, const double *__restrict__ vm, const double *__restrict__ va,
-           const double *__restrict__ ph, double *__restrict__ P, double *__restrict__ Q, double *__restrict__ J) {
+//
+// CSC = true (WITH_J, phasors on the fly) writes J in column-major order,
+// as k_ew_csc does: the nonzero (i, j) of row i receives the partials of
+// S_j with respect to bus i's angle and magnitude,
+//   dS_j/dtheta_i = j V_j (-conj(Y_ji V_i)),  dS_j/dv_i = V_j conj(Y_ji U_i),
+// from the transposed entry Y_ji, with the products rounded as the CSR
+// evaluation of row j rounds them (CSC values = CSR values transposed, bit
+// for bit), and the diagonal entries dQ_i/dtheta_i and dP_i/dv_i trade
+// places.
+template <int NT, bool WITH_J, bool ONE, int PH, bool CSC>
+__device__ __forceinline__ void yb_eval(const DevGrid &g, int nstate, int spb, int nchunk, bool state_major,
+                                        const double *__restrict__ vm, const double *__restrict__ va,
+                                        const double *__restrict__ ph, double *__restrict__ P,
+                                        double *__restrict__ Q, double *__restrict__ J) {
+    static_assert(!CSC || (WITH_J && PH == PH_FLY), "the CSC order concerns J values");
     constexpr int NBUF = ONE ? 1 : 2;
     __shared__ double s_yv[NBUF][2][NT];  // Y_ij V_j
     __shared__ double s_vu[NBUF][4][NT];  // per row: V_i, U_i (re, im)
@@ -604,6 +615,8 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? 6
     const int j = g.ylane_j[lane];
     const int pk = g.ylane_pk[lane];
     const double2 yl = g.ylane_y[lane];
+    double2 ylt = make_double2(0.0, 0.0);
+    if constexpr (CSC) ylt = g.ylane_yt[lane];
     const Tile c = g.ytiles[t];
     const size_t nb = (size_t)g.nb;
 
@@ -665,10 +678,29 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? 6
                     const Cx dst = cmul({-Vi.im, Vi.re}, x);                                  // j V_i x
                     Cx dsv = cmul(Vi, cconj(cmul(Y, Uj)));
                     if (dg) dsv = cadd(dsv, cmul(Ic, Ui));
-                    st_out(Js + c.jp + lp, dst.re);
-                    st_out(Js + c.jp + d + lp, dsv.re);
-                    st_out(Js + c.jq + lp, dst.im);
-                    st_out(Js + c.jq + d + lp, dsv.im);
+                    if constexpr (CSC) {
+                        double a0 = dst.re, a1 = dst.im, a2 = dsv.re, a3 = dsv.im;  // the diagonal
+                        if (!dg) {  // partials of S_jc with respect to bus i, from Y_(jc, i)
+                            const int pt = g.yt_slot[p];
+                            const Cx YT = {g.yre[pt], g.yim[pt]};
+                            const Cx yt = cmul(YT, Vi);
+                            const Cx so = cmul({-Vj.im, Vj.re}, {-yt.re, yt.im});
+                            const Cx vo = cmul(Vj, cconj(cmul(YT, Ui)));
+                            a0 = so.re;
+                            a1 = so.im;
+                            a2 = vo.re;
+                            a3 = vo.im;
+                        }
+                        st_out(Js + c.jp + lp, a0);
+                        st_out(Js + c.jp + d + lp, a1);
+                        st_out(Js + c.jq + lp, a2);
+                        st_out(Js + c.jq + d + lp, a3);
+                    } else {
+                        st_out(Js + c.jp + lp, dst.re);
+                        st_out(Js + c.jp + d + lp, dsv.re);
+                        st_out(Js + c.jq + lp, dst.im);
+                        st_out(Js + c.jq + d + lp, dsv.im);
+                    }
                 }
             }
             __syncthreads();
@@ -732,17 +764,29 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? 6
             const Cx dst = cmul({-Vk.im, Vk.re}, x2);
             const Cx dsv = cadd(cmul(Vk, cconj(yu)), cmul(Ic, Ui));
             s_J[p][dd11] = dst.re;
-            s_J[p][dd12] = dsv.re;
-            s_J[p][kQ<NT> + dd11] = dst.im;
+            s_J[p][dd12] = CSC ? dst.im : dsv.re;
+            s_J[p][kQ<NT> + dd11] = CSC ? dsv.re : dst.im;
             s_J[p][kQ<NT> + dd12] = dsv.im;
             // off-diagonal entry of this nonzero
             const Cx Vi = {s_vu[p][0][row], s_vu[p][1][row]};
-            const Cx dso = cmul({-Vi.im, Vi.re}, {-yv.re, yv.im});  // j V_i (-conj(Y_ij V_j))
-            const Cx dvo = cmul(Vi, cconj(cmul(Y, Uj)));
-            s_J[p][o11] = dso.re;
-            s_J[p][o12] = dvo.re;
-            s_J[p][kQ<NT> + o11] = dso.im;
-            s_J[p][kQ<NT> + o12] = dvo.im;
+            if constexpr (CSC) {
+                const Cx Uo = {s_vu[p][2][row], s_vu[p][3][row]};
+                const Cx YT = {ylt.x, ylt.y};
+                const Cx yt = cmul(YT, Vi);
+                const Cx so = cmul({-Vj.im, Vj.re}, {-yt.re, yt.im});  // j V_j (-conj(Y_ji V_i))
+                const Cx vo = cmul(Vj, cconj(cmul(YT, Uo)));
+                s_J[p][o11] = so.re;
+                s_J[p][o12] = so.im;
+                s_J[p][kQ<NT> + o11] = vo.re;
+                s_J[p][kQ<NT> + o12] = vo.im;
+            } else {
+                const Cx dso = cmul({-Vi.im, Vi.re}, {-yv.re, yv.im});  // j V_i (-conj(Y_ij V_j))
+                const Cx dvo = cmul(Vi, cconj(cmul(Y, Uj)));
+                s_J[p][o11] = dso.re;
+                s_J[p][o12] = dvo.re;
+                s_J[p][kQ<NT> + o11] = dso.im;
+                s_J[p][kQ<NT> + o12] = dvo.im;
+            }
         }
         if (P && rowt) {  // stores last (see k_ew)
             st_out(P + (size_t)s * nb + ir, S.re);
@@ -754,6 +798,21 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? 6
         }
     };
     pipelined_states<In, ONE>(sb, se, first, load, proc);
+}
+
+template <int NT, bool WITH_J, bool ONE, int PH>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? 6 : 1, 8)))
+    k_ybus(DevGrid g, int nstate, int spb, int nchunk, bool state_major, const double *__restrict__ vm, const double *__restrict__ va,
+           const double *__restrict__ ph, double *__restrict__ P, double *__restrict__ Q, double *__restrict__ J) {
+    yb_eval<NT, WITH_J, ONE, PH, false>(g, nstate, spb, nchunk, state_major, vm, va, ph, P, Q, J);
+}
+
+// Injections and J values in CSC order by the Ybus method.
+template <int NT, bool ONE>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? 6 : 1, 8)))
+    k_ybus_csc(DevGrid g, int nstate, int spb, int nchunk, bool state_major, const double *__restrict__ vm,
+               const double *__restrict__ va, double *__restrict__ P, double *__restrict__ Q, double *__restrict__ J) {
+    yb_eval<NT, true, ONE, PH_FLY, true>(g, nstate, spb, nchunk, state_major, vm, va, nullptr, P, Q, J);
 }
 
 // ===================================================================
@@ -1269,8 +1328,9 @@ __global__ void k_lane_fill(DevLaneFill f, bool ew) {
         f.lane_grbr[l] = e >= 0 ? make_double2(f.Gr[e], f.Br[e]) : make_double2(0.0, 0.0);
     } else {
         if (l < f.nylanes) {
-            const int q = f.ylane_slot[l];
+            const int q = f.ylane_slot[l], qt = f.ylane_tslot[l];
             f.ylane_y[l] = q >= 0 ? make_double2(f.yre[q], f.yim[q]) : make_double2(0.0, 0.0);
+            f.ylane_yt[l] = qt >= 0 ? make_double2(f.yre[qt], f.yim[qt]) : make_double2(0.0, 0.0);
         }
     }
 }
@@ -1297,7 +1357,11 @@ void launch_ybus_ph(const DevGrid &g, const Launch &L, dim3 grid, dim3 block, in
 template <int NT, bool ONE>
 hipError_t launch_ybus(const DevGrid &g, const Launch &L, dim3 grid, dim3 block, int spb, int nchunk, hipStream_t st) {
     if (L.phasor != PH_FLY && L.phasor != PH_SPLIT && L.phasor != PH_INTERLEAVED) return hipErrorInvalidValue;
-    if (L.kind == K_YB_SJ)
+    if (L.kind == K_YB_SJ_CSC) {
+        if (L.phasor != PH_FLY) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_ybus_csc<NT, ONE>), grid, block, 0, st, g, L.nstate, spb, nchunk, L.state_major, L.vm, L.va,
+                           L.p, L.q, L.jval);
+    } else if (L.kind == K_YB_SJ)
         launch_ybus_ph<NT, ONE, true>(g, L, grid, block, spb, nchunk, st);
     else
         launch_ybus_ph<NT, ONE, false>(g, L, grid, block, spb, nchunk, st);
@@ -1308,7 +1372,7 @@ template <int NT, bool ONE>
 hipError_t launch_nt(const DevGrid &g, const Launch &L, hipStream_t st) {
     const int spb = L.states_per_block;
     const int nchunk = (L.nstate + spb - 1) / spb;
-    const bool yb = L.kind == K_YB_S || L.kind == K_YB_SJ;
+    const bool yb = L.kind == K_YB_S || L.kind == K_YB_SJ || L.kind == K_YB_SJ_CSC;
     const int64_t work = (int64_t)(yb ? g.nytiles : g.ntiles) * nchunk;
     const int64_t blocks = (work + kXcds - 1) / kXcds * kXcds;
     if (blocks > INT32_MAX) return hipErrorInvalidConfiguration;
@@ -1340,6 +1404,7 @@ hipError_t launch_nt(const DevGrid &g, const Launch &L, hipStream_t st) {
             break;
         case K_YB_S:
         case K_YB_SJ:
+        case K_YB_SJ_CSC:
             return launch_ybus<NT, ONE>(g, L, grid, block, spb, nchunk, st);
         case K_EW_VJP:
             hipLaunchKernelGGL((k_ew_vjp<NT, ONE>), grid, block, 0, st, g, L.nstate, spb, nchunk, L.state_major, L.vm, L.va, L.lp, L.lq,
@@ -1374,6 +1439,9 @@ int occupancy_nt(int kind, bool par) {
             break;
         case K_YB_SJ:
             q(reinterpret_cast<const void *>(&k_ybus<NT, true, ONE, PH_FLY>));
+            break;
+        case K_YB_SJ_CSC:
+            q(reinterpret_cast<const void *>(&k_ybus_csc<NT, ONE>));
             break;
         case K_EW_VJP:
             q(reinterpret_cast<const void *>(&k_ew_vjp<NT, ONE>));
@@ -1410,8 +1478,8 @@ hipError_t launch_eval(const DevGrid &g, const Launch &L, hipStream_t stream) {
 int resident_blocks_per_cu(int kind, int tile_items, bool has_parallel) {
     // One value per (kind, tile size, parallel flag): a property of the
     // compiled kernel and the device, so concurrent first calls agree.
-    static std::atomic<int> cache[6][4][2] = {};
-    if (kind < 0 || kind > 5) return 0;
+    static std::atomic<int> cache[7][4][2] = {};
+    if (kind < 0 || kind > 6) return 0;
     const int ti = tile_items == 64 ? 0 : tile_items == 128 ? 1 : tile_items == 256 ? 2 : tile_items == 512 ? 3 : -1;
     if (ti < 0) return 0;
     std::atomic<int> &slot = cache[kind][ti][has_parallel ? 1 : 0];

@@ -5,8 +5,8 @@ and the interleaved layout, must give bit-identical P, Q and J values to the
 fused Ybus calls (which form the phasors on the fly with the same
 arithmetic), and therefore the oracle's values within the parity gate.
 
-CSC order (PF_JAC_CSC): the element-wise Jacobian written column by column
-must be the CSR values transposed, bit for bit, and the oracle's J
+CSC order (PF_JAC_CSC): the Jacobian written column by column, by either
+method, must be the CSR values transposed, bit for bit, and the oracle's J
 transposed within the parity gate.
 """
 from __future__ import annotations
@@ -154,18 +154,20 @@ def _grid_perms(G, bus_off=None):
     return perm
 
 
-def _csc_case(g, vm, va, tile, spb, bus_off=None, br_off=None):
+def _csc_case(g, vm, va, tile, spb, bus_off=None, br_off=None, method=pf.PF_METHOD_ELEMENTWISE):
     import torch
     G = pf.Grid.from_grid(g, bus_off, br_off)
     G.set_schedule(tile, spb)
+    if method == pf.PF_METHOD_YBUS:
+        pf.pf_ybus(G)
     ns = vm.shape[0]
     vmd, vad = to_dev(vm), to_dev(va)
     p0, q0 = torch.empty_like(vmd), torch.empty_like(vmd)
     j0 = torch.empty(ns, G.nnz_j, dtype=torch.float64, device="cuda:0")
-    pf.pf_jacobian_values(G, pf.PF_METHOD_ELEMENTWISE, vmd, vad, p0, q0, j0)
+    pf.pf_jacobian_values(G, method, vmd, vad, p0, q0, j0)
     p1, q1 = torch.full_like(vmd, np.nan), torch.full_like(vmd, np.nan)
     j1 = torch.full_like(j0, np.nan)
-    pf.pf_jacobian_values(G, pf.PF_METHOD_ELEMENTWISE | pf.PF_JAC_CSC, vmd, vad, p1, q1, j1)
+    pf.pf_jacobian_values(G, method | pf.PF_JAC_CSC, vmd, vad, p1, q1, j1)
     torch.cuda.synchronize()
     perm = _grid_perms(G, bus_off)
     j0h, j1h = j0.cpu().numpy(), j1.cpu().numpy()
@@ -175,16 +177,18 @@ def _csc_case(g, vm, va, tile, spb, bus_off=None, br_off=None):
     return G, j1h
 
 
-def test_csc_config0_against_oracle():
+@pytest.mark.parametrize("method", [pf.PF_METHOD_ELEMENTWISE, pf.PF_METHOD_YBUS])
+def test_csc_config0_against_oracle(method):
     import scipy.sparse as sp
     g = gridgen.config0()
     vm, va = gridgen.states(g.nb, 2, cfg=0)
-    G, jcsc = _csc_case(g, vm, va, 256, 0)
+    G, jcsc = _csc_case(g, vm, va, 256, 0, method=method)
     yr, yc, jr, jc = G.pattern()
     yb = oracle.ybus(g)
     pat = oracle.jac_pattern(yb)
     for s in range(2):
-        jo = oracle.jac_ew(g, vm[s], va[s], pat)
+        jo = (oracle.jac_ew(g, vm[s], va[s], pat) if method == pf.PF_METHOD_ELEMENTWISE
+              else oracle.jac_ybus(yb, vm[s], va[s], pat))
         A = sp.csr_matrix((jo, pat[1], pat[0]), shape=(2 * g.nb, 2 * g.nb))
         # CSC values = column by column: the CSR data of the transpose
         T = A.T.tocsr()
@@ -192,23 +196,25 @@ def test_csc_config0_against_oracle():
         assert rel_err(jcsc[s], T.data) <= TOL
 
 
+@pytest.mark.parametrize("method", [pf.PF_METHOD_ELEMENTWISE, pf.PF_METHOD_YBUS])
 @pytest.mark.parametrize("tile", [64, 256, 512])
-def test_csc_edge_grids(tile):
+def test_csc_edge_grids(tile, method):
     for g in (_grids.random_small(80, 150, 21, parallel=9, isolated=4), star_grid(700, seed=1),
               star_grid(600, seed=2, parallel=40), _grids.two_bus(0.01, 0.1, 0.02, 1.03, 0.04, flip=True)):
         vm, va = _grids.random_state(g.nb, 3)
-        _csc_case(g, vm[None, :], va[None, :], tile, 1)
+        _csc_case(g, vm[None, :], va[None, :], tile, 1, method=method)
 
 
-def test_csc_batched_and_multigrid():
+@pytest.mark.parametrize("method", [pf.PF_METHOD_ELEMENTWISE, pf.PF_METHOD_YBUS])
+def test_csc_batched_and_multigrid(method):
     g = gridgen.config0()
     vm, va = gridgen.states(g.nb, 11, cfg=0)
-    _csc_case(g, vm, va, 128, 3)
+    _csc_case(g, vm, va, 128, 3, method=method)
     grids = [_grids.random_small(n, int(n * 1.4), 70 + n, parallel=n % 4) for n in (5, 40, 300, 17, 2)]
     grids.append(star_grid(530, seed=9))
     big, bo, ro = gridgen.concat(grids)
     vm, va = _grids.random_state(big.nb, 7)
-    _csc_case(big, vm[None, :], va[None, :], 256, 0, bo, ro)
+    _csc_case(big, vm[None, :], va[None, :], 256, 0, bo, ro, method=method)
 
 
 def test_csc_other_methods_unsupported():
@@ -217,7 +223,7 @@ def test_csc_other_methods_unsupported():
     pf.pf_ybus(G)
     vm = torch.ones(G.nb, dtype=torch.float64, device="cuda:0")
     j = torch.empty(G.nnz_j, dtype=torch.float64, device="cuda:0")
-    for m in (pf.PF_METHOD_YBUS, pf.PF_METHOD_ELEMENTWISE_TWO_PHASE):
+    for m in (pf.PF_METHOD_ELEMENTWISE_TWO_PHASE, pf.PF_METHOD_ELEMENTWISE_ATOMIC):
         with pytest.raises(pf.PFError) as e:
             pf.pf_jacobian_values(G, m | pf.PF_JAC_CSC, vm, vm, None, None, j)
         assert e.value.code == pf.PF_EUNSUP
@@ -296,6 +302,7 @@ def test_variants_config1_full_size():
     g = gridgen.config1()
     vm, va = gridgen.states(g.nb, 1, cfg=1)
     _csc_case(g, vm, va, 256, 0)
+    _csc_case(g, vm, va, 256, 0, method=pf.PF_METHOD_YBUS)
     for layout in LAYOUTS:
         r = _phasor_case(g, vm, va, 256, 0, layout)
         assert np.array_equal(r["p1"], r["p0"]) and np.array_equal(r["q1"], r["q0"])
