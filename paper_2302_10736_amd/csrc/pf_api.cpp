@@ -842,11 +842,12 @@ int check_eval(const pf_grid *g, int32_t nstate) {
 // workgroups read the constants fewer times, while more, shorter workgroups
 // keep more of every state's output stream in flight.  The automatic choice
 // takes at most 2 states per workgroup for Jacobian launches (their time is
-// the J stream: 8 nnzJ bytes per state against a few bytes of constants) and
-// at most 8 for injections and the adjoint (small per-state outputs, so
-// reusing the constants pays), and fewer when the tiles alone would leave
-// part of one round of resident workgroups empty (it then splits each tile's
-// states into about resident capacity / tiles chunks).
+// the J stream: 8 nnzJ bytes per state against a few bytes of constants),
+// 1 when the tables are small enough to stay in L2 between states, and at
+// most 8 for injections and the adjoint (small per-state outputs, so reusing
+// the constants pays); fewer when the tiles alone would leave part of one
+// round of resident workgroups empty (it then splits each tile's states into
+// about resident capacity / tiles chunks).
 int auto_states_per_block(const pf_grid *g, int kind, int32_t nstate) {
     if (g->states_per_block > 0) return std::min<int32_t>(g->states_per_block, std::max(nstate, 1));
     if (nstate <= 1) return 1;
@@ -859,7 +860,15 @@ int auto_states_per_block(const pf_grid *g, int kind, int32_t nstate) {
     int64_t chunks = std::max<int64_t>(1, capacity / nt);
     chunks = std::min<int64_t>(chunks, nstate);
     const int fill = (int)((nstate + chunks - 1) / chunks);
-    return std::min(fill, with_j ? 2 : 8);
+    if (with_j) {
+        // One state per workgroup (the lean single-state kernel) when the
+        // tile tables a state walks (about 24 bytes per lane and per bus)
+        // stay in one XCD's 4 MB L2 across states; else two.
+        const int64_t lanes = nt * (int64_t)g->tile_items;
+        const int64_t table_bytes = 24 * lanes + 24 * (int64_t)g->nb;
+        return std::min(fill, table_bytes <= (int64_t)2 << 20 ? 1 : 2);
+    }
+    return std::min(fill, 8);
 }
 
 // Scratch of the two-phase element-wise method: ten values per record,
