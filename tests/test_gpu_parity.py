@@ -161,7 +161,7 @@ def test_determinism_across_runs_and_schedules():
 
 
 def test_graph_replays_match_eager_calls():
-    """A recorded [injections, Jacobian (both methods), VJP] sequence, replayed
+    """A recorded [injections, Jacobian (both methods), VJP, Jacobian in CSC order] sequence, replayed
     several times with eager work and input changes in between; every replay
     equals the eager calls bit for bit."""
     import torch
@@ -176,36 +176,39 @@ def test_graph_replays_match_eager_calls():
     lp, lq = dev(rng.normal(size=(ns, g.nb))), dev(rng.normal(size=(ns, g.nb)))
     z = lambda *sh: torch.zeros(*sh, dtype=torch.float64, device="cuda:0")
     out = {k: z(ns, g.nb) for k in ("p", "q", "p2", "q2", "p3", "q3", "gvm", "gva")}
-    j_ew, j_yb = z(ns, G.nnz_j), z(ns, G.nnz_j)
+    j_ew, j_yb, j_cs = z(ns, G.nnz_j), z(ns, G.nnz_j), z(ns, G.nnz_j)
     ops = [
         dict(op=pf.PF_OP_INJECTIONS, method=pf.PF_METHOD_ELEMENTWISE, vm=vm, va=va, out_a=out["p"], out_b=out["q"]),
         dict(op=pf.PF_OP_JACOBIAN, method=pf.PF_METHOD_ELEMENTWISE, vm=vm, va=va, out_a=out["p2"], out_b=out["q2"],
              jval=j_ew),
         dict(op=pf.PF_OP_JACOBIAN, method=pf.PF_METHOD_YBUS, vm=vm, va=va, out_a=out["p3"], out_b=out["q3"], jval=j_yb),
         dict(op=pf.PF_OP_VJP, vm=vm, va=va, lam_p=lp, lam_q=lq, out_a=out["gvm"], out_b=out["gva"]),
+        dict(op=pf.PF_OP_JACOBIAN, method=pf.PF_METHOD_YBUS | pf.PF_JAC_CSC, vm=vm, va=va, jval=j_cs),
     ]
     gr = pf.Graph(G, ops)
 
     def eager():
         e = {k: z(ns, g.nb) for k in out}
-        je, jy = z(ns, G.nnz_j), z(ns, G.nnz_j)
+        je, jy, jc = z(ns, G.nnz_j), z(ns, G.nnz_j), z(ns, G.nnz_j)
         pf.pf_injections_elementwise(G, vm, va, e["p"], e["q"])
         pf.pf_jacobian_values(G, pf.PF_METHOD_ELEMENTWISE, vm, va, e["p2"], e["q2"], je)
         pf.pf_jacobian_values(G, pf.PF_METHOD_YBUS, vm, va, e["p3"], e["q3"], jy)
         pf.pf_injections_vjp(G, vm, va, lp, lq, e["gvm"], e["gva"])
+        pf.pf_jacobian_values(G, pf.PF_METHOD_YBUS | pf.PF_JAC_CSC, vm, va, None, None, jc)
         torch.cuda.synchronize()
-        return {k: v.cpu().numpy() for k, v in e.items()}, je.cpu().numpy(), jy.cpu().numpy()
+        return {k: v.cpu().numpy() for k, v in e.items()}, je.cpu().numpy(), jy.cpu().numpy(), jc.cpu().numpy()
 
     for rep in range(4):
-        for t in list(out.values()) + [j_ew, j_yb]:
+        for t in list(out.values()) + [j_ew, j_yb, j_cs]:
             t.fill_(float("nan"))
         gr.launch()
         torch.cuda.synchronize()
-        want, je, jy = eager()
+        want, je, jy, jc = eager()
         for k in out:
             assert np.array_equal(out[k].cpu().numpy(), want[k]), (rep, k)
         assert np.array_equal(j_ew.cpu().numpy(), je), rep
         assert np.array_equal(j_yb.cpu().numpy(), jy), rep
+        assert np.array_equal(j_cs.cpu().numpy(), jc), rep
         vm.mul_(1.0 + 0.01 * (rep + 1))  # the next replay reads the new inputs
         va.add_(0.02)
     # within tolerance of the oracle too (last inputs, state 0)
