@@ -48,7 +48,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 # sources that decide the headline kernel's memory traffic (kernels and lane-table layout)
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2302_10736_amd", "csrc", f) for f in ("pf_kernels.hip", "pf_api.cpp")]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_ew_cfg1_100k_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_ew_100k_1state_traffic.json")
 HEADLINE_KERNEL = "k_ew<256, false, true, true>"  # element-wise S+J, one state per workgroup
 COPY_PROBE_DOUBLES = 4 * 1024 * 1024  # 32 MiB read + 32 MiB written by the calibration copy
 
@@ -158,7 +158,7 @@ def size_sweep(torch, gridgen, pf, log):
     rows = []
     for idx, (nb, reps_k) in enumerate(cases):
         if reps_k is None:
-            g = gridgen.make_grid(nb, round(1.27 * nb), 0.15, cfg=5, grid=idx)
+            g = gridgen.make_grid(nb, round(1.27 * nb), 0.15, case=5, grid=idx)
             if nb == 82_000:
                 base82 = g
             G = pf.Grid.from_grid(g)
@@ -168,7 +168,7 @@ def size_sweep(torch, gridgen, pf, log):
             G = pf.Grid.from_grid(big, bo, ro)
             ntot = big.nb
         pf.pf_ybus(G)
-        vm, va = gridgen.states(ntot, 1, cfg=5, grid=idx)
+        vm, va = gridgen.states(ntot, 1, case=5, grid=idx)
         a, b = torch.as_tensor(vm, device=dev), torch.as_tensor(va, device=dev)
         p, q = torch.empty_like(a), torch.empty_like(a)
         j = torch.empty(1, G.nnz_j, dtype=torch.float64, device=dev)
@@ -235,8 +235,8 @@ def main():
         return
 
     # ------------------------------------------------------------ workload
-    g = gridgen.config1()
-    vm, va = gridgen.states(g.nb, 1, cfg=1)
+    g = gridgen.grid_100k()
+    vm, va = gridgen.states(g.nb, 1, case=1)
     R = max(1, args.replicas)
     reps = []
     for r in range(R):
@@ -606,9 +606,9 @@ def main():
     torch.cuda.empty_cache()
 
     if want("batched"):
-        g2 = gridgen.config2()
+        g2 = gridgen.grid_20k()
         B = 512
-        vm2, va2 = gridgen.states(g2.nb, B, cfg=2, vlo=0.9, vhi=1.1, sigma=0.3)
+        vm2, va2 = gridgen.states(g2.nb, B, case=2, vlo=0.9, vhi=1.1, sigma=0.3)
         G2 = pf.Grid.from_grid(g2)
         vm2d, va2d = torch.as_tensor(vm2, device=dev), torch.as_tensor(va2, device=dev)
         p2 = torch.empty(B, g2.nb, dtype=torch.float64, device=dev)
@@ -654,11 +654,11 @@ def main():
         torch.cuda.empty_cache()
 
     if want("multigrid"):
-        grids = gridgen.config3()
+        grids = gridgen.grids_uneven_64()
         big, bo, ro = gridgen.concat(grids)
         G3 = pf.Grid.from_grid(big, bo, ro)
-        vm3 = np.concatenate([gridgen.states(gr.nb, 4, cfg=3, grid=k + 1)[0] for k, gr in enumerate(grids)], axis=1)
-        va3 = np.concatenate([gridgen.states(gr.nb, 4, cfg=3, grid=k + 1)[1] for k, gr in enumerate(grids)], axis=1)
+        vm3 = np.concatenate([gridgen.states(gr.nb, 4, case=3, grid=k + 1)[0] for k, gr in enumerate(grids)], axis=1)
+        va3 = np.concatenate([gridgen.states(gr.nb, 4, case=3, grid=k + 1)[1] for k, gr in enumerate(grids)], axis=1)
         vm3d, va3d = torch.as_tensor(vm3, device=dev), torch.as_tensor(va3, device=dev)
         p3 = torch.empty(4, big.nb, dtype=torch.float64, device=dev)
         q3 = torch.empty_like(p3)
@@ -700,8 +700,8 @@ def main():
 
     if want("adjoint"):
         B = 32
-        vm4, va4 = gridgen.states(g.nb, B, cfg=4)
-        lp4, lq4 = gridgen.adjoint_seeds(g.nb, B, cfg=4)
+        vm4, va4 = gridgen.states(g.nb, B, case=4)
+        lp4, lq4 = gridgen.adjoint_seeds(g.nb, B, case=4)
         G4 = pf.Grid.from_grid(g)
         t = lambda a: torch.as_tensor(a, device=dev)
         vm4d, va4d, lp4d, lq4d = t(vm4), t(va4), t(lp4), t(lq4)
@@ -737,8 +737,8 @@ def main():
         # the evaluation as the inner step of a Newton-Raphson power flow: 5000-bus
         # grid, 20 % PV buses, start near the solution; host sparse LU per iteration
         from paper_2302_10736_amd import newton
-        g5 = gridgen.make_grid(5000, 6750, 0.15, cfg=2)
-        vm5, va5 = gridgen.states(g5.nb, 1, cfg=2, vlo=0.98, vhi=1.02, sigma=0.02)
+        g5 = gridgen.make_grid(5000, 6750, 0.15, case=2)
+        vm5, va5 = gridgen.states(g5.nb, 1, case=2, vlo=0.98, vhi=1.02, sigma=0.02)
         G5 = pf.Grid.from_grid(g5)
         # specified powers: the injections at the chosen state
         p5 = torch.empty(1, g5.nb, dtype=torch.float64, device=dev)
@@ -794,8 +794,8 @@ def main():
             # the batched workload's states on the oracle, one state per task over the host's cores
             # (the C oracle releases the interpreter lock, so the threads run in parallel)
             from concurrent.futures import ThreadPoolExecutor
-            g2 = gridgen.config2()
-            vm2, va2 = gridgen.states(g2.nb, 512, cfg=2, vlo=0.9, vhi=1.1, sigma=0.3)
+            g2 = gridgen.grid_20k()
+            vm2, va2 = gridgen.states(g2.nb, 512, case=2, vlo=0.9, vhi=1.1, sigma=0.3)
             pat2 = oracle.jac_pattern(oracle.ybus(g2))
             ns_cpu = 512
             threads = max(1, min(16, os.cpu_count() or 1))

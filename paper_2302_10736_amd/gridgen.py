@@ -28,9 +28,11 @@ Recipe (every grid):
 * states: vm ~ U(lo, hi), va ~ N(0, sigma) radians;
 * adjoint seeds: lambda_P, lambda_Q ~ N(0, 1).
 
-Streams: ``numpy.random.Generator(PCG64(SeedSequence([2302, 10736, cfg,
-grid, stream])))`` with stream 0 = topology and parameters, 1 = states,
-2 = adjoint seeds, 3 = sampled coordinates.
+Streams: ``numpy.random.Generator(PCG64(SeedSequence([2302, 10736, case,
+grid, stream])))`` with case numbering the workload (0: 500 buses, 1: 100k
+buses, 2: 20k buses x 512 states, 3: 64 uneven grids, 4: the adjoint states
+on the 100k-bus grid, 5: the size sweep), stream 0 = topology and
+parameters, 1 = states, 2 = adjoint seeds, 3 = sampled coordinates.
 """
 from __future__ import annotations
 
@@ -42,8 +44,8 @@ import numpy as np
 SEED_ROOT = (2302, 10736)
 
 
-def rng(cfg: int, grid: int, stream: int) -> np.random.Generator:
-    return np.random.Generator(np.random.PCG64(np.random.SeedSequence([*SEED_ROOT, cfg, grid, stream])))
+def rng(case: int, grid: int, stream: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(np.random.SeedSequence([*SEED_ROOT, case, grid, stream])))
 
 
 @dataclass
@@ -112,10 +114,10 @@ def _extra_edges(nb: int, parent: np.ndarray, n_extra: int, g: np.random.Generat
     return np.asarray(out, dtype=np.int64)
 
 
-def make_grid(nb: int, nl: int, xf_frac: float, cfg: int, grid: int = 0) -> Grid:
+def make_grid(nb: int, nl: int, xf_frac: float, case: int, grid: int = 0) -> Grid:
     if nb < 2 or nl < nb - 1:
         raise ValueError("need nb >= 2 and nl >= nb - 1 for a connected grid")
-    g = rng(cfg, grid, 0)
+    g = rng(case, grid, 0)
     parent = _tree(nb, g)
     tree = np.stack([np.arange(1, nb, dtype=np.int64), parent], axis=1)
     extra = _extra_edges(nb, parent, nl - (nb - 1), g)
@@ -139,26 +141,26 @@ def make_grid(nb: int, nl: int, xf_frac: float, cfg: int, grid: int = 0) -> Grid
     gs[sh] = g.uniform(0.0, 0.02, nsh)
     bs[sh] = g.uniform(-0.1, 0.1, nsh)
     return Grid(nb, nl, fbus, tbus, r, x, b, tap, shift, gs, bs,
-                meta={"cfg": cfg, "grid": grid, "xf_frac": xf_frac})
+                meta={"case": case, "grid": grid, "xf_frac": xf_frac})
 
 
-def states(nb: int, nstate: int, cfg: int, grid: int = 0, vlo: float = 0.95, vhi: float = 1.05,
+def states(nb: int, nstate: int, case: int, grid: int = 0, vlo: float = 0.95, vhi: float = 1.05,
            sigma: float = 0.2) -> tuple[np.ndarray, np.ndarray]:
     """vm, va as float64 [nstate, nb]."""
-    g = rng(cfg, grid, 1)
+    g = rng(case, grid, 1)
     vm = g.uniform(vlo, vhi, (nstate, nb))
     va = g.normal(0.0, sigma, (nstate, nb))
     return vm, va
 
 
-def adjoint_seeds(nb: int, nstate: int, cfg: int, grid: int = 0) -> tuple[np.ndarray, np.ndarray]:
-    g = rng(cfg, grid, 2)
+def adjoint_seeds(nb: int, nstate: int, case: int, grid: int = 0) -> tuple[np.ndarray, np.ndarray]:
+    g = rng(case, grid, 2)
     return g.normal(0.0, 1.0, (nstate, nb)), g.normal(0.0, 1.0, (nstate, nb))
 
 
-def sample_coords(nstate: int, nb: int, count: int, cfg: int, grid: int = 0) -> np.ndarray:
+def sample_coords(nstate: int, nb: int, count: int, case: int, grid: int = 0) -> np.ndarray:
     """``count`` (state, var, bus) triples, var 0 = vm, 1 = va."""
-    g = rng(cfg, grid, 3)
+    g = rng(case, grid, 3)
     return np.stack([g.integers(0, nstate, count), g.integers(0, 2, count), g.integers(0, nb, count)], axis=1)
 
 
@@ -166,22 +168,22 @@ def sample_coords(nstate: int, nb: int, count: int, cfg: int, grid: int = 0) -> 
 # The five workloads
 
 
-def config0() -> Grid:
+def grid_500() -> Grid:
     """500 buses, 700 branches, 15 % transformers."""
-    return make_grid(500, 700, 0.15, cfg=0)
+    return make_grid(500, 700, 0.15, case=0)
 
 
-def config1() -> Grid:
+def grid_100k() -> Grid:
     """100,000 buses, 130,000 branches, 20 % transformers."""
-    return make_grid(100_000, 130_000, 0.20, cfg=1)
+    return make_grid(100_000, 130_000, 0.20, case=1)
 
 
-def config2() -> Grid:
+def grid_20k() -> Grid:
     """20,000 buses, 27,000 branches, 15 % transformers (batched states)."""
-    return make_grid(20_000, 27_000, 0.15, cfg=2)
+    return make_grid(20_000, 27_000, 0.15, case=2)
 
 
-def config3_sizes(ngrid: int = 64) -> list[tuple[int, int]]:
+def uneven_sizes(ngrid: int = 64) -> list[tuple[int, int]]:
     """(nb, nl) of the uneven grids: nb log-uniform in [1e3, 8e4], nl = nb U(1.2, 1.5)."""
     g = rng(3, 0, 0)
     nb = np.rint(np.exp(g.uniform(math.log(1e3), math.log(8e4), ngrid))).astype(np.int64)
@@ -190,8 +192,8 @@ def config3_sizes(ngrid: int = 64) -> list[tuple[int, int]]:
     return [(int(a), int(c)) for a, c in zip(nb, nl)]
 
 
-def config3(ngrid: int = 64) -> list[Grid]:
-    return [make_grid(nb, nl, 0.15, cfg=3, grid=k + 1) for k, (nb, nl) in enumerate(config3_sizes(ngrid))]
+def grids_uneven_64(ngrid: int = 64) -> list[Grid]:
+    return [make_grid(nb, nl, 0.15, case=3, grid=k + 1) for k, (nb, nl) in enumerate(uneven_sizes(ngrid))]
 
 
 def concat(grids: list[Grid]) -> tuple[Grid, np.ndarray, np.ndarray]:

@@ -20,4 +20,4 @@ def pytest_collection_modifyitems(config, items):
 @pytest.fixture(scope="session")
 def cfg0():
     from paper_2302_10736_amd import gridgen
-    return gridgen.config0()
+    return gridgen.grid_500()

@@ -63,7 +63,7 @@ def test_unknown_op_rejected():
 def test_tune_on_device_keeps_results(tmp_path):
     import torch
     from tests._gpu import to_dev
-    g = gridgen.config0()
+    g = gridgen.grid_500()
     G = pf.Grid.from_grid(g)
     rng = np.random.default_rng(4)
     vm, va = to_dev(rng.uniform(0.95, 1.05, (6, g.nb))), to_dev(rng.normal(0, 0.2, (6, g.nb)))

@@ -57,7 +57,7 @@ def per_grid_oracle_pattern(grids):
 
 
 @pytest.mark.parametrize("make", [
-    lambda: gridgen.config0(),
+    lambda: gridgen.grid_500(),
     lambda: _grids.random_small(50, 90, 1, parallel=6, isolated=3),
     lambda: _grids.random_small(2, 9, 2, parallel=8),
     lambda: _grids.two_bus(0.01, 0.1, 0.0, 1.0, 0.0, flip=True),
@@ -208,7 +208,7 @@ def test_graph_create_argument_checks():
 
 
 def test_schedule_choices():
-    G = pf.Grid.from_grid(gridgen.config0(), host_only=True)
+    G = pf.Grid.from_grid(gridgen.grid_500(), host_only=True)
     for cap in (64, 128, 256, 512):
         G.set_schedule(cap, 0)
         t, spb, order, nt = G.schedule()

@@ -83,9 +83,9 @@ def _check_phasor_case(g, vm, va, tile, spb, layout):
 
 
 @pytest.mark.parametrize("layout", LAYOUTS)
-def test_phasor_variants_config0_batched(layout):
-    g = gridgen.config0()
-    vm, va = gridgen.states(g.nb, 5, cfg=0)
+def test_phasor_variants_grid_500_batched(layout):
+    g = gridgen.grid_500()
+    vm, va = gridgen.states(g.nb, 5, case=0)
     _check_phasor_case(g, vm, va, 256, 0, layout)
     _check_phasor_case(g, vm, va, 128, 3, layout)
 
@@ -101,7 +101,7 @@ def test_phasor_variants_long_rows_and_ragged(layout, tile):
 
 def test_phasor_argument_checks():
     import torch
-    G = pf.Grid.from_grid(gridgen.config0())
+    G = pf.Grid.from_grid(gridgen.grid_500())
     L = pf.lib()
     vm = torch.ones(G.nb, dtype=torch.float64, device="cuda:0")
     ph = torch.empty(4 * G.nb + 2, dtype=torch.float64, device="cuda:0")
@@ -178,10 +178,10 @@ def _csc_case(g, vm, va, tile, spb, bus_off=None, br_off=None, method=pf.PF_METH
 
 
 @pytest.mark.parametrize("method", [pf.PF_METHOD_ELEMENTWISE, pf.PF_METHOD_YBUS])
-def test_csc_config0_against_oracle(method):
+def test_csc_grid_500_against_oracle(method):
     import scipy.sparse as sp
-    g = gridgen.config0()
-    vm, va = gridgen.states(g.nb, 2, cfg=0)
+    g = gridgen.grid_500()
+    vm, va = gridgen.states(g.nb, 2, case=0)
     G, jcsc = _csc_case(g, vm, va, 256, 0, method=method)
     yr, yc, jr, jc = G.pattern()
     yb = oracle.ybus(g)
@@ -207,8 +207,8 @@ def test_csc_edge_grids(tile, method):
 
 @pytest.mark.parametrize("method", [pf.PF_METHOD_ELEMENTWISE, pf.PF_METHOD_YBUS])
 def test_csc_batched_and_multigrid(method):
-    g = gridgen.config0()
-    vm, va = gridgen.states(g.nb, 11, cfg=0)
+    g = gridgen.grid_500()
+    vm, va = gridgen.states(g.nb, 11, case=0)
     _csc_case(g, vm, va, 128, 3, method=method)
     grids = [_grids.random_small(n, int(n * 1.4), 70 + n, parallel=n % 4) for n in (5, 40, 300, 17, 2)]
     grids.append(star_grid(530, seed=9))
@@ -219,7 +219,7 @@ def test_csc_batched_and_multigrid(method):
 
 def test_csc_other_methods_unsupported():
     import torch
-    G = pf.Grid.from_grid(gridgen.config0())
+    G = pf.Grid.from_grid(gridgen.grid_500())
     pf.pf_ybus(G)
     vm = torch.ones(G.nb, dtype=torch.float64, device="cuda:0")
     j = torch.empty(G.nnz_j, dtype=torch.float64, device="cuda:0")
@@ -230,14 +230,14 @@ def test_csc_other_methods_unsupported():
 
 
 # ------------------------------------------------- precomputed branch constants
-@pytest.mark.parametrize("case", ["config0x3", "parallel_isolated", "hub_600_parallel"])
+@pytest.mark.parametrize("case", ["grid_500_x3", "parallel_isolated", "hub_600_parallel"])
 def test_precomputed_constants_same_values(case):
     """PF_EW_PRECOMPUTED reads the constants the branch kernel would derive:
     the two-phase results are bit-identical, copy-add stays within the gate."""
     import torch
-    if case == "config0x3":
-        g = gridgen.config0()
-        vm, va = gridgen.states(g.nb, 3, cfg=0)
+    if case == "grid_500_x3":
+        g = gridgen.grid_500()
+        vm, va = gridgen.states(g.nb, 3, case=0)
     else:
         g = (_grids.random_small(80, 150, 21, parallel=9, isolated=4) if case == "parallel_isolated"
              else star_grid(600, seed=2, parallel=40))
@@ -269,7 +269,7 @@ def test_precomputed_constants_same_values(case):
 
 def test_precomputed_flag_scope_and_graphs():
     import torch
-    G = pf.Grid.from_grid(gridgen.config0())
+    G = pf.Grid.from_grid(gridgen.grid_500())
     pf.pf_ybus(G)
     vm = to_dev(np.ones((2, G.nb)))
     va = to_dev(np.zeros((2, G.nb)))
@@ -280,12 +280,12 @@ def test_precomputed_flag_scope_and_graphs():
         assert e.value.code == pf.PF_EUNSUP
     # a recorded two-phase evaluation with precomputed constants (its scratch is
     # allocated before recording) replays to the eager result
-    vm = to_dev(gridgen.states(G.nb, 2, cfg=0)[0])
-    va = to_dev(gridgen.states(G.nb, 2, cfg=0)[1])
+    vm = to_dev(gridgen.states(G.nb, 2, case=0)[0])
+    va = to_dev(gridgen.states(G.nb, 2, case=0)[1])
     m = pf.PF_METHOD_ELEMENTWISE_TWO_PHASE | pf.PF_EW_PRECOMPUTED
     j_eager = torch.empty_like(j)
     pf.pf_jacobian_values(G, m, vm, va, None, None, j_eager)
-    G2 = pf.Grid.from_grid(gridgen.config0())  # fresh handle: no scratch yet
+    G2 = pf.Grid.from_grid(gridgen.grid_500())  # fresh handle: no scratch yet
     gr = pf.Graph(G2, [dict(op=pf.PF_OP_JACOBIAN, method=m, vm=vm, va=va, jval=j)])
     for _ in range(3):
         j.fill_(float("nan"))
@@ -295,12 +295,12 @@ def test_precomputed_flag_scope_and_graphs():
     gr.close()
 
 
-def test_variants_config1_full_size():
+def test_variants_grid_100k_full_size():
     """The 100k-bus benchmark grid: CSC output and both stored-phasor layouts
     against the fused kernels, bit for bit, and the fused kernels' oracle
     parity (covered in test_gpu_parity) carries over."""
-    g = gridgen.config1()
-    vm, va = gridgen.states(g.nb, 1, cfg=1)
+    g = gridgen.grid_100k()
+    vm, va = gridgen.states(g.nb, 1, case=1)
     _csc_case(g, vm, va, 256, 0)
     _csc_case(g, vm, va, 256, 0, method=pf.PF_METHOD_YBUS)
     for layout in LAYOUTS:

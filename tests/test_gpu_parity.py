@@ -38,9 +38,9 @@ def check_single(g, vm, va, tile=256, spb=0, use_scale=False, lam=True, order=pf
     return gres
 
 
-def test_config0_every_call():
-    g = gridgen.config0()
-    vm, va = gridgen.states(g.nb, 1, cfg=0)
+def test_grid_500_every_call():
+    g = gridgen.grid_500()
+    vm, va = gridgen.states(g.nb, 1, case=0)
     check_single(g, vm, va)
 
 
@@ -98,14 +98,14 @@ def test_shunt_only_buses():
 @pytest.mark.parametrize("order", [pf.PF_ORDER_TILE_MAJOR, pf.PF_ORDER_STATE_MAJOR])
 @pytest.mark.parametrize("spb", [0, 1, 3, 8, 64])
 def test_batched_states_ragged(spb, order):
-    g = gridgen.config0()
-    vm, va = gridgen.states(g.nb, 37, cfg=0)
+    g = gridgen.grid_500()
+    vm, va = gridgen.states(g.nb, 37, case=0)
     check_single(g, vm, va, tile=128, spb=spb, order=order)
 
 
 def test_zero_states_is_a_no_op():
     import torch
-    G = pf.Grid.from_grid(gridgen.config0())
+    G = pf.Grid.from_grid(gridgen.grid_500())
     e = torch.empty(0, G.nb, dtype=torch.float64, device="cuda:0")
     ej = torch.empty(0, G.nnz_j, dtype=torch.float64, device="cuda:0")
     pf.pf_injections_elementwise(G, e, e, e, e)
@@ -229,7 +229,7 @@ def test_graph_replays_match_eager_calls():
 
 def test_ybus_required_before_ybus_calls():
     import torch
-    G = pf.Grid.from_grid(gridgen.config0())
+    G = pf.Grid.from_grid(gridgen.grid_500())
     z = torch.zeros(1, G.nb, dtype=torch.float64, device="cuda:0")
     with pytest.raises(pf.PFError) as e:
         pf.pf_injections_ybus(G, z, z, z.clone(), z.clone())
@@ -242,7 +242,7 @@ def test_ybus_required_before_ybus_calls():
 
 def test_jval_alignment_checked():
     import torch
-    G = pf.Grid.from_grid(gridgen.config0())
+    G = pf.Grid.from_grid(gridgen.grid_500())
     z = torch.zeros(1, G.nb, dtype=torch.float64, device="cuda:0")
     jbig = torch.zeros(G.nnz_j + 1, dtype=torch.float64, device="cuda:0")
     rc = pf.lib().pf_jacobian_values(G.handle, 0, 1, z.data_ptr(), z.data_ptr(), None, None,
@@ -252,10 +252,10 @@ def test_jval_alignment_checked():
 
 # ------------------------------------------------------------------ full sizes
 
-def test_config1_full_size():
+def test_grid_100k_full_size():
     """100k buses, one state, in the benchmark's launch configuration."""
-    g = gridgen.config1()
-    vm, va = gridgen.states(g.nb, 1, cfg=1)
+    g = gridgen.grid_100k()
+    vm, va = gridgen.states(g.nb, 1, case=1)
     G = pf.Grid.from_grid(g)
     rng = np.random.default_rng(11)
     lp, lq = rng.normal(size=vm.shape), rng.normal(size=vm.shape)
@@ -265,12 +265,12 @@ def test_config1_full_size():
     print(dict(errs))
 
 
-def test_config2_batched_sampled_states():
+def test_grid_20k_batched_sampled_states():
     """20k buses x 512 states in one launch; six sampled states compared in full."""
     import torch
-    g = gridgen.config2()
+    g = gridgen.grid_20k()
     B = 512
-    vm, va = gridgen.states(g.nb, B, cfg=2, vlo=0.9, vhi=1.1, sigma=0.3)
+    vm, va = gridgen.states(g.nb, B, case=2, vlo=0.9, vhi=1.1, sigma=0.3)
     G = pf.Grid.from_grid(g)
     vm_d, va_d = to_dev(vm), to_dev(va)
     p = torch.empty(B, G.nb, dtype=torch.float64, device="cuda:0")
@@ -285,13 +285,13 @@ def test_config2_batched_sampled_states():
         assert rel_err(j[s].cpu().numpy(), ores["j_ew"]) <= TOL
 
 
-def test_config3_uneven_grids():
+def test_uneven_grids_64x4():
     """64 grids (1k-80k buses), 4 states each, one launch; every grid and state compared."""
-    grids = gridgen.config3()
+    grids = gridgen.grids_uneven_64()
     big, bo, ro = gridgen.concat(grids)
     G = pf.Grid.from_grid(big, bo, ro)
-    vm = np.concatenate([gridgen.states(gr.nb, 4, cfg=3, grid=k + 1)[0] for k, gr in enumerate(grids)], axis=1)
-    va = np.concatenate([gridgen.states(gr.nb, 4, cfg=3, grid=k + 1)[1] for k, gr in enumerate(grids)], axis=1)
+    vm = np.concatenate([gridgen.states(gr.nb, 4, case=3, grid=k + 1)[0] for k, gr in enumerate(grids)], axis=1)
+    va = np.concatenate([gridgen.states(gr.nb, 4, case=3, grid=k + 1)[1] for k, gr in enumerate(grids)], axis=1)
     gres = gpu_all(G, vm, va, with_ybus=False)
     y_off, j_off = G.offsets()
     for k, gr in enumerate(grids):
@@ -306,14 +306,14 @@ def test_config3_uneven_grids():
             assert rel_err(gres["j_ew"][s, j_off[k]:j_off[k + 1]], jv) <= TOL
 
 
-def test_config4_vjp_against_oracle_and_fd():
+def test_adjoint_100k_x32_against_oracle_and_fd():
     """100k buses x 32 states: VJP vs J^T lambda from the oracle Jacobian (sampled
     states) and vs central differences (h = 1e-7) on 1000 sampled coordinates."""
     import torch
-    g = gridgen.config1()
+    g = gridgen.grid_100k()
     B = 32
-    vm, va = gridgen.states(g.nb, B, cfg=4)
-    lp, lq = gridgen.adjoint_seeds(g.nb, B, cfg=4)
+    vm, va = gridgen.states(g.nb, B, case=4)
+    lp, lq = gridgen.adjoint_seeds(g.nb, B, case=4)
     G = pf.Grid.from_grid(g)
     vm_d, va_d, lp_d, lq_d = map(to_dev, (vm, va, lp, lq))
     gvm = torch.empty_like(vm_d)
@@ -329,7 +329,7 @@ def test_config4_vjp_against_oracle_and_fd():
         assert rel_err(gvm_h[s], ovm) <= TOL
         assert rel_err(gva_h[s], ova) <= TOL
     # central differences of the local objective sum_{i in N(k)} lP_i P_i + lQ_i Q_i
-    coords = gridgen.sample_coords(B, g.nb, 1000, cfg=4)
+    coords = gridgen.sample_coords(B, g.nb, 1000, case=4)
     nbrs = [[] for _ in range(g.nb)]
     for a, c in zip(g.fbus.tolist(), g.tbus.tolist()):
         nbrs[a].append(c)
@@ -382,8 +382,8 @@ def test_bound_calls_match_plain_calls():
     """pf.bind: arguments marshalled once, each call only calls the library;
     same results as the plain calls, also after the inputs change in place."""
     import torch
-    g = gridgen.config0()
-    vm, va = gridgen.states(g.nb, 3, cfg=0)
+    g = gridgen.grid_500()
+    vm, va = gridgen.states(g.nb, 3, case=0)
     G = pf.Grid.from_grid(g)
     pf.pf_ybus(G)
     vmd, vad = to_dev(vm), to_dev(va)

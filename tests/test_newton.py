@@ -18,10 +18,10 @@ def test_reduced_index():
 
 def test_reduced_map_matches_slicing():
     import scipy.sparse as sp
-    g = gridgen.config0()
+    g = gridgen.grid_500()
     yb = oracle.ybus(g)
     jr, jc = oracle.jac_pattern(yb)
-    vm, va = gridgen.states(g.nb, 1, cfg=0)
+    vm, va = gridgen.states(g.nb, 1, case=0)
     jv = oracle.jac_ew(g, vm[0], va[0], (jr, jc))
     bt = np.full(g.nb, newton.PQ)
     bt[::5] = newton.PV
@@ -34,8 +34,8 @@ def test_reduced_map_matches_slicing():
 
 
 def test_case_from_state():
-    g = gridgen.config0()
-    vm, va = gridgen.states(g.nb, 1, cfg=0)
+    g = gridgen.grid_500()
+    vm, va = gridgen.states(g.nb, 1, case=0)
     p, q = oracle.inject_ew(g, vm[0], va[0])
     bt, ps, qs, vm0, va0 = newton.case_from_state(g, vm[0], va[0], p, q)
     assert bt[0] == newton.SLACK and (bt == newton.SLACK).sum() == 1
@@ -71,8 +71,8 @@ def reference_newton(g, bt, ps, qs, vm0, va0, tol, max_iter):
 def test_newton_recovers_the_state(method):
     # a mild operating point (neighbouring angles differ by a few hundredths of
     # a radian), reached from a flat start
-    g = gridgen.config0()
-    vm, va = gridgen.states(g.nb, 1, cfg=0, vlo=0.98, vhi=1.02, sigma=0.02)
+    g = gridgen.grid_500()
+    vm, va = gridgen.states(g.nb, 1, case=0, vlo=0.98, vhi=1.02, sigma=0.02)
     p, q = oracle.inject_ew(g, vm[0], va[0])
     bt, ps, qs, vm0, va0 = newton.case_from_state(g, vm[0], va[0], p, q)
     G = pf.Grid.from_grid(g)

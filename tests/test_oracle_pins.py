@@ -151,8 +151,8 @@ def test_power_balance_identity(seed):
         assert abs(np.sum(s) - np.sum(terms)) <= 1e-13 * scale
 
 
-def test_power_balance_config0():
-    g = gridgen.config0()
+def test_power_balance_grid_500():
+    g = gridgen.grid_500()
     vm, va = gridgen.states(g.nb, 1, 0)
     p, q = oracle.inject_ew(g, vm[0], va[0])
     terms = balance_terms(g, vm[0], va[0])
@@ -217,8 +217,8 @@ def test_jacobians_complex_step_small(seed):
     assert rel_inf(P, p) <= 1e-14 and rel_inf(Q, q) <= 1e-14
 
 
-def test_jacobians_complex_step_config0():
-    g = gridgen.config0()
+def test_jacobians_complex_step_grid_500():
+    g = gridgen.grid_500()
     vm, va = gridgen.states(g.nb, 1, 0)
     vm, va = vm[0], va[0]
     yb, pat, _, _, j_ew = ew_all(g, vm, va)
@@ -269,8 +269,8 @@ def test_methods_agree_random(nb, extra, par, iso, seed):
     assert np.max(np.abs(j_ew - j_yb)) <= 1e-14 * sc * (nb + par + extra)
 
 
-def test_methods_agree_config0():
-    g = gridgen.config0()
+def test_methods_agree_grid_500():
+    g = gridgen.grid_500()
     vm, va = gridgen.states(g.nb, 1, 0)
     yb, pat, p, q, j_ew = ew_all(g, vm[0], va[0])
     p2, q2 = oracle.inject_ybus(yb, vm[0], va[0])
@@ -340,7 +340,7 @@ def test_alg2_matches_closed_form():
 
 
 def test_structure_counts():
-    g = gridgen.config0()
+    g = gridgen.grid_500()
     yb = oracle.ybus(g)
     pairs = {(min(a, b), max(a, b)) for a, b in zip(g.fbus.tolist(), g.tbus.tolist())}
     assert yb.nnz == g.nb + 2 * len(pairs) == 1900
