@@ -631,6 +631,20 @@ def main():
                                      "automatic_schedule": auto_sched,
                                      "automatic_schedule_us": ev_auto / max(10, K // 100) * 1e6}
         log(f"batched: {ev / steps * 1e6:.1f} us/launch")
+        # the same launch recorded by the library's own graph API (pf_graph_create / pf_graph_launch)
+        pgr = pf.Graph(G2, [dict(op=pf.PF_OP_JACOBIAN, method=pf.PF_METHOD_ELEMENTWISE, vm=vm2d, va=va2d, out_a=p2,
+                                 out_b=q2, jval=j2)])
+        for _ in range(3):
+            pgr.launch(stream=side)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(side)
+        for _ in range(steps):  # one host call per launch; the device time dominates
+            pgr.launch(stream=side)
+        e1.record(side)
+        torch.cuda.synchronize()
+        extra["batched_20k_x512"]["pf_graph_launch_us"] = e0.elapsed_time(e1) * 1e3 / steps
+        pgr.close()
         # the Ybus method on the same states, tuned the same way (same grid, separate handle)
         G2y = pf.Grid.from_grid(g2)
         pf.pf_ybus(G2y)
