@@ -914,31 +914,50 @@ __global__ void __launch_bounds__(NT)
         return;
     }
 
-    // ---- packed tile (lane tables as in k_ew)
+    // ---- packed tile (lane tables as in k_ew); row threads hand their bus's
+    // values to the row's lanes through LDS
+    __shared__ double s_own[ONE ? 1 : 2][4][NT];
     const bool rowt = k < c.nrows;
     const int ir = c.r0 + (rowt ? k : 0);
-    const int li = c.r0 + rowl;
     struct In {
-        VjpIn x;
-        double vr, lpr, lqr;
+        double vj, tj, lpj, lqj, vr, tr, lpr, lqr;
     };
     auto load = [&](int s, In &in) {
         const size_t so = (size_t)s * nb;
-        in.x = fetch(so, li, j);
+        in.vj = vm[so + j];
+        in.tj = va[so + j];
+        in.lpj = lp[so + j];
+        in.lqj = lq[so + j];
         in.vr = vm[so + ir];
+        in.tr = va[so + ir];
         in.lpr = lp[so + ir];
         in.lqr = lq[so + ir];
     };
-    In first;  // first state's gathers before the row loads, as in k_ew
+    In first;
     load(sb, first);
     const int irr = rowt ? ir : g.nb;
     const int2 rw = g.row_ew[irr];
     const double dA = g.dA[irr], dC = g.dC[irr];
     const int ra = lo16(rw.x), rz = hi16(rw.x);
-    // As in k_ew: every lane computes; stores depend on the lane's role.
     auto proc = [&](int s, int p, const In &in) {
+        if (rowt) {
+            s_own[p][0][k] = in.vr;
+            s_own[p][1][k] = in.tr;
+            s_own[p][2][k] = in.lpr;
+            s_own[p][3][k] = in.lqr;
+        }
+        lds_barrier();
+        VjpIn x;
+        x.vi = s_own[p][0][rowl];
+        x.ti = s_own[p][1][rowl];
+        x.lpi = s_own[p][2][rowl];
+        x.lqi = s_own[p][3][rowl];
+        x.vj = in.vj;
+        x.tj = in.tj;
+        x.lpj = in.lpj;
+        x.lqj = in.lqj;
         double ga, gv;
-        vjp_record(in.x, gb.x, gb.y, grb.x, grb.y, ga, gv);
+        vjp_record(x, gb.x, gb.y, grb.x, grb.y, ga, gv);
         s_val[p][0][k] = ga;
         s_val[p][1][k] = gv;
         lds_barrier();
