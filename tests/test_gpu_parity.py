@@ -408,7 +408,7 @@ def test_bound_calls_match_plain_calls():
     assert torch.equal(p1, p2) and torch.equal(q1, q2)
 
 
-@pytest.mark.parametrize("seed", range(12))
+@pytest.mark.parametrize("seed", range(40))
 def test_random_grids_and_schedules(seed):
     """Randomised sweep: grid size and shape (parallel branches, isolated
     buses, transformer share), tile size, states per workgroup, order and
