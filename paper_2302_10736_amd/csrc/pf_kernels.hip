@@ -3,27 +3,29 @@
 // eqs. (5)-(7); Section IV.C) and by the Ybus method (Section II.A,
 // eqs. (1)-(4); Section IV.B).
 //
-// Work decomposition (both methods)
-// ---------------------------------
+// Work decomposition (both fused methods)
+// ---------------------------------------
 // Records are sorted by (bus, neighbour, branch).  A tile is a run of whole
-// bus rows holding at most NT records (NT = workgroup size); one thread owns
-// one record, and thread r < rows also owns row r of the tile.  Per voltage
-// state a workgroup
-//   1. evaluates every record of the tile (one branch end or one bus shunt
-//      for the element-wise method, one Ybus nonzero for the Ybus method),
-//      writing the off-diagonal Jacobian entries into an LDS copy of the
-//      tile's Jacobian rows;
+// bus rows holding at most NT branch ends (element-wise; bus shunts live in
+// the per-bus constants and take no lane) or NT Ybus nonzeros (NT =
+// workgroup size); one thread owns one of them, and thread r < rows also
+// owns row r of the tile.  Per voltage state a workgroup
+//   1. evaluates every branch end (or nonzero) of the tile, writing the
+//      off-diagonal Jacobian entries into an LDS copy of the tile's
+//      Jacobian rows;
 //   2. reduces each row sequentially, in record order, by its row thread,
 //      which writes P_i, Q_i and the four diagonal Jacobian entries;
-//   3. writes the tile's Jacobian rows with contiguous 16-byte stores: a
-//      tile's rows are two contiguous ranges of the CSR value array (the P
-//      rows and the Q rows).
+//   3. writes the tile's Jacobian rows with contiguous 16-byte streaming
+//      stores: a tile's rows are two contiguous ranges of the CSR value
+//      array (the P rows and the Q rows).
 // No atomics; every sum has a fixed order set by the pattern, so results do
 // not depend on the tile size or on the states per workgroup.  LDS buffers
 // alternate between consecutive states (two barriers per state), and the
 // gathers of the next state are issued before the current one is reduced.
 // A row with more than NT records is a tile of its own, walked in chunks by
-// one thread's sequential sums in the same order.
+// one thread's sequential sums in the same order.  The baselines further
+// down (the two-phase and copy-add methods, branch flows) use one thread
+// per branch instead.
 //
 // Element-wise records
 // --------------------
