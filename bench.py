@@ -46,6 +46,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+WARM_S = 0.05  # untimed replays before every timed region, seconds
 # sources that decide the headline kernel's memory traffic (kernels and lane-table layout)
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2302_10736_amd", "csrc", f) for f in ("pf_kernels.hip", "pf_api.cpp")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_ew_100k_1state_traffic.json")
@@ -141,9 +142,13 @@ def size_sweep(torch, gridgen, pf, log):
         with torch.cuda.graph(gr, stream=side):
             for _ in range(n):
                 fn(side)
-        with torch.cuda.stream(side):
-            gr.replay()
-        torch.cuda.synchronize()
+        tw = time.perf_counter()
+        while True:  # untimed replays: the device has idled during the grid build
+            with torch.cuda.stream(side):
+                gr.replay()
+            torch.cuda.synchronize()
+            if time.perf_counter() - tw >= WARM_S:
+                break
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         with torch.cuda.stream(side):
             e0.record(side)
@@ -280,10 +285,17 @@ def main():
         full, rest = divmod(steps, period)
         g_full = record(period) if full else None
         g_rest = record(rest) if rest else None
-        with torch.cuda.stream(side):
-            for _ in range(2):
-                (g_full or g_rest).replay()
-        torch.cuda.synchronize()
+        # Untimed replays for at least WARM_S seconds: after host work (grid
+        # builds, schedule changes) the device has idled, and the first
+        # milliseconds of work after that run measurably slower.
+        tw = time.perf_counter()
+        while True:
+            with torch.cuda.stream(side):
+                for _ in range(2):
+                    (g_full or g_rest).replay()
+            torch.cuda.synchronize()
+            if time.perf_counter() - tw >= WARM_S:
+                break
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         t0 = time.perf_counter()

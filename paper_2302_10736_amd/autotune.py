@@ -19,6 +19,7 @@ import hashlib
 import json
 import os
 import tempfile
+import time
 from typing import Callable, Iterable, Optional, Sequence, Tuple
 
 from . import pf
@@ -112,10 +113,14 @@ def _device_name() -> str:
     return f"{p.name}|{getattr(p, 'gcnArchName', '')}"
 
 
-def device_timer(grid: "pf.Grid", op: str, nstate: int, reps: int = 5, seed: int = 0) -> Callable[[Schedule], float]:
+def device_timer(grid: "pf.Grid", op: str, nstate: int, reps: int = 5, seed: int = 0,
+                 warm_s: float = 0.01, samples: int = 3) -> Callable[[Schedule], float]:
     """Seconds per call of ``op`` on synthetic states under a given schedule,
     measured with HIP events around a replayed graph of ``reps`` calls (so
-    the host cost of a call does not hide differences)."""
+    the host cost of a call does not hide differences): the median of
+    ``samples`` timed replays, after untimed replays for ``warm_s`` seconds
+    (a tile-size change rebuilds the tables on the host, and the device runs
+    slower for the first milliseconds after idling)."""
     import torch
     if op not in OPS:
         raise ValueError(f"unknown op {op!r}")
@@ -156,15 +161,24 @@ def device_timer(grid: "pf.Grid", op: str, nstate: int, reps: int = 5, seed: int
             for _ in range(reps):
                 call(side)
         torch.cuda.synchronize()
+        tw = time.perf_counter()
+        while True:
+            with torch.cuda.stream(side):
+                gr.replay()
+            torch.cuda.synchronize()
+            if time.perf_counter() - tw >= warm_s:
+                break
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
-        with torch.cuda.stream(side):
-            gr.replay()
-            e0.record(side)
-            gr.replay()
-            e1.record(side)
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / 1e3 / reps
+        ts = []
+        for _ in range(max(1, samples)):
+            with torch.cuda.stream(side):
+                e0.record(side)
+                gr.replay()
+                e1.record(side)
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1) / 1e3 / reps)
+        return sorted(ts)[len(ts) // 2]
 
     return measure
 
