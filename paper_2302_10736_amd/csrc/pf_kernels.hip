@@ -173,22 +173,33 @@ __device__ __forceinline__ void pipelined_states(int sb, int se, In &ra, Load &&
 
 // Row sums of two LDS arrays over records [a, z), strictly left to right.
 // Records are read four at a time so one LDS round trip serves four terms;
-// reads past the row end use a clamped index and contribute +0.0, which
-// leaves every partial sum unchanged.
+// the last zero to three records of the row are added one by one.
 __device__ __forceinline__ void row_sum2(const double *x, const double *y, int a, int z, double &sx, double &sy) {
     double u = 0.0, v = 0.0;
-    for (int q = a; q < z; q += 4) {
-        const int q1 = min(q + 1, z - 1), q2 = min(q + 2, z - 1), q3 = min(q + 3, z - 1);
-        const double x0 = x[q], x1 = x[q1], x2 = x[q2], x3 = x[q3];
-        const double y0 = y[q], y1 = y[q1], y2 = y[q2], y3 = y[q3];
+    int q = a;
+    for (; q + 3 < z; q += 4) {
+        const double x0 = x[q], x1 = x[q + 1], x2 = x[q + 2], x3 = x[q + 3];
+        const double y0 = y[q], y1 = y[q + 1], y2 = y[q + 2], y3 = y[q + 3];
         u += x0;
         v += y0;
-        u += q + 1 < z ? x1 : 0.0;
-        v += q + 1 < z ? y1 : 0.0;
-        u += q + 2 < z ? x2 : 0.0;
-        v += q + 2 < z ? y2 : 0.0;
-        u += q + 3 < z ? x3 : 0.0;
-        v += q + 3 < z ? y3 : 0.0;
+        u += x1;
+        v += y1;
+        u += x2;
+        v += y2;
+        u += x3;
+        v += y3;
+    }
+    if (q < z) {
+        u += x[q];
+        v += y[q];
+    }
+    if (q + 1 < z) {
+        u += x[q + 1];
+        v += y[q + 1];
+    }
+    if (q + 2 < z) {
+        u += x[q + 2];
+        v += y[q + 2];
     }
     sx = u;
     sy = v;
