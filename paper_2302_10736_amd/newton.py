@@ -62,8 +62,9 @@ def solve(grid: "pf.Grid", bus_type, p_spec, q_spec, vm0, va0, method: int = pf.
     """Solve S(v, theta) = p_spec + j q_spec on the PV and PQ rows.
 
     vm0, va0 hold the fixed values (slack magnitude and angle, PV magnitudes)
-    and the starting point of the unknowns.  The handle must have had
-    pf_ybus called if method is PF_METHOD_YBUS."""
+    and the starting point of the unknowns.  ``method`` is any Jacobian
+    method of ``pf_jacobian_values``; the handle must have had pf_ybus
+    called if it is PF_METHOD_YBUS."""
     import scipy.sparse as sp
     import scipy.sparse.linalg as spla
     import torch
@@ -72,8 +73,6 @@ def solve(grid: "pf.Grid", bus_type, p_spec, q_spec, vm0, va0, method: int = pf.
     bus_type = np.asarray(bus_type)
     if bus_type.shape != (nb,):
         raise ValueError("bus_type must have one entry per bus")
-    if method == pf.PF_METHOD_ELEMENTWISE_TWO_PHASE:
-        method = pf.PF_METHOD_ELEMENTWISE
     dev = torch.device("cuda", torch.cuda.current_device())
     yr, yc, jr, jc = grid.pattern()
     if grid.ngrids != 1:

@@ -67,7 +67,7 @@ def reference_newton(g, bt, ps, qs, vm0, va0, tol, max_iter):
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("method", [pf.PF_METHOD_ELEMENTWISE, pf.PF_METHOD_YBUS])
+@pytest.mark.parametrize("method", [pf.PF_METHOD_ELEMENTWISE, pf.PF_METHOD_YBUS, pf.PF_METHOD_ELEMENTWISE_TWO_PHASE])
 def test_newton_recovers_the_state(method):
     # a mild operating point (neighbouring angles differ by a few hundredths of
     # a radian), reached from a flat start
