@@ -210,6 +210,9 @@ def main():
     ap.add_argument("--only", default="", help="comma list of side measurements to run")
     ap.add_argument("--probe", action="store_true",
                     help="counter-run workload: headline launches, then one copy of known size; no timing")
+    ap.add_argument("--probe-batched", action="store_true",
+                    help="counter-run workload: 3 batched S+J launches (20k buses x 512 states), 3 injection and "
+                         "3 adjoint launches (100k buses x 32 states), then one copy of known size; no timing")
     ap.add_argument("--traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the headline kernel's HBM traffic from two counter CSVs and exit")
     args = ap.parse_args()
@@ -237,6 +240,36 @@ def main():
     log = lambda *a: print(*a, file=sys.stderr, flush=True)
     if args.sweep:
         print(json.dumps(size_sweep(torch, gridgen, pf, log)), flush=True)
+        return
+
+    if args.probe_batched:
+        g2 = gridgen.grid_20k()
+        vm2, va2 = gridgen.states(g2.nb, 512, case=2, vlo=0.9, vhi=1.1, sigma=0.3)
+        G2 = pf.Grid.from_grid(g2)
+        v2, a2 = torch.as_tensor(vm2, device=dev), torch.as_tensor(va2, device=dev)
+        p2, q2 = torch.empty_like(v2), torch.empty_like(v2)
+        j2 = torch.empty(512, G2.nnz_j, dtype=torch.float64, device=dev)
+        for _ in range(3):
+            pf.pf_jacobian_values(G2, pf.PF_METHOD_ELEMENTWISE, v2, a2, p2, q2, j2)
+        torch.cuda.synchronize()
+        del j2, G2
+        g4 = gridgen.grid_100k()
+        vm4, va4 = gridgen.states(g4.nb, 32, case=4)
+        lp4, lq4 = gridgen.adjoint_seeds(g4.nb, 32, case=4)
+        G4 = pf.Grid.from_grid(g4)
+        v4, a4, l4p, l4q = (torch.as_tensor(x, device=dev) for x in (vm4, va4, lp4, lq4))
+        o = [torch.empty_like(v4) for _ in range(4)]
+        for _ in range(3):
+            pf.pf_injections_elementwise(G4, v4, a4, o[0], o[1])
+        for _ in range(3):
+            pf.pf_injections_vjp(G4, v4, a4, l4p, l4q, o[2], o[3])
+        a = torch.ones(COPY_PROBE_DOUBLES, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log("probe done: 3 launches each of 20k x 512 S+J, 100k x 32 injections and adjoint; one copy of "
+            f"{8 * COPY_PROBE_DOUBLES} bytes")
         return
 
     # ------------------------------------------------------------ workload
