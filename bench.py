@@ -562,6 +562,42 @@ def main():
             del d["fl"], d["fj"]
         log(f"branch flows + partials: {ev / K * 1e6:.2f} us/launch")
 
+    if want("relabelled"):
+        # the same grid with its buses renumbered at random (no locality in the
+        # remote-bus gathers), same protocol: cold replicas, graph replays; and
+        # the random numbering renumbered by reverse Cuthill-McKee on
+        # the host (a standard fix a caller can apply before building)
+        import scipy.sparse as sps
+        from scipy.sparse.csgraph import reverse_cuthill_mckee
+        gr_, perm_r = gridgen.relabel(g, case=1)
+        adj = sps.coo_matrix((np.ones(g.nl), (gr_.fbus, gr_.tbus)), shape=(g.nb, g.nb)).tocsr()
+        order = reverse_cuthill_mckee((adj + adj.T).tocsr(), symmetric_mode=True)
+        perm_c = np.argsort(order)  # new number of each relabelled bus
+        gc_ = gridgen.renumber(gr_, perm_c)
+        res_r = {}
+        for tag, gx, pfull in (("random", gr_, perm_r), ("rcm", gc_, perm_c[perm_r])):
+            inv = np.argsort(pfull)
+            reps_r = []
+            for r in range(R):
+                Gr = pf.Grid.from_grid(gx)
+                pf.pf_ybus(Gr)
+                reps_r.append((Gr, torch.as_tensor(vm[:, inv], device=dev).contiguous(),
+                               torch.as_tensor(va[:, inv], device=dev).contiguous(),
+                               torch.empty(1, g.nb, dtype=torch.float64, device=dev),
+                               torch.empty(1, g.nb, dtype=torch.float64, device=dev),
+                               torch.empty(1, Gr.nnz_j, dtype=torch.float64, device=dev)))
+            for mname, m in (("ew_sj", pf.PF_METHOD_ELEMENTWISE), ("ybus_sj", pf.PF_METHOD_YBUS)):
+                ev, wall = timed(lambda k, st, m=m: pf.pf_jacobian_values(reps_r[k % R][0], m, *reps_r[k % R][1:],
+                                                                          stream=st), K, W)
+                res_r[f"{tag}_{mname}_us"] = ev / K * 1e6
+            res_r[f"{tag}_ew_sj_over_generator_numbering"] = res_r[f"{tag}_ew_sj_us"] / (avg_launch * 1e6)
+            del reps_r
+            torch.cuda.empty_cache()
+        extra["relabelled_100k"] = res_r
+        log(f"random bus numbering: element-wise S+J {res_r['random_ew_sj_us']:.2f} us, Ybus S+J "
+            f"{res_r['random_ybus_sj_us']:.2f} us; after RCM renumbering {res_r['rcm_ew_sj_us']:.2f} / "
+            f"{res_r['rcm_ybus_sj_us']:.2f} us")
+
     if want("copy"):
         # a plain device copy moving the same number of bytes (half read, half written)
         n = abytes // 16

@@ -32,7 +32,8 @@ Streams: ``numpy.random.Generator(PCG64(SeedSequence([2302, 10736, case,
 grid, stream])))`` with case numbering the workload (0: 500 buses, 1: 100k
 buses, 2: 20k buses x 512 states, 3: 64 uneven grids, 4: the adjoint states
 on the 100k-bus grid, 5: the size sweep), stream 0 = topology and
-parameters, 1 = states, 2 = adjoint seeds, 3 = sampled coordinates.
+parameters, 1 = states, 2 = adjoint seeds, 3 = sampled coordinates,
+4 = the bus relabelling of :func:`relabel`.
 """
 from __future__ import annotations
 
@@ -162,6 +163,26 @@ def sample_coords(nstate: int, nb: int, count: int, case: int, grid: int = 0) ->
     """``count`` (state, var, bus) triples, var 0 = vm, 1 = va."""
     g = rng(case, grid, 3)
     return np.stack([g.integers(0, nstate, count), g.integers(0, 2, count), g.integers(0, nb, count)], axis=1)
+
+
+def relabel(g: Grid, case: int, grid: int = 0) -> tuple[Grid, np.ndarray]:
+    """The same grid with its buses renumbered by a seeded random permutation
+    (a stress case for locality: the generator's numbering keeps neighbours
+    close, real case files need not).  Returns (grid, perm) with new bus
+    number perm[old]; branch order and parameters are unchanged, bus shunts
+    move with their buses, and a state x of the original grid is
+    ``x[..., inv]`` here with ``inv = numpy.argsort(perm)``."""
+    perm = rng(case, grid, 4).permutation(g.nb)
+    return renumber(g, perm), perm
+
+
+def renumber(g: Grid, perm: np.ndarray) -> Grid:
+    """The grid with bus i renamed perm[i] (perm a permutation of 0..nb-1)."""
+    perm = np.asarray(perm)
+    inv = np.argsort(perm)
+    return Grid(g.nb, g.nl, perm[g.fbus].astype(np.int32), perm[g.tbus].astype(np.int32), g.r.copy(), g.x.copy(),
+                g.b.copy(), g.tap.copy(), g.shift.copy(), g.gs[inv].copy(), g.bs[inv].copy(),
+                meta={**g.meta, "renumbered": True})
 
 
 # ---------------------------------------------------------------------------

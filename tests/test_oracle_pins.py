@@ -278,6 +278,39 @@ def test_methods_agree_grid_500():
     assert rel_inf(j_ew, oracle.jac_ybus(yb, vm[0], va[0], pat)) <= 1e-14
 
 
+@pytest.mark.parametrize("method", ["ew", "ybus"])
+def test_relabelling_invariance(method):
+    """Renumbering the buses permutes S, J and the adjoint and changes nothing
+    else (a wrong bus index anywhere, say a shunt or a remote end, breaks it)."""
+    import scipy.sparse as sp
+    g = gridgen.grid_500()
+    vm, va = gridgen.states(g.nb, 1, 0)
+    lp, lq = gridgen.adjoint_seeds(g.nb, 1, 0)
+    h, perm = gridgen.relabel(g, case=0)
+    inv = np.argsort(perm)
+    nb = g.nb
+
+    def evaluate(gr, v, a):
+        yb = oracle.ybus(gr)
+        pat = oracle.jac_pattern(yb)
+        if method == "ew":
+            p, q = oracle.inject_ew(gr, v, a)
+            j = oracle.jac_ew(gr, v, a, pat)
+        else:
+            p, q = oracle.inject_ybus(yb, v, a)
+            j = oracle.jac_ybus(yb, v, a, pat)
+        return p, q, sp.csr_matrix((j, pat[1], pat[0]), shape=(2 * nb, 2 * nb)), pat, j
+
+    p0, q0, J0, pat0, j0 = evaluate(g, vm[0], va[0])
+    p1, q1, J1, pat1, j1 = evaluate(h, vm[0][inv], va[0][inv])
+    assert rel_inf(p1, p0[inv]) <= 1e-14 and rel_inf(q1, q0[inv]) <= 1e-14
+    var = np.concatenate([perm, nb + perm])  # new index of each old row / column
+    assert abs(J1[var][:, var] - J0).max() <= 1e-14 * abs(J0).max()
+    gv0, ga0 = oracle.vjp(nb, pat0, j0, lp[0], lq[0])
+    gv1, ga1 = oracle.vjp(nb, pat1, j1, lp[0][inv], lq[0][inv])
+    assert rel_inf(gv1, gv0[inv]) <= 1e-14 and rel_inf(ga1, ga0[inv]) <= 1e-14
+
+
 # ------------------------------------------------------------- dense brute force
 
 def test_dense_matrix_form():
