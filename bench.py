@@ -18,9 +18,10 @@ the same byte count (the practical bandwidth ceiling at this size), 512
 batched states on a 20k-bus grid, 64 uneven grids x 4 states, and the
 adjoint (32 states at 100k buses) against its forward pass, the Ybus
 injections with a separate phasor step in split and interleaved storage
-(Table I's comparison) against the fused kernel, and a
-Newton-Raphson power flow on a 5000-bus grid (device evaluation against
-host sparse solve per iteration).
+(Table I's comparison) against the fused kernel, the headline grid with its
+buses renumbered at random and then by reverse Cuthill-McKee (locality of
+the remote-bus gathers), and a Newton-Raphson power flow on a 5000-bus grid
+(device evaluation against host sparse solve per iteration).
 
 Counter runs (HBM traffic of the dominant kernel):
     rocprofv3 --pmc FETCH_SIZE --output-format csv -d D1 -o f -- python3 bench.py --probe
