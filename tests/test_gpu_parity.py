@@ -227,6 +227,61 @@ def test_graph_replays_match_eager_calls():
     assert e.value.code == pf.PF_ESTATE
 
 
+def test_graph_multigrid_and_baselines():
+    """A recorded sequence on a multi-grid handle with several states: fused
+    element-wise and Ybus Jacobians, the two-phase baseline (its scratch is
+    allocated before recording) and the atomic copy-add baseline.  Replays
+    equal the eager calls bit for bit (copy-add: to rounding, its additions
+    run in no fixed order) and every grid matches the oracle."""
+    import torch
+    grids = [_grids.random_small(n, int(n * 1.4), 90 + n, parallel=n % 3, isolated=1) for n in (60, 7, 400)]
+    grids.append(star_grid(300, seed=4))
+    big, bo, ro = gridgen.concat(grids)
+    G = pf.Grid.from_grid(big, bo, ro)
+    pf.pf_ybus(G)
+    ns = 2
+    rng = np.random.default_rng(8)
+    vm = to_dev(rng.uniform(0.9, 1.1, (ns, big.nb)))
+    va = to_dev(rng.normal(0, 0.2, (ns, big.nb)))
+    z = lambda *sh: torch.zeros(*sh, dtype=torch.float64, device="cuda:0")
+    methods = (pf.PF_METHOD_ELEMENTWISE, pf.PF_METHOD_YBUS, pf.PF_METHOD_ELEMENTWISE_TWO_PHASE,
+               pf.PF_METHOD_ELEMENTWISE_ATOMIC)
+    outs = [(z(ns, big.nb), z(ns, big.nb), z(ns, G.nnz_j)) for _ in methods]
+    ops = [dict(op=pf.PF_OP_JACOBIAN, method=m, vm=vm, va=va, out_a=o[0], out_b=o[1], jval=o[2])
+           for m, o in zip(methods, outs)]
+    gr = pf.Graph(G, ops)
+    y_off, j_off = G.offsets()
+    for rep in range(3):
+        for o in outs:
+            for t in o:
+                t.fill_(float("nan"))
+        gr.launch()
+        torch.cuda.synchronize()
+        for m, o in zip(methods, outs):
+            e = (z(ns, big.nb), z(ns, big.nb), z(ns, G.nnz_j))
+            pf.pf_jacobian_values(G, m, vm, va, *e)
+            torch.cuda.synchronize()
+            for a, b in zip(o, e):
+                a, b = a.cpu().numpy(), b.cpu().numpy()
+                if m == pf.PF_METHOD_ELEMENTWISE_ATOMIC:
+                    assert rel_err(a, b) <= TOL, (rep, m)
+                else:
+                    assert np.array_equal(a, b), (rep, m)
+        vm_h, va_h = vm.cpu().numpy(), va.cpu().numpy()
+        for k, g in enumerate(grids):
+            bsl = slice(bo[k], bo[k + 1])
+            jsl = slice(j_off[k], j_off[k + 1])
+            for s in range(ns):
+                ores = oracle_all(g, vm_h[s, bsl], va_h[s, bsl])
+                for m, o in zip(methods, outs):
+                    key = "yb" if m == pf.PF_METHOD_YBUS else "ew"
+                    assert rel_err(o[0][s, bsl].cpu().numpy(), ores["p_" + key]) <= TOL, (rep, k, s, m)
+                    assert rel_err(o[2][s, jsl].cpu().numpy(), ores["j_" + key]) <= TOL, (rep, k, s, m)
+        vm.mul_(1.01)
+        va.add_(0.03)
+    gr.close()
+
+
 def test_ybus_required_before_ybus_calls():
     import torch
     G = pf.Grid.from_grid(gridgen.grid_500())
