@@ -717,9 +717,10 @@ def main():
         # the same launch recorded by the library's own graph API (pf_graph_create / pf_graph_launch)
         pgr = pf.Graph(G2, [dict(op=pf.PF_OP_JACOBIAN, method=pf.PF_METHOD_ELEMENTWISE, vm=vm2d, va=va2d, out_a=p2,
                                  out_b=q2, jval=j2)])
-        for _ in range(3):
+        tw = time.perf_counter()
+        while time.perf_counter() - tw < WARM_S:  # untimed launches first, as in timed()
             pgr.launch(stream=side)
-        torch.cuda.synchronize()
+            torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(side)
         for _ in range(steps):  # one host call per launch; the device time dominates
