@@ -608,8 +608,15 @@ def main():
         extra["copy_same_bytes"] = {"bytes": 16 * n, "avg_launch_us": ev / K * 1e6,
                                     "GBs": 16 * n / (ev / K) / 1e9,
                                     "headline_over_copy_time": avg_launch / (ev / K)}
+        # the library's streaming copy (16-byte loads, streaming stores): the
+        # practical ceiling at this byte count
+        evs, _ = timed(lambda k, st: pf.pf_stream_copy(ca[k % R], cb[k % R], stream=st), K, W)
+        extra["stream_copy_same_bytes"] = {"bytes": 16 * n, "avg_launch_us": evs / K * 1e6,
+                                           "GBs": 16 * n / (evs / K) / 1e9,
+                                           "frac_hbm": 16 * n / (evs / K) / 1e9 / HBM_PEAK_GBS,
+                                           "headline_over_stream_copy_time": avg_launch / (evs / K)}
         del ca, cb
-        log(f"copy of the same bytes: {ev / K * 1e6:.2f} us")
+        log(f"copy of the same bytes: {ev / K * 1e6:.2f} us (torch), {evs / K * 1e6:.2f} us (streaming copy)")
 
     if want("warm"):
         def ew_warm(k, st):
@@ -748,6 +755,8 @@ def main():
         cb = torch.empty_like(ca)
         evc, _ = timed(lambda k, st: cb.copy_(ca), 20, 3, period=10)
         extra["batched_20k_x512"]["copy_same_bytes_us"] = evc / 20 * 1e6
+        evc, _ = timed(lambda k, st: pf.pf_stream_copy(ca, cb, stream=st), 20, 3, period=10)
+        extra["batched_20k_x512"]["stream_copy_same_bytes_us"] = evc / 20 * 1e6
         del ca, cb
         torch.cuda.empty_cache()
 
@@ -793,6 +802,8 @@ def main():
         cb = torch.empty_like(ca)
         evc, _ = timed(lambda k, st: cb.copy_(ca), 20, 3, period=10)
         extra["multigrid_64x4"]["copy_same_bytes_us"] = evc / 20 * 1e6
+        evc, _ = timed(lambda k, st: pf.pf_stream_copy(ca, cb, stream=st), 20, 3, period=10)
+        extra["multigrid_64x4"]["stream_copy_same_bytes_us"] = evc / 20 * 1e6
         del ca, cb
         torch.cuda.empty_cache()
 

@@ -267,6 +267,16 @@ int pf_jacobian_map(const pf_grid *g, int32_t layout, int32_t n, const int32_t *
 int pf_jacobian_scatter(const pf_grid *g, int32_t nstate, const double *jval, const int32_t *map, int64_t out_nnz,
                         double *out, void *stream);
 
+/* Measurement aid, not part of the method: a streaming device copy of n
+ * doubles from src to dst (DEVICE buffers, 16-byte aligned, not
+ * overlapping), 16-byte loads and streaming stores over a grid-stride loop.
+ * A copy moves its bytes with no dependent loads, so at a given byte count
+ * it is the practical bandwidth ceiling for a kernel that reads half and
+ * writes half of those bytes; the benchmark times it beside the evaluation
+ * kernels.  One launch on `stream`.  Errors: PF_EINVAL (n < 0, NULL,
+ * misaligned or overlapping buffers), PF_EHIP. */
+int pf_stream_copy(const double *src, double *dst, int64_t n, void *stream);
+
 /* Launch schedule.
  *   tile_items        workgroup size (64, 128, 256 or 512): branch ends per
  *                     element-wise work tile, Ybus nonzeros per Ybus tile

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpf.so")
-SOURCES = ["pf_api.cpp", "pf_kernels.hip"]
+SOURCES = ["pf_api.cpp", "pf_kernels.hip", "pf_probe.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [

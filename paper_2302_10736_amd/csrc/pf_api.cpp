@@ -1082,6 +1082,19 @@ int pf_jacobian_scatter(const pf_grid *g, int32_t nstate, const double *jval, co
     return PF_OK;
 }
 
+int pf_stream_copy(const double *src, double *dst, int64_t n, void *stream) {
+    g_err.clear();
+    if (n < 0) return fail(PF_EINVAL, "n must be >= 0");
+    if (n == 0) return PF_OK;
+    if (!src || !dst) return fail(PF_EINVAL, "NULL buffer");
+    if ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 15u)
+        return fail(PF_EINVAL, "buffers must be 16-byte aligned");
+    if (src < dst + n && dst < src + n) return fail(PF_EINVAL, "buffers overlap");
+    const hipError_t e = pf::launch_stream_copy(src, dst, n, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return PF_OK;
+}
+
 int pf_branch_flows(const pf_grid *g, int32_t nstate, const double *vm, const double *va, double *pf, double *qf,
                     double *pt, double *qt, double *jac, void *stream) {
     g_err.clear();

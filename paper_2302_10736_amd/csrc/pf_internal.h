@@ -170,6 +170,8 @@ hipError_t launch_copy_add(const DevTwoPhase &d, int32_t nstate, int64_t nnz_j, 
 // entry k with 0 <= map[k] < out_nnz (other entries are skipped).
 hipError_t launch_jscatter(int32_t nstate, int64_t nnz_j, const double *jval, const int32_t *map, int64_t out_nnz,
                            double *out, hipStream_t stream);
+// Streaming copy of n doubles (16-byte aligned buffers), the bandwidth probe.
+hipError_t launch_stream_copy(const double *src, double *dst, int64_t n, hipStream_t stream);
 // Precomputed branch constants (d.bc's layout) into bc.
 hipError_t launch_branch_consts(const DevTwoPhase &d, double *bc, hipStream_t stream);
 // States [0, nstate) one after another, two launches each.

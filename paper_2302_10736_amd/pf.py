@@ -30,7 +30,7 @@ EXPORTS = (
     "pf_build_pattern", "pf_grid_free", "pf_grid_sizes", "pf_pattern_sizes", "pf_grid_offsets",
     "pf_pattern_export", "pf_ybus", "pf_injections_elementwise", "pf_injections_ybus", "pf_jacobian_values",
     "pf_injections_vjp", "pf_branch_flows", "pf_phasors", "pf_ybus_from_phasors", "pf_jacobian_map", "pf_jacobian_scatter", "pf_set_schedule", "pf_get_schedule", "pf_graph_create", "pf_graph_launch",
-    "pf_graph_free", "pf_last_error", "pf_version",
+    "pf_graph_free", "pf_stream_copy", "pf_last_error", "pf_version",
 )
 PF_OP_INJECTIONS, PF_OP_JACOBIAN, PF_OP_VJP = 0, 1, 2
 
@@ -77,6 +77,7 @@ def lib() -> C.CDLL:
         L.pf_phasors.argtypes = [P, i32, i32, P, P, P, P]
         L.pf_jacobian_map.argtypes = [P, i32, i32, P, P, P]
         L.pf_jacobian_scatter.argtypes = [P, i32, P, P, i64, P, P]
+        L.pf_stream_copy.argtypes = [P, P, i64, P]
         L.pf_ybus_from_phasors.argtypes = [P, i32, i32, P, P, P, P, P]
         L.pf_set_schedule.argtypes = [P, i32, i32, i32]
         L.pf_graph_create.argtypes = [P, P, i32, C.POINTER(P)]
@@ -364,6 +365,17 @@ def pf_jacobian_scatter(grid: Grid, jval, jmap, out, stream=None):
     oshp = (out_nnz,) if jval.dim() == 1 else (ns, out_nnz)
     check(lib().pf_jacobian_scatter(grid.handle, ns, _dev(jval, jshp, "jval"), C.c_void_p(jmap.data_ptr()),
                                     int(out_nnz), _dev(out, oshp, "out"), _stream(stream)))
+
+
+def pf_stream_copy(src, dst, stream=None):
+    """dst[:] = src[:] by the library's streaming copy kernel (measurement
+    aid: the bandwidth ceiling at a byte count).  Contiguous float64 CUDA
+    tensors of equal size, 16-byte aligned, not overlapping."""
+    if src is None or dst is None or src.numel() != dst.numel():
+        raise ValueError("src and dst must be tensors of equal size")
+    n = src.numel()
+    check(lib().pf_stream_copy(_dev(src, tuple(src.shape), "src"), _dev(dst, tuple(dst.shape), "dst"), int(n),
+                               _stream(stream)))
 
 
 def pf_version() -> str:

@@ -240,3 +240,16 @@ def test_bind_refuses_unknown_calls_and_host_arrays():
     z = torch.zeros(6, dtype=torch.float64)
     with pytest.raises((TypeError, ValueError)):
         pf.bind(pf.pf_injections_elementwise, G, z, z, z, z)
+
+
+def test_stream_copy_argument_checks():
+    """pf_stream_copy rejects bad arguments on the host, before any launch."""
+    import ctypes as C
+    L = pf.lib()
+    a, b = C.c_void_p(1 << 20), C.c_void_p(2 << 20)
+    assert L.pf_stream_copy(None, None, 0, None) == pf.PF_OK  # nothing to copy
+    assert L.pf_stream_copy(a, b, -1, None) == pf.PF_EINVAL
+    assert L.pf_stream_copy(None, b, 4, None) == pf.PF_EINVAL
+    assert L.pf_stream_copy(C.c_void_p((1 << 20) + 8), b, 4, None) == pf.PF_EINVAL  # not 16-byte aligned
+    assert L.pf_stream_copy(a, C.c_void_p((1 << 20) + 16), 4, None) == pf.PF_EINVAL  # overlapping
+    assert b"overlap" in L.pf_last_error()

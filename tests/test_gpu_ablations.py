@@ -307,3 +307,15 @@ def test_variants_grid_100k_full_size():
         r = _phasor_case(g, vm, va, 256, 0, layout)
         assert np.array_equal(r["p1"], r["p0"]) and np.array_equal(r["q1"], r["q0"])
         assert np.array_equal(r["j1"], r["j0"]) and np.array_equal(r["p2"], r["ps"])
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 1001, (1 << 20) + 1, 5_000_000])
+def test_stream_copy(n):
+    """The bandwidth probe copies every element, odd lengths included."""
+    import torch
+    src = torch.randn(n + 2, dtype=torch.float64, device="cuda:0")[:n]  # the first n of a larger buffer
+    dst = torch.full((n + 2,), float("nan"), dtype=torch.float64, device="cuda:0")
+    pf.pf_stream_copy(src, dst[:n])
+    torch.cuda.synchronize()
+    assert torch.equal(dst[:n], src)
+    assert torch.isnan(dst[n:]).all()  # nothing written past the end
