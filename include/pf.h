@@ -103,8 +103,9 @@ typedef enum pf_method {
 } pf_method;
 
 enum {
-    PF_BUILD_HOST_ONLY = 1u /* build and validate the pattern on the host only: no device
-                               memory, no GPU needed; evaluation calls return PF_ESTATE */
+    PF_BUILD_HOST_ONLY = 1u /* build and validate the pattern and the launch schedule (tiles
+                               and lane tables) on the host only: no device memory, no GPU
+                               needed; evaluation calls return PF_ESTATE */
 };
 
 /* Build a handle: validate the grid, build the Ybus pattern, the Jacobian

@@ -253,7 +253,10 @@ HostLanes build_lanes(const pf_grid *g) {
 }
 
 int upload_tiles(pf_grid *g) {
-    if (g->host_only) return PF_OK;
+    if (g->host_only) {  // the lane tables are still built: the whole schedule is validated on the host
+        (void)build_lanes(g);
+        return PF_OK;
+    }
     hipError_t e;
     if (g->dtile) {
         e = hipFree(g->dtile);
@@ -502,6 +505,7 @@ int pf_build_pattern(int32_t nb, int32_t nl, const int32_t *fbus, const int32_t 
         build_tiles(g, g->tile_items);
 
         if (g->host_only) {
+            (void)upload_tiles(g);  // host-only: builds the lane tables, touches no device
             *out = g;
             return PF_OK;
         }
