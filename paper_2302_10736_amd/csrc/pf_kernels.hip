@@ -171,11 +171,11 @@ __device__ __forceinline__ void pipelined_states(int sb, int se, In &ra, Load &&
     }
 }
 
-// Row sums of two LDS arrays over records [a, z), strictly left to right.
-// Records are read four at a time so one LDS round trip serves four terms;
-// the last zero to three records of the row are added one by one.
-__device__ __forceinline__ void row_sum2(const double *x, const double *y, int a, int z, double &sx, double &sy) {
-    double u = 0.0, v = 0.0;
+// Row sums of two LDS arrays over records [a, z), strictly left to right,
+// continuing the running sums u and v.  Records are read four at a time so
+// one LDS round trip serves four terms; the last zero to three records of
+// the range are added one by one.
+__device__ __forceinline__ void row_sum2_acc(const double *x, const double *y, int a, int z, double &u, double &v) {
     int q = a;
     for (; q + 3 < z; q += 4) {
         const double x0 = x[q], x1 = x[q + 1], x2 = x[q + 2], x3 = x[q + 3];
@@ -201,6 +201,12 @@ __device__ __forceinline__ void row_sum2(const double *x, const double *y, int a
         u += x[q + 2];
         v += y[q + 2];
     }
+}
+
+// The same sums started from zero.
+__device__ __forceinline__ void row_sum2(const double *x, const double *y, int a, int z, double &sx, double &sy) {
+    double u = 0.0, v = 0.0;
+    row_sum2_acc(x, y, a, z, u, v);
     sx = u;
     sy = v;
 }
@@ -288,6 +294,8 @@ __device__ __forceinline__ void ew_eval(const DevGrid &g, int nstate, int spb, i
     constexpr int NS = kEwSlots(NT);              // Ybus slots per tile
     __shared__ int s_ls[NT];   // long rows: local slot of each record of a chunk
     __shared__ int s_dslot[1];  // long rows: local diagonal slot
+    __shared__ int s_cls[2];    // long rows: slot carried into the next chunk (-1: none), by chunk parity
+    __shared__ double s_carry[8];  // long rows: its partial sums, written [4, 8), read [0, 4)
     __shared__ double s_ab[NBUF][2][NT];
     __shared__ __align__(16) double s_J[NBUF][WITH_J ? kJStage<NS> : 2];
     __shared__ double s_rem[NBUF][4][NR];
@@ -310,7 +318,14 @@ __device__ __forceinline__ void ew_eval(const DevGrid &g, int nstate, int spb, i
     const size_t nb = (size_t)g.nb;
 
     if (c.ne > NT) {
-        // ---- one row with more than NT branch ends, walked in chunks of NT records
+        // ---- one row with more than NT branch ends, walked in chunks of NT
+        // records.  Each thread evaluates one record of the chunk; the first
+        // record of each Ybus slot in the chunk sums its slot's records in
+        // order and writes the slot's four J values (a slot that the chunk end
+        // cuts hands its partial sums to the next chunk through LDS, so every
+        // slot sum runs in record order); thread 0 carries the row sums, in
+        // record order.  The diagonal slot holds only the bus-shunt record;
+        // thread 0 writes it last, from the row sums.
         const int i = c.r0;
         const int d = c.ns;  // slots in the row
         const double dA = g.dA[i], dC = g.dC[i];
@@ -320,10 +335,13 @@ __device__ __forceinline__ void ew_eval(const DevGrid &g, int nstate, int spb, i
             double *Js = WITH_J ? J + (size_t)s * (size_t)g.nnz_j : nullptr;
             const double vi = vms[i], ti = vas[i];
             double as = 0.0, bs = 0.0;
-            double racc[4] = {0.0, 0.0, 0.0, 0.0};
-            int cur = -1;
-            for (int base = 0; base < c.n; base += NT) {
-                if (base + k < c.n) {
+            if (WITH_J && k == 0) s_cls[1] = -1;  // nothing carried into the first chunk
+            for (int base = 0, chunk = 0; base < c.n; base += NT, ++chunk) {
+                const int m = min(NT, c.n - base);
+                int ls = -1;
+                bool shunt = false;
+                if (WITH_J && k == 0) s_cls[chunk & 1] = -1;  // read last in the previous chunk
+                if (k < m) {
                     const int e = c.i0 + base + k;
                     const int je = g.nbr[e];
                     EwRec r;
@@ -334,43 +352,61 @@ __device__ __forceinline__ void ew_eval(const DevGrid &g, int nstate, int spb, i
                     s_ab[0][0][k] = r.a;
                     s_ab[0][1][k] = r.b;
                     if constexpr (WITH_J) {
-                        // the J stage holds the slot values of the chunk's records
                         s_J[0][0 * NT + k] = r.o[0];
                         s_J[0][1 * NT + k] = r.o[1];
                         s_J[0][2 * NT + k] = r.o[2];
                         s_J[0][3 * NT + k] = r.o[3];
-                        const int ls = (PAR ? g.slot[e] : e) - c.s0;
+                        ls = (PAR ? g.slot[e] : e) - c.s0;
                         s_ls[k] = ls;
-                        if (je == i) s_dslot[0] = ls;
+                        shunt = je == i;
+                        if (shunt) s_dslot[0] = ls;
                     }
                 }
                 __syncthreads();
-                if (k == 0) {
-                    const int m = min(NT, c.n - base);
-                    for (int q = 0; q < m; ++q) {
-                        as += s_ab[0][0][q];
-                        bs += s_ab[0][1][q];
-                        if constexpr (WITH_J) {
-                            const int ls = s_ls[q];
-                            if (ls != cur) {
-                                // a finished slot; the diagonal slot's zeros are overwritten below
-                                if (cur >= 0) {
-                                    st_out(Js + c.jp + cur, racc[0]);
-                                    st_out(Js + c.jp + d + cur, racc[1]);
-                                    st_out(Js + c.jq + cur, racc[2]);
-                                    st_out(Js + c.jq + d + cur, racc[3]);
-                                }
-                                cur = ls;
-                                racc[0] = racc[1] = racc[2] = racc[3] = 0.0;
-                            }
-                            racc[0] += s_J[0][0 * NT + q];
-                            racc[1] += s_J[0][1 * NT + q];
-                            racc[2] += s_J[0][2 * NT + q];
-                            racc[3] += s_J[0][3 * NT + q];
+                if (k == 0) row_sum2_acc(s_ab[0][0], s_ab[0][1], 0, m, as, bs);
+                if constexpr (WITH_J) {
+                    const int prev_cls = s_cls[(chunk + 1) & 1];  // slot carried in from the previous chunk
+                    const bool cont = k == 0 && ls == prev_cls;
+                    const bool head = k < m && (k == 0 || ls != s_ls[k - 1]);
+                    if (head && !shunt) {
+                        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+                        if (cont) {
+                            a0 = s_carry[0];
+                            a1 = s_carry[1];
+                            a2 = s_carry[2];
+                            a3 = s_carry[3];
+                        }
+                        int q = k;
+                        for (; q < m && s_ls[q] == ls; ++q) {
+                            a0 += s_J[0][0 * NT + q];
+                            a1 += s_J[0][1 * NT + q];
+                            a2 += s_J[0][2 * NT + q];
+                            a3 += s_J[0][3 * NT + q];
+                        }
+                        const int en = c.i0 + base + m;  // first record of the next chunk
+                        if (q == m && base + m < c.n && (PAR ? g.slot[en] : en) - c.s0 == ls) {
+                            s_carry[4] = a0;  // the slot goes on in the next chunk
+                            s_carry[5] = a1;
+                            s_carry[6] = a2;
+                            s_carry[7] = a3;
+                            s_cls[chunk & 1] = ls;
+                        } else {
+                            st_out(Js + c.jp + ls, a0);
+                            st_out(Js + c.jp + d + ls, a1);
+                            st_out(Js + c.jq + ls, a2);
+                            st_out(Js + c.jq + d + ls, a3);
                         }
                     }
                 }
                 __syncthreads();
+                if constexpr (WITH_J) {  // the carried partial sums move to the slots read by the next chunk
+                    if (k == 0 && s_cls[chunk & 1] >= 0) {
+                        s_carry[0] = s_carry[4];
+                        s_carry[1] = s_carry[5];
+                        s_carry[2] = s_carry[6];
+                        s_carry[3] = s_carry[7];
+                    }
+                }
             }
             if (k == 0) {
                 const EwRow o = ew_row(vi, dA, dC, as, bs);
@@ -379,12 +415,6 @@ __device__ __forceinline__ void ew_eval(const DevGrid &g, int nstate, int spb, i
                     st_out(Q + (size_t)s * nb + i, o.q);
                 }
                 if constexpr (WITH_J) {
-                    if (cur >= 0) {
-                        st_out(Js + c.jp + cur, racc[0]);
-                        st_out(Js + c.jp + d + cur, racc[1]);
-                        st_out(Js + c.jq + cur, racc[2]);
-                        st_out(Js + c.jq + d + cur, racc[3]);
-                    }
                     const int ld = s_dslot[0];
                     st_out(Js + c.jp + ld, o.j11);
                     st_out(Js + c.jp + d + ld, CSC ? o.j21 : o.j12);
@@ -634,7 +664,8 @@ __device__ __forceinline__ void yb_eval(const DevGrid &g, int nstate, int spb, i
     const size_t nb = (size_t)g.nb;
 
     if (c.ns > NT) {
-        // ---- one long row: pass 1 sums I_i in chunks (thread 0, in slot order), pass 2 writes J.
+        // ---- one long row: pass 1 sums I_i in chunks (thread 0, in slot order, four terms per LDS
+        // round trip), pass 2 writes J.
         const int i = c.r0;
         const int d = c.ns;
         const size_t n = (size_t)nstate * nb;
@@ -655,11 +686,7 @@ __device__ __forceinline__ void yb_eval(const DevGrid &g, int nstate, int spb, i
                 }
                 __syncthreads();
                 if (k == 0) {
-                    const int m = min(NT, d - base);
-                    for (int q = 0; q < m; ++q) {
-                        I.re += s_yv[0][0][q];
-                        I.im += s_yv[0][1][q];
-                    }
+                    row_sum2_acc(s_yv[0][0], s_yv[0][1], 0, min(NT, d - base), I.re, I.im);
                     s_vu[0][0][0] = I.re;
                     s_vu[0][1][0] = I.im;
                 }
@@ -909,13 +936,7 @@ __global__ void __launch_bounds__(NT)
                     s_val[0][1][k] = gv;
                 }
                 __syncthreads();
-                if (k == 0) {
-                    const int m = min(NT, c.n - base);
-                    for (int q = 0; q < m; ++q) {
-                        acc_a += s_val[0][0][q];
-                        acc_v += s_val[0][1][q];
-                    }
-                }
+                if (k == 0) row_sum2_acc(s_val[0][0], s_val[0][1], 0, min(NT, c.n - base), acc_a, acc_v);
                 __syncthreads();
             }
             if (k == 0) {
