@@ -292,6 +292,9 @@ int pf_stream_copy(const double *src, double *dst, int64_t n, void *stream);
  *                     of one state chunk are adjacent, so concurrent
  *                     workgroups write neighbouring parts of J) or
  *                     PF_ORDER_AUTO (= state-major)
+ * The initial schedule is tile_items 256 (with several grids per handle:
+ * the smallest of 64, 128, 256 that holds the mean branch ends per grid,
+ * since tiles never span grids), states_per_block 0, PF_ORDER_AUTO.
  * Changing the schedule never changes results.  Rebuilds the tile list on
  * the host and device; not for use while work on the handle is in flight.
  * Graphs recorded before the call must be recorded again. */

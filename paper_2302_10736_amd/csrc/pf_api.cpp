@@ -502,6 +502,13 @@ int pf_build_pattern(int32_t nb, int32_t nl, const int32_t *fbus, const int32_t 
             delete g;
             return fail(PF_EUNSUP, "Jacobian larger than 2^31-1 entries");
         }
+        // Tiles never span grids, so a grid with fewer branch ends than a tile
+        // leaves lanes idle: with many small grids, start from the smallest
+        // tile that holds an average grid's branch ends.
+        if (ngrids > 1) {
+            const int64_t mean_ends = (2 * (int64_t)nl + ngrids - 1) / ngrids;
+            g->tile_items = mean_ends <= 64 ? 64 : mean_ends <= 128 ? 128 : 256;
+        }
         build_tiles(g, g->tile_items);
 
         if (g->host_only) {

@@ -253,3 +253,16 @@ def test_stream_copy_argument_checks():
     assert L.pf_stream_copy(C.c_void_p((1 << 20) + 8), b, 4, None) == pf.PF_EINVAL  # not 16-byte aligned
     assert L.pf_stream_copy(a, C.c_void_p((1 << 20) + 16), 4, None) == pf.PF_EINVAL  # overlapping
     assert b"overlap" in L.pf_last_error()
+
+
+def test_default_tile_size_follows_grid_size():
+    """Tiles never span grids: a handle of many small grids starts with the
+    smallest tile that holds a mean grid's branch ends; one grid, or large
+    grids, start at 256."""
+    small = [gridgen.make_grid(14, 20, 0.15, case=6, grid=k) for k in range(50)]     # 40 ends per grid
+    mid = [gridgen.make_grid(40, 55, 0.15, case=6, grid=100 + k) for k in range(10)]  # 110 ends per grid
+    large = [gridgen.make_grid(500, 700, 0.15, case=6, grid=200 + k) for k in range(3)]
+    for grids, want in ((small, 64), (mid, 128), (large, 256)):
+        big, bo, ro = gridgen.concat(grids)
+        assert pf.Grid.from_grid(big, bo, ro, host_only=True).schedule()[0] == want
+    assert pf.Grid.from_grid(small[0], host_only=True).schedule()[0] == 256
