@@ -615,6 +615,9 @@ def main():
                                            "GBs": 16 * n / (evs / K) / 1e9,
                                            "frac_hbm": 16 * n / (evs / K) / 1e9 / HBM_PEAK_GBS,
                                            "headline_over_stream_copy_time": avg_launch / (evs / K)}
+        # the measured ceiling at this byte count, beside the 8 TB/s peak
+        out["roofline"]["stream_copy_GBs"] = 16 * n / (evs / K) / 1e9
+        out["roofline"]["frac_of_stream_copy"] = (evs / K) / avg_launch
         del ca, cb
         log(f"copy of the same bytes: {ev / K * 1e6:.2f} us (torch), {evs / K * 1e6:.2f} us (streaming copy)")
 
