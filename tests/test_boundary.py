@@ -266,3 +266,25 @@ def test_default_tile_size_follows_grid_size():
         big, bo, ro = gridgen.concat(grids)
         assert pf.Grid.from_grid(big, bo, ro, host_only=True).schedule()[0] == want
     assert pf.Grid.from_grid(small[0], host_only=True).schedule()[0] == 256
+
+
+# Full-size pattern identity (Algorithm 2's pattern, Section IV.B): the
+# exported Ybus and Jacobian patterns of the benchmark grids equal the
+# oracle's independently built ones bit for bit.
+@pytest.mark.parametrize("which", ["grid_100k", "grid_100k_relabelled", "grids_uneven_64"])
+def test_pattern_matches_oracle_full_size(which):
+    if which == "grids_uneven_64":
+        grids = gridgen.grids_uneven_64()
+        big, bo, ro = gridgen.concat(grids)
+        G = pf.Grid.from_grid(big, bo, ro, host_only=True)
+    else:
+        g = gridgen.grid_100k()
+        if which == "grid_100k_relabelled":
+            g, _ = gridgen.relabel(g, case=1)
+        grids = [g]
+        G = pf.Grid.from_grid(g, host_only=True)
+    got = G.pattern()
+    want = per_grid_oracle_pattern(grids)
+    for a, b in zip(got, want):
+        assert a.dtype == np.int32 and a.shape == b.shape and np.array_equal(a, b)
+    assert G.nnz_j == 4 * G.nnz_y == 4 * sum(oracle.ybus(g).nnz for g in grids)
