@@ -49,11 +49,16 @@
  *   caller, 8-byte aligned (16-byte for jval); outputs must not overlap
  *   inputs.  `stream` is a hipStream_t (NULL = default stream).
  * Evaluation calls enqueue work on `stream` and return: they allocate
- *   nothing (the one exception: the first PF_METHOD_ELEMENTWISE_TWO_PHASE
- *   call on a handle allocates that baseline's scratch), never synchronise
- *   and never read device data back, so they may be captured in a HIP graph.
- *   The handle holds only read-only data during evaluation (the two-phase
- *   scratch aside), so one handle may serve several streams at once.
+ *   nothing, never synchronise and never read device data back, so they may
+ *   be captured in a HIP graph.
+ * Streams: the fused evaluation calls only read the handle's device data,
+ *   so one handle may serve several streams at once, with two exceptions
+ *   the caller orders: pf_ybus rewrites the handle's Ybus values and Ybus
+ *   lane tables on its own stream, so Ybus evaluations (and replays of
+ *   graphs holding them) on other streams must be ordered after it (an
+ *   event and hipStreamWaitEvent, or a synchronisation); and every
+ *   PF_METHOD_ELEMENTWISE_TWO_PHASE call on a handle uses that handle's one
+ *   scratch buffer, so such calls on one handle must not overlap.
  * Results are deterministic: every sum runs in a fixed order set by the
  *   pattern (bus, then neighbour, then branch), independent of launch shape
  *   (the copy-add baseline, PF_METHOD_ELEMENTWISE_ATOMIC, excepted).
@@ -88,9 +93,9 @@ typedef enum pf_method {
     /* Element-wise in the paper's two steps (Section IV.C): every branch
      * evaluated once (both ends) into scratch, then a separate per-bus
      * reduction into P, Q and J.  A baseline for the fused method above;
-     * pf_jacobian_values only.  Its first call on a handle allocates the
-     * scratch (10 doubles per record, kept until pf_grid_free); states run
-     * one after another, two launches each. */
+     * pf_jacobian_values only.  Its scratch (10 doubles per record) belongs
+     * to the handle, allocated by pf_build_pattern; states run one after
+     * another, two launches each. */
     PF_METHOD_ELEMENTWISE_TWO_PHASE = 2,
     /* Element-wise with the paper's copy-add reduction (Section IV.C.2) done
      * by atomic adds: J set to zero and P, Q and the diagonal entries to the
@@ -112,7 +117,9 @@ enum {
  * pattern (eq. (2)), the bus-sorted branch-end records and the launch
  * schedule, copy everything to the current HIP device and compute the
  * per-record branch constants there.  Setup work; not part of the timed
- * evaluation (the paper pre-builds the pattern once, Section IV.B.2).
+ * evaluation (the paper pre-builds the pattern once, Section IV.B.3).  The
+ * handle's device memory also holds the two-phase baseline's scratch (80
+ * bytes per record, nb + 2 nl records).
  *   nb, nl        total buses (>= 1) and branches (>= 0) over all grids
  *   fbus, tbus    int32[nl], 0-based, grid-local bus indices; fbus != tbus
  *   r, x, b_charging, tap, shift   f64[nl]: p.u. series resistance and
@@ -177,8 +184,8 @@ int pf_injections_ybus(const pf_grid *g, int32_t nstate, const double *vm, const
  *   method  PF_METHOD_ELEMENTWISE: the 16 partial derivatives per branch
  *           (Section II.B), reduced into the J slots (Section IV.C.2);
  *           PF_METHOD_YBUS: eqs. (3)-(4) by the row-wise two-pass scheme
- *           (Section IV.B.2), written in place into J (PF_ESTATE before
- *           pf_ybus).
+ *           (Section IV.B.2), written in place into J (Section IV.B.3;
+ *           PF_ESTATE before pf_ybus).
  *           PF_METHOD_ELEMENTWISE or PF_METHOD_YBUS | PF_JAC_CSC: jval in
  *           column-major (CSC) order, the storage sparse direct solvers take
  *           (the paper keeps J in CSC, Section IV.A).  The pattern is
@@ -245,7 +252,7 @@ int pf_branch_flows(const pf_grid *g, int32_t nstate, const double *vm, const do
                     double *qf, double *pt, double *qt, double *jac, void *stream);
 
 /* Jacobian values in another sparsity pattern (Algorithm 2, Section
- * IV.B.2: indices into the target pattern found once by matching row and
+ * IV.B.3: indices into the target pattern found once by matching row and
  * column, then an in-place copy by those indices).  For targets whose
  * pattern holds J's entries and more, e.g. the extra couplings of series
  * devices such as a TCSC.
@@ -267,16 +274,6 @@ int pf_jacobian_map(const pf_grid *g, int32_t layout, int32_t n, const int32_t *
                     int32_t *map);
 int pf_jacobian_scatter(const pf_grid *g, int32_t nstate, const double *jval, const int32_t *map, int64_t out_nnz,
                         double *out, void *stream);
-
-/* Measurement aid, not part of the method: a streaming device copy of n
- * doubles from src to dst (DEVICE buffers, 16-byte aligned, not
- * overlapping), 16-byte loads and streaming stores over a grid-stride loop.
- * A copy moves its bytes with no dependent loads, so at a given byte count
- * it is the practical bandwidth ceiling for a kernel that reads half and
- * writes half of those bytes; the benchmark times it beside the evaluation
- * kernels.  One launch on `stream`.  Errors: PF_EINVAL (n < 0, NULL,
- * misaligned or overlapping buffers), PF_EHIP. */
-int pf_stream_copy(const double *src, double *dst, int64_t n, void *stream);
 
 /* Launch schedule.
  *   tile_items        workgroup size (64, 128, 256 or 512): branch ends per

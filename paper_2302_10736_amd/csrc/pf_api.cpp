@@ -3,21 +3,22 @@
 // schedule, device upload and the launch of the evaluation kernels.
 //
 // Setup follows the paper's advice to build the sparsity pattern once and
-// reuse it (Section IV.B.2, Algorithm 2; Section IV.C.2): nothing here runs
+// reuse it (Section IV.B.3, Algorithm 2; Section IV.C.2): nothing here runs
 // in the evaluation calls except argument checks and one kernel launch.
 
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <new>
-#include <mutex>
 #include <string>
 #include <vector>
 
 #include "../../include/pf.h"
+#include "../../include/pf_testing.h"
 #include "pf_internal.h"
 
 namespace {
@@ -31,6 +32,21 @@ int fail(int code, const std::string &msg) {
 
 int hip_fail(hipError_t e, const char *what) {
     return fail(PF_EHIP, std::string(what) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")");
+}
+
+// Every device allocation of the library goes through here, so that a test
+// can make the next n of them fail (pf_debug_fail_allocs).
+std::atomic<int> g_fail_allocs{0};
+
+hipError_t dev_alloc(void **p, size_t bytes) {
+    int n = g_fail_allocs.load();
+    while (n > 0) {
+        if (g_fail_allocs.compare_exchange_weak(n, n - 1)) {
+            *p = nullptr;
+            return hipErrorOutOfMemory;
+        }
+    }
+    return hipMalloc(p, bytes);
 }
 
 // Device arrays are carved from one allocation; each array starts on a
@@ -65,9 +81,7 @@ struct pf_grid {
     std::vector<pf::TileDesc> tiles, ytiles;  // element-wise and Ybus work tiles
     int32_t num_cus = 0;
     pf::DevLaneFill lanes{};  // gather sources and targets of the lane values
-    pf::DevTwoPhase tp{};     // two-phase element-wise tables (scratch allocated on first use)
-    void *dscr = nullptr;
-    std::mutex scr_mu;        // first use of the scratch may come from several threads
+    pf::DevTwoPhase tp{};     // two-phase element-wise tables and scratch (inside dmem)
 
     void *dmem = nullptr;   // grid data
     void *dtile = nullptr;  // schedule
@@ -155,7 +169,7 @@ void build_tiles(pf_grid *g, int NT) {
 // Q rows start at 2 NS + 2, and position 2 NS (Q: 4 NS + 2) is a pad that
 // absorbs the writes of lanes with nothing to write.  For row r of a tile
 // with local slot range [ya, yz) and local slot ls, dP/dtheta sits at
-// ya + ls and dP/dv at yz + ls (Section IV.B.2: J11 and J12 entries of one
+// ya + ls and dP/dv at yz + ls (eq. (2): J11 and J12 entries of one
 // row are adjacent, as are J21 and J22).
 struct HostLanes {
     std::vector<int32_t> lane_j, lane_rec, lane_pk, lane_run;
@@ -252,16 +266,14 @@ HostLanes build_lanes(const pf_grid *g) {
     return h;
 }
 
+// Upload the schedule (tiles and lane tables) of g->tiles / g->ytiles /
+// g->tile_items into a fresh device allocation.  The handle switches to it
+// only when every step succeeded; on failure the new allocation is released
+// and the handle keeps its previous device schedule untouched.
 int upload_tiles(pf_grid *g) {
     if (g->host_only) {  // the lane tables are still built: the whole schedule is validated on the host
         (void)build_lanes(g);
         return PF_OK;
-    }
-    hipError_t e;
-    if (g->dtile) {
-        e = hipFree(g->dtile);
-        g->dtile = nullptr;
-        if (e != hipSuccess) return hip_fail(e, "hipFree(schedule)");
     }
     const HostLanes h = build_lanes(g);
     const size_t nt = g->tiles.size(), nyt = g->ytiles.size();
@@ -276,13 +288,12 @@ int upload_tiles(pf_grid *g) {
     const size_t o_yy = ar.take<double2>(nly), o_ryb = ar.take<int2>(g->nb + 1);
     const size_t o_yds = ar.take<int32_t>(g->nb);
     const size_t o_yts = ar.take<int32_t>(g->nnz_y), o_ylt = ar.take<int32_t>(nly), o_yyt = ar.take<double2>(nly);
-    e = hipMalloc(&g->dtile, ar.off);
-    if (e != hipSuccess) {
-        g->dtile = nullptr;
+    void *mem = nullptr;
+    hipError_t e = dev_alloc(&mem, ar.off);
+    if (e != hipSuccess)
         return e == hipErrorOutOfMemory ? fail(PF_ENOMEM, "device allocation of the schedule failed")
                                         : hip_fail(e, "hipMalloc(schedule)");
-    }
-    char *base = static_cast<char *>(g->dtile);
+    char *base = static_cast<char *>(mem);
     hipError_t ee = hipSuccess;
     auto up = [&](size_t off, const void *src, size_t bytes) {
         if (ee == hipSuccess && bytes) ee = hipMemcpy(base + off, src, bytes, hipMemcpyHostToDevice);
@@ -301,8 +312,11 @@ int upload_tiles(pf_grid *g) {
     up(o_yds, h.ydslot.data(), (size_t)g->nb * 4);
     up(o_yts, h.yt_slot.data(), (size_t)g->nnz_y * 4);
     up(o_ylt, h.ylane_tslot.data(), nly * 4);
-    if (ee != hipSuccess) return hip_fail(ee, "hipMemcpy(schedule)");
-    pf::DevGrid &d = g->dev;
+    if (ee != hipSuccess) {
+        (void)hipFree(mem);
+        return hip_fail(ee, "hipMemcpy(schedule)");
+    }
+    pf::DevGrid d = g->dev;
     d.tiles = reinterpret_cast<const pf::TileDesc *>(base + o_t);
     d.ntiles = (int32_t)nt;
     d.ytiles = reinterpret_cast<const pf::TileDesc *>(base + o_yt);
@@ -319,7 +333,7 @@ int upload_tiles(pf_grid *g) {
     d.row_yb = reinterpret_cast<const int2 *>(base + o_ryb);
     d.yt_slot = reinterpret_cast<const int32_t *>(base + o_yts);
     d.ylane_yt = reinterpret_cast<const double2 *>(base + o_yyt);
-    pf::DevLaneFill &f = g->lanes;
+    pf::DevLaneFill f = g->lanes;
     f.nlanes = (int64_t)nle;
     f.nylanes = (int64_t)nly;
     f.lane_rec = reinterpret_cast<const int32_t *>(base + o_lrec);
@@ -343,7 +357,15 @@ int upload_tiles(pf_grid *g) {
     e = pf::launch_lane_fill(f, true, nullptr);
     if (e == hipSuccess && g->ybus_valid) e = pf::launch_lane_fill(f, false, nullptr);
     if (e == hipSuccess) e = hipDeviceSynchronize();
-    if (e != hipSuccess) return hip_fail(e, "lane table kernel");
+    if (e != hipSuccess) {
+        (void)hipFree(mem);
+        return hip_fail(e, "lane table kernel");
+    }
+    void *old = g->dtile;
+    g->dtile = mem;
+    g->dev = d;
+    g->lanes = f;
+    if (old) (void)hipFree(old);
     return PF_OK;
 }
 
@@ -540,7 +562,9 @@ int pf_build_pattern(int32_t nb, int32_t nl, const int32_t *fbus, const int32_t 
         // two-phase tables
         size_t o_bf = ar.take<int32_t>(nl), o_bt = ar.take<int32_t>(nl), o_brec = ar.take<int32_t>(2 * (size_t)nl),
                o_jpq = ar.take<int2>(nb), o_bc = ar.take<double>(6 * (size_t)nl);
-        e = hipMalloc(&g->dmem, ar.off);
+        // two-phase scratch: ten values per record, owned by the handle
+        size_t o_scr = ar.take<double>(10 * (size_t)ni);
+        e = dev_alloc(&g->dmem, ar.off);
         if (e != hipSuccess) {
             g->dmem = nullptr;
             delete g;
@@ -662,6 +686,7 @@ int pf_build_pattern(int32_t nb, int32_t nl, const int32_t *fbus, const int32_t 
         tp.yrow = d.yrow;
         tp.jpq = reinterpret_cast<const int2 *>(base + o_jpq);
         tp.bc = F64(o_bc);
+        tp.scr = F64(o_scr);
         e = pf::launch_setup_items(s, nullptr);
         if (e == hipSuccess) e = pf::launch_branch_consts(tp, F64(o_bc), nullptr);
         if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -687,7 +712,6 @@ void pf_grid_free(pf_grid *g) {
     if (!g) return;
     if (g->dmem) (void)hipFree(g->dmem);
     if (g->dtile) (void)hipFree(g->dtile);
-    if (g->dscr) (void)hipFree(g->dscr);
     delete g;
 }
 
@@ -814,14 +838,34 @@ int pf_set_schedule(pf_grid *g, int32_t tile_items, int32_t states_per_block, in
     if (states_per_block < 0) return fail(PF_EINVAL, "states_per_block must be >= 0");
     if (order != PF_ORDER_AUTO && order != PF_ORDER_TILE_MAJOR && order != PF_ORDER_STATE_MAJOR)
         return fail(PF_EINVAL, "unknown order");
+    if (tile_items != g->tile_items) {
+        // new tiles on the host and device; on failure the old ones stay
+        std::vector<pf::TileDesc> old_t, old_yt;
+        try {
+            old_t = g->tiles;
+            old_yt = g->ytiles;
+        } catch (const std::bad_alloc &) {
+            return fail(PF_ENOMEM, "host allocation failed");
+        }
+        const int32_t old_items = g->tile_items;
+        int st = PF_OK;
+        try {
+            g->tile_items = tile_items;
+            build_tiles(g, tile_items);
+            st = upload_tiles(g);
+        } catch (const std::bad_alloc &) {
+            st = fail(PF_ENOMEM, "host allocation failed");
+        }
+        if (st != PF_OK) {
+            g->tiles.swap(old_t);
+            g->ytiles.swap(old_yt);
+            g->tile_items = old_items;
+            return st;
+        }
+    }
     g->states_per_block = states_per_block;
     g->order = order;
     ++g->sched_gen;
-    if (tile_items != g->tile_items) {
-        g->tile_items = tile_items;
-        build_tiles(g, tile_items);
-        return upload_tiles(g);
-    }
     return PF_OK;
 }
 
@@ -882,20 +926,19 @@ int auto_states_per_block(const pf_grid *g, int kind, int32_t nstate) {
     return std::min(fill, 8);
 }
 
-// Scratch of the two-phase element-wise method: ten values per record,
-// allocated on the first call that needs it.
-int ensure_two_phase_scratch(const pf_grid *g) {
-    pf_grid *mg = const_cast<pf_grid *>(g);
-    std::lock_guard<std::mutex> lock(mg->scr_mu);
-    if (mg->dscr) return PF_OK;
-    const size_t bytes = 10 * (size_t)g->nitems * sizeof(double);
-    hipError_t e = hipMalloc(&mg->dscr, bytes);
-    if (e != hipSuccess) {
-        mg->dscr = nullptr;
-        return e == hipErrorOutOfMemory ? fail(PF_ENOMEM, "device allocation of the two-phase scratch failed")
-                                        : hip_fail(e, "hipMalloc(two-phase scratch)");
-    }
-    mg->tp.scr = static_cast<double *>(mg->dscr);
+// The two-phase baseline with the given scratch (ten doubles per record).
+int run_two_phase(const pf_grid *g, int32_t nstate, const double *vm, const double *va, double *p, double *q,
+                  double *jval, bool pre, double *scr, void *stream) {
+    if (nstate == 0) return PF_OK;
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (cur != g->device) return fail(PF_EINVAL, "current HIP device differs from the handle's device");
+    pf::DevTwoPhase d = g->tp;
+    d.ydslot = g->lanes.ydslot;
+    d.scr = scr;
+    e = pf::launch_two_phase(d, nstate, 4 * g->nnz_y, vm, va, p, q, jval, pre, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
     return PF_OK;
 }
 
@@ -1004,20 +1047,8 @@ int pf_jacobian_values(const pf_grid *g, int32_t method, int32_t nstate, const d
         if (e != hipSuccess) return hip_fail(e, "kernel launch");
         return PF_OK;
     }
-    if (method == PF_METHOD_ELEMENTWISE_TWO_PHASE) {
-        if (nstate == 0) return PF_OK;
-        int cur = -1;
-        hipError_t e = hipGetDevice(&cur);
-        if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
-        if (cur != g->device) return fail(PF_EINVAL, "current HIP device differs from the handle's device");
-        st = ensure_two_phase_scratch(g);
-        if (st) return st;
-        pf::DevTwoPhase d = g->tp;
-        d.ydslot = g->lanes.ydslot;
-        e = pf::launch_two_phase(d, nstate, 4 * g->nnz_y, vm, va, p, q, jval, pre, static_cast<hipStream_t>(stream));
-        if (e != hipSuccess) return hip_fail(e, "kernel launch");
-        return PF_OK;
-    }
+    if (method == PF_METHOD_ELEMENTWISE_TWO_PHASE)
+        return run_two_phase(g, nstate, vm, va, p, q, jval, pre, g->tp.scr, stream);
     pf::Launch L{};
     L.kind = method == PF_METHOD_ELEMENTWISE ? (csc ? pf::K_EW_SJ_CSC : pf::K_EW_SJ)
                                              : (csc ? pf::K_YB_SJ_CSC : pf::K_YB_SJ);
@@ -1090,6 +1121,13 @@ int pf_jacobian_scatter(const pf_grid *g, int32_t nstate, const double *jval, co
     if (cur != g->device) return fail(PF_EINVAL, "current HIP device differs from the handle's device");
     e = pf::launch_jscatter(nstate, 4 * g->nnz_y, jval, map, out_nnz, out, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return PF_OK;
+}
+
+int pf_debug_fail_allocs(int32_t n) {
+    g_err.clear();
+    if (n < 0) return fail(PF_EINVAL, "n must be >= 0");
+    g_fail_allocs.store(n);
     return PF_OK;
 }
 
@@ -1200,14 +1238,8 @@ int pf_graph_create(const pf_grid *g, const pf_op *ops, int32_t nops, pf_graph *
     if (cur != g->device) return fail(PF_EINVAL, "current HIP device differs from the handle's device");
     // Resolve every launch shape before recording, so that nothing but
     // kernel launches happens while the stream is captured.
-    for (int32_t k = 0; k < nops; ++k) {
+    for (int32_t k = 0; k < nops; ++k)
         if (ops[k].nstate > 0) auto_states_per_block(g, op_kind(ops[k]), ops[k].nstate);
-        if (ops[k].op == PF_OP_JACOBIAN &&
-            (ops[k].method & ~(PF_JAC_CSC | PF_EW_PRECOMPUTED)) == PF_METHOD_ELEMENTWISE_TWO_PHASE) {
-            const int st0 = ensure_two_phase_scratch(g);
-            if (st0) return st0;
-        }
-    }
     hipStream_t s = nullptr;
     e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
     if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");

@@ -616,9 +616,9 @@ __device__ __forceinline__ void yb_phasor(const YbIn &x, Cx &V, Cx &U) {
 // pass 1 forms Y_ij V_j and the row sums I_i, pass 2 turns each nonzero into
 //   dS_i/dtheta_j = j V_i (delta_ij conj(I_i) - conj(Y_ij V_j))
 //   dS_i/dv_j     = V_i conj(Y_ij U_j) + delta_ij conj(I_i) U_i
-// and writes the four real parts in place into J (Section IV.B.2).
+// and writes the four real parts in place into J (Section IV.B.3).
 // With PH = PH_FLY, U = e^{j theta} and V = v U are formed on the fly from
-// (vm, va); the stored-phasor variants (Section V.B.1, Table I) read V and U
+// (vm, va); the stored-phasor variants (Section V.A.1, Table I) read V and U
 // written beforehand by k_phasor, either as separate real / imaginary planes
 // (PH_SPLIT) or as interleaved {re, im} pairs (PH_INTERLEAVED).  k_phasor
 // computes the same products as the on-the-fly path, so all three give

@@ -30,7 +30,7 @@ EXPORTS = (
     "pf_build_pattern", "pf_grid_free", "pf_grid_sizes", "pf_pattern_sizes", "pf_grid_offsets",
     "pf_pattern_export", "pf_ybus", "pf_injections_elementwise", "pf_injections_ybus", "pf_jacobian_values",
     "pf_injections_vjp", "pf_branch_flows", "pf_phasors", "pf_ybus_from_phasors", "pf_jacobian_map", "pf_jacobian_scatter", "pf_set_schedule", "pf_get_schedule", "pf_graph_create", "pf_graph_launch",
-    "pf_graph_free", "pf_stream_copy", "pf_last_error", "pf_version",
+    "pf_graph_free", "pf_stream_copy", "pf_debug_fail_allocs", "pf_last_error", "pf_version",
 )
 PF_OP_INJECTIONS, PF_OP_JACOBIAN, PF_OP_VJP = 0, 1, 2
 
@@ -78,6 +78,7 @@ def lib() -> C.CDLL:
         L.pf_jacobian_map.argtypes = [P, i32, i32, P, P, P]
         L.pf_jacobian_scatter.argtypes = [P, i32, P, P, i64, P, P]
         L.pf_stream_copy.argtypes = [P, P, i64, P]
+        L.pf_debug_fail_allocs.argtypes = [i32]
         L.pf_ybus_from_phasors.argtypes = [P, i32, i32, P, P, P, P, P]
         L.pf_set_schedule.argtypes = [P, i32, i32, i32]
         L.pf_graph_create.argtypes = [P, P, i32, C.POINTER(P)]
@@ -376,6 +377,12 @@ def pf_stream_copy(src, dst, stream=None):
     n = src.numel()
     check(lib().pf_stream_copy(_dev(src, tuple(src.shape), "src"), _dev(dst, tuple(dst.shape), "dst"), int(n),
                                _stream(stream)))
+
+
+def pf_debug_fail_allocs(n: int):
+    """Make the library's next ``n`` device allocations fail as out of memory
+    (testing aid, include/pf_testing.h)."""
+    check(lib().pf_debug_fail_allocs(int(n)))
 
 
 def pf_version() -> str:

@@ -23,9 +23,14 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def header_symbols():
-    src = open(os.path.join(ROOT, "include", "pf.h")).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(pf_[a-z_]+)\s*\(", src)))
+    """Every function declared in include/*.h (pf.h and the testing header)."""
+    syms = set()
+    for name in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if name.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", name)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            syms |= set(re.findall(r"\b(pf_[a-z_]+)\s*\(", src))
+    return sorted(syms)
 
 
 def test_library_exports_every_declared_symbol():
@@ -42,7 +47,8 @@ def test_header_compiles_as_c():
     import subprocess, tempfile
     with tempfile.TemporaryDirectory() as d:
         c = os.path.join(d, "t.c")
-        open(c, "w").write('#include "pf.h"\nint main(void){ const char *(*f)(void) = pf_last_error; (void)f; return PF_OK; }\n')
+        open(c, "w").write('#include "pf.h"\n#include "pf_testing.h"\nint main(void){ const char *(*f)(void) = '
+                           'pf_last_error; int (*g)(int32_t) = pf_debug_fail_allocs; (void)f; (void)g; return PF_OK; }\n')
         subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"), "-c", c, "-o",
                         os.path.join(d, "t.o")], check=True)
 
@@ -288,3 +294,11 @@ def test_pattern_matches_oracle_full_size(which):
     for a, b in zip(got, want):
         assert a.dtype == np.int32 and a.shape == b.shape and np.array_equal(a, b)
     assert G.nnz_j == 4 * G.nnz_y == 4 * sum(oracle.ybus(g).nnz for g in grids)
+
+
+def test_debug_alloc_hook_arguments():
+    """The allocation-failure hook (include/pf_testing.h) takes n >= 0."""
+    with pytest.raises(pf.PFError) as e:
+        pf.pf_debug_fail_allocs(-1)
+    assert e.value.code == pf.PF_EINVAL
+    pf.pf_debug_fail_allocs(0)

@@ -228,9 +228,10 @@ def test_graph_replays_match_eager_calls():
 
 
 def test_graph_multigrid_and_baselines():
-    """A recorded sequence on a multi-grid handle with several states: fused
-    element-wise and Ybus Jacobians, the two-phase baseline (its scratch is
-    allocated before recording) and the atomic copy-add baseline.  Replays
+    """A recorded sequence on a freshly built multi-grid handle (no evaluation
+    call before recording) with several states: fused element-wise and Ybus
+    Jacobians, the two-phase baseline (its scratch belongs to the handle from
+    the build on) and the atomic copy-add baseline.  Replays
     equal the eager calls bit for bit (copy-add: to rounding, its additions
     run in no fixed order) and every grid matches the oracle."""
     import torch
