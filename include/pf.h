@@ -209,6 +209,24 @@ enum { PF_EW_PRECOMPUTED = 0x200 };
 int pf_jacobian_values(const pf_grid *g, int32_t method, int32_t nstate, const double *vm,
                        const double *va, double *p, double *q, double *jval, void *stream);
 
+/* For callers that cannot allocate device memory or use a handle's own
+ * buffers at call time (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): pf_jacobian_values with
+ * PF_METHOD_ELEMENTWISE_TWO_PHASE (optionally | PF_EW_PRECOMPUTED), same
+ * arguments, layouts and results bit for bit, whose scratch is the library's
+ * static device array instead of the handle's buffer.  The array is 32 MiB
+ * per device (ten doubles per record: grids of at most 419,430 records,
+ * nb + 2 nl over all grids of the handle; larger grids get PF_EUNSUP), is
+ * resolved once per device when a handle is built and stays allocated until
+ * the process ends.  The call allocates nothing.  Every call on a device
+ * shares that device's array and reads only what it wrote itself earlier in
+ * the same call (nothing needs to start at zero), so calls that overlap on
+ * one device (other streams, other threads, other handles) race and must be
+ * ordered by the caller.  Errors: as pf_jacobian_values, plus PF_EINVAL for
+ * another method and PF_EUNSUP for a grid beyond the limit. */
+int pf_jacobian_two_phase_static(const pf_grid *g, int32_t method, int32_t nstate, const double *vm,
+                                 const double *va, double *p, double *q, double *jval, void *stream);
+
 /* Adjoint of the injections: for seeds lam_p, lam_q (f64[nstate][nb]),
  *   g_va = J11^T lam_p + J21^T lam_q,   g_vm = J12^T lam_p + J22^T lam_q,
  * i.e. the gradient of sum_i (lam_p_i P_i + lam_q_i Q_i) with respect to

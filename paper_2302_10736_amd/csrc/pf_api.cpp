@@ -546,6 +546,13 @@ int pf_build_pattern(int32_t nb, int32_t nl, const int32_t *fbus, const int32_t 
             delete g;
             return hip_fail(e, "hipGetDevice");
         }
+        // Set-up of the library's static scratch on this device (the address
+        // is resolved once per device and cached; a failure is reported by
+        // the entry point that uses it, pf_jacobian_two_phase_static).
+        {
+            double *scr = nullptr;
+            (void)pf::static_scratch(g->device, &scr);
+        }
         Arena ar;
         size_t o_yrow = ar.take<int32_t>(nb + 1), o_irow = ar.take<int32_t>(nb + 1);
         size_t o_ycol = ar.take<int32_t>(g->nnz_y), o_nbr = ar.take<int32_t>(ni), o_slot = ar.take<int32_t>(ni);
@@ -1059,6 +1066,28 @@ int pf_jacobian_values(const pf_grid *g, int32_t method, int32_t nstate, const d
     L.q = q;
     L.jval = jval;
     return run(g, L, stream);
+}
+
+int pf_jacobian_two_phase_static(const pf_grid *g, int32_t method, int32_t nstate, const double *vm,
+                                 const double *va, double *p, double *q, double *jval, void *stream) {
+    g_err.clear();
+    int st = check_eval(g, nstate);
+    if (st) return st;
+    if ((method & ~PF_EW_PRECOMPUTED) != PF_METHOD_ELEMENTWISE_TWO_PHASE)
+        return fail(PF_EINVAL, "method must be PF_METHOD_ELEMENTWISE_TWO_PHASE, optionally | PF_EW_PRECOMPUTED");
+    const bool pre = (method & PF_EW_PRECOMPUTED) != 0;
+    if (g->nitems > pf::kStaticScratchRecords)
+        return fail(PF_EUNSUP, "the grid has " + std::to_string(g->nitems) + " records (nb + 2 nl); the static scratch "
+                               "holds at most " + std::to_string(pf::kStaticScratchRecords) +
+                               " (use pf_jacobian_values)");
+    if (nstate > 0 && (!vm || !va || !jval)) return fail(PF_EINVAL, "NULL state or Jacobian pointer");
+    if ((p == nullptr) != (q == nullptr)) return fail(PF_EINVAL, "p and q must both be given or both be NULL");
+    if (reinterpret_cast<uintptr_t>(jval) % 16) return fail(PF_EINVAL, "jval must be 16-byte aligned");
+    if (nstate == 0) return PF_OK;
+    double *scr = nullptr;
+    const hipError_t e = pf::static_scratch(g->device, &scr);
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(static scratch)");
+    return run_two_phase(g, nstate, vm, va, p, q, jval, pre, scr, stream);
 }
 
 static_assert(PF_PHASOR_SPLIT == pf::PH_SPLIT && PF_PHASOR_INTERLEAVED == pf::PH_INTERLEAVED,

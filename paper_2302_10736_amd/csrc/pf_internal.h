@@ -174,6 +174,16 @@ hipError_t launch_jscatter(int32_t nstate, int64_t nnz_j, const double *jval, co
 hipError_t launch_stream_copy(const double *src, double *dst, int64_t n, hipStream_t stream);
 // Precomputed branch constants (d.bc's layout) into bc.
 hipError_t launch_branch_consts(const DevTwoPhase &d, double *bc, hipStream_t stream);
+// The library's static scratch: a file-scope device array of
+// kStaticScratchBytes (one copy per device, held until the process ends),
+// used by the allocation-free two-phase entry point.  It holds ten doubles
+// per record for at most kStaticScratchRecords records.
+constexpr int64_t kStaticScratchBytes = int64_t(32) << 20;
+constexpr int64_t kStaticScratchRecords = kStaticScratchBytes / (10 * (int64_t)sizeof(double));
+// Device address of that array on `device`, which must be the current
+// device.  Resolved with hipGetSymbolAddress on the first call for a device
+// and cached; later calls make no HIP call.
+hipError_t static_scratch(int device, double **out);
 // States [0, nstate) one after another, two launches each.
 hipError_t launch_two_phase(const DevTwoPhase &d, int32_t nstate, int64_t nnz_j, const double *vm, const double *va,
                             double *p, double *q, double *jval, bool pre, hipStream_t stream);

@@ -55,6 +55,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <mutex>
 
 #include "pf_internal.h"
 #include "pf_math.h"
@@ -1576,6 +1577,29 @@ hipError_t launch_lane_fill(const DevLaneFill &f, bool ew, hipStream_t stream) {
     const int64_t blocks = (n + 255) / 256;
     hipLaunchKernelGGL(k_lane_fill, dim3((unsigned)blocks), dim3(256), 0, stream, f, ew);
     return hipGetLastError();
+}
+
+// Scratch of the allocation-free two-phase entry point (k_tp_branch writes
+// ten values per record into it, k_tp_reduce reads them back).  In host code
+// `scratch` names a host-side stand-in, not device memory: kernels only ever
+// receive the device address that static_scratch() resolves.
+static __device__ __align__(256) double scratch[kStaticScratchBytes / sizeof(double)];
+
+hipError_t static_scratch(int device, double **out) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static double *addr[kMaxDevices] = {};
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[device] = static_cast<double *>(p);
+    }
+    *out = addr[device];
+    return hipSuccess;
 }
 
 hipError_t launch_two_phase(const DevTwoPhase &d, int32_t nstate, int64_t nnz_j, const double *vm, const double *va,

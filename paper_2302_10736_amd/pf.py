@@ -29,7 +29,7 @@ PF_EW_PRECOMPUTED = 0x200  # OR into the two-phase / copy-add methods: precomput
 EXPORTS = (
     "pf_build_pattern", "pf_grid_free", "pf_grid_sizes", "pf_pattern_sizes", "pf_grid_offsets",
     "pf_pattern_export", "pf_ybus", "pf_injections_elementwise", "pf_injections_ybus", "pf_jacobian_values",
-    "pf_injections_vjp", "pf_branch_flows", "pf_phasors", "pf_ybus_from_phasors", "pf_jacobian_map", "pf_jacobian_scatter", "pf_set_schedule", "pf_get_schedule", "pf_graph_create", "pf_graph_launch",
+    "pf_injections_vjp", "pf_jacobian_two_phase_static", "pf_branch_flows", "pf_phasors", "pf_ybus_from_phasors", "pf_jacobian_map", "pf_jacobian_scatter", "pf_set_schedule", "pf_get_schedule", "pf_graph_create", "pf_graph_launch",
     "pf_graph_free", "pf_stream_copy", "pf_debug_fail_allocs", "pf_last_error", "pf_version",
 )
 PF_OP_INJECTIONS, PF_OP_JACOBIAN, PF_OP_VJP = 0, 1, 2
@@ -73,6 +73,7 @@ def lib() -> C.CDLL:
         L.pf_injections_ybus.argtypes = [P, i32, P, P, P, P, P]
         L.pf_jacobian_values.argtypes = [P, i32, i32, P, P, P, P, P, P]
         L.pf_injections_vjp.argtypes = [P, i32, P, P, P, P, P, P, P]
+        L.pf_jacobian_two_phase_static.argtypes = [P, i32, i32, P, P, P, P, P, P]
         L.pf_branch_flows.argtypes = [P, i32, P, P, P, P, P, P, P, P]
         L.pf_phasors.argtypes = [P, i32, i32, P, P, P, P]
         L.pf_jacobian_map.argtypes = [P, i32, i32, P, P, P]
@@ -264,6 +265,12 @@ def pf_injections_ybus(grid: Grid, vm, va, p, q, stream=None):
 
 def pf_jacobian_values(grid: Grid, method: int, vm, va, p, q, jval, stream=None):
     check(lib().pf_jacobian_values(*_m_jacobian_values(grid, method, vm, va, p, q, jval, stream)))
+
+
+def pf_jacobian_two_phase_static(grid: Grid, method: int, vm, va, p, q, jval, stream=None):
+    """The two-phase Jacobian with the library's static scratch (allocates
+    nothing; see include/pf.h for the size limit and the sharing rule)."""
+    check(lib().pf_jacobian_two_phase_static(*_m_jacobian_values(grid, method, vm, va, p, q, jval, stream)))
 
 
 def pf_injections_vjp(grid: Grid, vm, va, lam_p, lam_q, g_vm, g_va, stream=None):
