@@ -127,73 +127,128 @@ def algorithmic_bytes(nb, nl, nnz_y, nstate, with_j=True, method="ew", vjp=False
     return nstate * per_state + grid
 
 
-def size_sweep(torch, gridgen, pf, log):
-    """Device time of one evaluation (one state, warm, graph replays) by both
-    methods over grid sizes from 118 buses to five replicas of an 82k-bus
-    grid; per-bus times, the time-cost ratio (per-bus time over that of the
-    118-bus grid) and the Ybus / element-wise time ratio per size."""
-    dev = torch.device("cuda:0")
-    side = torch.cuda.Stream()
+def make_timer(torch, side):
+    """timed(fn, steps, warmup, period): time exactly `steps` launches
+    fn(k, stream), issued as replays of HIP graphs that record `period`
+    consecutive launches (plus one graph for the remainder), so the host cost
+    of a call does not bound the rate.  Returns (seconds by HIP events on the
+    launch stream around exactly those launches, wall seconds of the same
+    region including the host's graph launches and the final synchronise)."""
 
-    def gtime(fn, n=20, reps=10):
+    def timed(fn, steps, warmup, period):
+        period = max(1, min(period, steps))
         with torch.cuda.stream(side):
-            fn(side)
+            for k in range(max(warmup, period)):
+                fn(k, side)
         torch.cuda.synchronize()
-        gr = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(gr, stream=side):
-            for _ in range(n):
-                fn(side)
+
+        def record(n):
+            gr = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(gr, stream=side):
+                for k in range(n):
+                    fn(k, side)
+            return gr
+        full, rest = divmod(steps, period)
+        g_full = record(period) if full else None
+        g_rest = record(rest) if rest else None
+        # Untimed replays for at least WARM_S seconds: after host work (grid
+        # builds, schedule changes) the device has idled, and the first
+        # milliseconds of work after that run measurably slower.
         tw = time.perf_counter()
-        while True:  # untimed replays: the device has idled during the grid build
+        while True:
             with torch.cuda.stream(side):
-                gr.replay()
+                for _ in range(2):
+                    (g_full or g_rest).replay()
             torch.cuda.synchronize()
             if time.perf_counter() - tw >= WARM_S:
                 break
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
         with torch.cuda.stream(side):
             e0.record(side)
-            for _ in range(reps):
-                gr.replay()
+            for _ in range(full):
+                g_full.replay()
+            if g_rest is not None:
+                g_rest.replay()
             e1.record(side)
         torch.cuda.synchronize()
-        return e0.elapsed_time(e1) * 1e3 / (n * reps)  # us
+        wall = time.perf_counter() - t0
+        return e0.elapsed_time(e1) / 1e3, wall
 
-    cases = [(nb, None) for nb in (118, 500, 2000, 10_000, 30_000, 82_000)] + [(82_000, k) for k in (2, 3, 4, 5)]
+    return timed
+
+
+SWEEP_SIZES = (118, 10_000, 82_000, 164_000, 410_000)  # the default run's sweep
+SWEEP_SIZES_FULL = (118, 500, 2_000, 10_000, 30_000, 82_000, 164_000, 246_000, 328_000, 410_000)
+COLD_BYTES = 512 << 20  # replicas of at least twice the 256 MB Infinity Cache per timed size
+
+
+def size_sweep(torch, gridgen, pf, timed, log, sizes=SWEEP_SIZES, cold_from=82_000):
+    """Device time of one evaluation (one state) by both methods, injections
+    alone and with the Jacobian, over grid sizes from 118 buses to five
+    replicas of an 82k-bus grid (the paper's Section V.C question, Tables VI
+    and IX-X and the time-cost-ratio figure).  Grids of the same generator
+    (nl = 1.27 nb, 15 % transformers); sizes above 82k are 2-5 disjoint copies
+    of the 82k-bus grid in one handle, as the paper replicates its 82k case.
+    From `cold_from` buses on, each timing rotates over R independent replicas
+    (grid tables, state, outputs) totalling at least 512 MB, so every launch
+    reads cold data from HBM; smaller grids fit the caches whatever is done
+    and run warm.  Per size: microseconds per evaluation, nanoseconds per bus,
+    the time-cost ratio (per-bus time over that of the 118-bus grid) and the
+    Ybus / element-wise time ratio."""
+    dev = torch.device("cuda:0")
     base82 = None
     rows = []
-    for idx, (nb, reps_k) in enumerate(cases):
-        if reps_k is None:
-            g = gridgen.make_grid(nb, round(1.27 * nb), 0.15, case=5, grid=idx)
+    for nb in sizes:
+        if nb <= 82_000:
+            g = gridgen.make_grid(nb, round(1.27 * nb), 0.15, case=5, grid=nb)
             if nb == 82_000:
                 base82 = g
-            G = pf.Grid.from_grid(g)
-            ntot = nb
         else:
-            big, bo, ro = gridgen.concat([base82] * reps_k)
-            G = pf.Grid.from_grid(big, bo, ro)
-            ntot = big.nb
-        pf.pf_ybus(G)
-        vm, va = gridgen.states(ntot, 1, case=5, grid=idx)
-        a, b = torch.as_tensor(vm, device=dev), torch.as_tensor(va, device=dev)
-        p, q = torch.empty_like(a), torch.empty_like(a)
-        j = torch.empty(1, G.nnz_j, dtype=torch.float64, device=dev)
+            if base82 is None:
+                base82 = gridgen.make_grid(82_000, round(1.27 * 82_000), 0.15, case=5, grid=82_000)
+            g, bo, ro = gridgen.concat([base82] * (nb // 82_000))
+        offs = (bo, ro) if nb > 82_000 else (None, None)  # copies are separate grids of one handle
+        vm, va = gridgen.states(g.nb, 1, case=5, grid=nb)
+        G0 = pf.Grid.from_grid(g, *offs)
+        per_rep = algorithmic_bytes(g.nb, g.nl, G0.nnz_y, 1) + 24 * 2 * g.nl  # + lane tables beyond branch data
+        R = max(1, -(-COLD_BYTES // per_rep)) if nb >= cold_from else 1
+        reps = []
+        for r in range(R):
+            G = G0 if r == 0 else pf.Grid.from_grid(g, *offs)
+            pf.pf_ybus(G)
+            reps.append((G, torch.as_tensor(vm, device=dev).clone(), torch.as_tensor(va, device=dev).clone(),
+                         torch.empty(1, g.nb, dtype=torch.float64, device=dev),
+                         torch.empty(1, g.nb, dtype=torch.float64, device=dev),
+                         torch.empty(1, G.nnz_j, dtype=torch.float64, device=dev)))
+        torch.cuda.synchronize()
+        n = max(2 * R, 40)
+
+        def t_us(fn):  # one graph of all n launches, rotating over the R replicas
+            ev, _ = timed(fn, n, R, n)
+            return ev / n * 1e6
         t = {
-            "ew_s": gtime(lambda st: pf.pf_injections_elementwise(G, a, b, p, q, stream=st)),
-            "ew_sj": gtime(lambda st: pf.pf_jacobian_values(G, 0, a, b, p, q, j, stream=st)),
-            "ybus_s": gtime(lambda st: pf.pf_injections_ybus(G, a, b, p, q, stream=st)),
-            "ybus_sj": gtime(lambda st: pf.pf_jacobian_values(G, 1, a, b, p, q, j, stream=st)),
+            "ew_s": t_us(lambda k, st: pf.pf_injections_elementwise(reps[k % R][0], *reps[k % R][1:5], stream=st)),
+            "ew_sj": t_us(lambda k, st: pf.pf_jacobian_values(reps[k % R][0], pf.PF_METHOD_ELEMENTWISE,
+                                                              *reps[k % R][1:], stream=st)),
+            "ybus_s": t_us(lambda k, st: pf.pf_injections_ybus(reps[k % R][0], *reps[k % R][1:5], stream=st)),
+            "ybus_sj": t_us(lambda k, st: pf.pf_jacobian_values(reps[k % R][0], pf.PF_METHOD_YBUS,
+                                                                *reps[k % R][1:], stream=st)),
         }
-        rows.append({"buses": ntot, "replicas_of_82k": reps_k, "us": t,
-                     "ns_per_bus": {k: 1e3 * v / ntot for k, v in t.items()},
+        rows.append({"buses": g.nb, "branches": g.nl, "replicas_of_82k": nb // 82_000 if nb > 82_000 else None,
+                     "cold_replicas": R, "us": t, "ns_per_bus": {k: 1e3 * v / g.nb for k, v in t.items()},
                      "ybus_over_ew": {"s": t["ybus_s"] / t["ew_s"], "sj": t["ybus_sj"] / t["ew_sj"]}})
-        log(f"{ntot:>8d} buses: " + ", ".join(f"{k} {v:.2f} us" for k, v in t.items()))
-        del G, a, b, p, q, j
+        log(f"{g.nb:>8d} buses ({R} replicas): " + ", ".join(f"{k} {v:.2f} us" for k, v in t.items()))
+        del reps, G0
         torch.cuda.empty_cache()
     ref = rows[0]["ns_per_bus"]
     for r in rows:
         r["time_cost_ratio_vs_118"] = {k: r["ns_per_bus"][k] / ref[k] for k in ref}
-    return {"sweep": "EW and Ybus, one state, warm, device time per evaluation", "rows": rows}
+    return {"protocol": f"one state per evaluation, device time by HIP events over graph replays; from "
+                        f"{cold_from} buses on, rotation over replicas of >= 512 MB (cold), smaller grids warm",
+            "rows": rows}
 
 
 def main():
@@ -240,7 +295,8 @@ def main():
     dev = torch.device("cuda:0")
     log = lambda *a: print(*a, file=sys.stderr, flush=True)
     if args.sweep:
-        print(json.dumps(size_sweep(torch, gridgen, pf, log)), flush=True)
+        timer = make_timer(torch, torch.cuda.Stream())
+        print(json.dumps(size_sweep(torch, gridgen, pf, timer, log, SWEEP_SIZES_FULL)), flush=True)
         return
 
     if args.probe_batched:
@@ -299,50 +355,10 @@ def main():
 
     side = torch.cuda.Stream()  # the launch stream (default priority)
 
-    def timed(fn, steps, warmup, period=R):
-        """Time exactly `steps` launches fn(k, stream), issued as replays of HIP
-        graphs that record `period` consecutive launches (plus one graph for
-        the remainder), so the host cost of a call does not bound the rate.
-        Returns (seconds by HIP events on the launch stream, wall seconds)."""
-        period = max(1, min(period, steps))
-        with torch.cuda.stream(side):
-            for k in range(max(warmup, period)):
-                fn(k, side)
-        torch.cuda.synchronize()
+    timer = make_timer(torch, side)
 
-        def record(n):
-            gr = torch.cuda.CUDAGraph()
-            with torch.cuda.graph(gr, stream=side):
-                for k in range(n):
-                    fn(k, side)
-            return gr
-        full, rest = divmod(steps, period)
-        g_full = record(period) if full else None
-        g_rest = record(rest) if rest else None
-        # Untimed replays for at least WARM_S seconds: after host work (grid
-        # builds, schedule changes) the device has idled, and the first
-        # milliseconds of work after that run measurably slower.
-        tw = time.perf_counter()
-        while True:
-            with torch.cuda.stream(side):
-                for _ in range(2):
-                    (g_full or g_rest).replay()
-            torch.cuda.synchronize()
-            if time.perf_counter() - tw >= WARM_S:
-                break
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        t0 = time.perf_counter()
-        with torch.cuda.stream(side):
-            e0.record(side)
-            for _ in range(full):
-                g_full.replay()
-            if g_rest is not None:
-                g_rest.replay()
-            e1.record(side)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        return e0.elapsed_time(e1) / 1e3, wall
+    def timed(fn, steps, warmup, period=R):
+        return timer(fn, steps, warmup, period)
 
     def eager_timed(fn, steps, warmup):
         """The same launches issued one Python call at a time (host-bound)."""
@@ -380,11 +396,16 @@ def main():
 
     K, W = args.steps, args.warmup
     ev_s, wall_s = timed(ew_sj, K, W)
-    value = K / wall_s
+    # value, ms_per_step and the roofline all come from this one event timing
+    # of exactly K launches (device time; the wall clock of the same region
+    # adds the host's graph launch and synchronise, reported beside it)
+    value = K / ev_s
     avg_launch = ev_s / K
+    rotated = min(R, K)
     abytes = algorithmic_bytes(g.nb, g.nl, nnz_y, 1)
     achieved = abytes / avg_launch / 1e9
-    log(f"element-wise S+J: {avg_launch * 1e6:.2f} us/launch (events), {value:.0f} evals/s (wall)")
+    log(f"element-wise S+J: {avg_launch * 1e6:.2f} us/launch, {value:.0f} evals/s (events); "
+        f"wall {wall_s / K * 1e6:.2f} us/step")
 
     # traffic measured by rocprofv3 counters for this exact kernel source, if recorded
     traffic = None
@@ -400,7 +421,7 @@ def main():
         "n_gpus": 1,
         "steps": K,
         "warmup": W,
-        "ms_per_step": wall_s / K * 1e3,
+        "ms_per_step": ev_s / K * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -408,9 +429,11 @@ def main():
         "data": "synthetic (seeded generator standing in for the paper's MATPOWER cases)",
         "config": {"workload": "100k-bus grid (nb=100000, nl=130000, 20% transformers), 1 voltage state, "
                                "element-wise S + full polar Jacobian, one launch per step, steps issued as "
-                               "HIP-graph replays over 24 cold replicas",
+                               f"HIP-graph replays rotating over {rotated} cold replicas",
                    "nb": g.nb, "nl": g.nl, "nnz_y": nnz_y, "nnz_j": nnz_j, "states": 1,
-                   "replicas_rotated": R, "tile_items": tile},
+                   "replicas_rotated": rotated, "replica_bytes": rotated * (abytes + 48 * g.nl),
+                   "tile_items": tile, "timing": "HIP events on the launch stream around exactly `steps` launches",
+                   "wall_ms_per_step": wall_s / K * 1e3},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": f"k_ew<{tile}, false, true, true>", "algorithmic_bytes_per_launch": abytes,
@@ -442,7 +465,7 @@ def main():
             pf.pf_jacobian_values(d["G"], pf.PF_METHOD_YBUS, d["vm"], d["va"], d["p"], d["q"], d["j"], stream=st)
         ev, wall = timed(yb_sj, K, W)
         yb_bytes = algorithmic_bytes(g.nb, g.nl, nnz_y, 1, method="ybus")
-        extra["ybus_sj"] = {"evals_per_s": K / wall, "avg_launch_us": ev / K * 1e6,
+        extra["ybus_sj"] = {"evals_per_s": K / ev, "avg_launch_us": ev / K * 1e6,
                             "achieved_GBs": yb_bytes / (ev / K) / 1e9, "algorithmic_bytes": yb_bytes,
                             "ew_speedup_vs_ybus": (ev / K) / avg_launch}
         log(f"Ybus S+J: {ev / K * 1e6:.2f} us/launch")
@@ -460,7 +483,7 @@ def main():
             pf.pf_jacobian_values(d["G"], pf.PF_METHOD_ELEMENTWISE_TWO_PHASE | pf.PF_EW_PRECOMPUTED, d["vm"], d["va"],
                                   d["p"], d["q"], d["j"], stream=st)
         ev_pre, _ = timed(tp_pre, K, W)
-        extra["ew_two_phase_sj"] = {"evals_per_s": K / wall, "avg_eval_us": ev / K * 1e6,
+        extra["ew_two_phase_sj"] = {"evals_per_s": K / ev, "avg_eval_us": ev / K * 1e6,
                                     "achieved_GBs": abytes / (ev / K) / 1e9, "launches_per_eval": 2,
                                     "fused_speedup": (ev / K) / avg_launch,
                                     "precomputed_constants_us": ev_pre / K * 1e6}
@@ -479,7 +502,7 @@ def main():
             pf.pf_jacobian_values(d["G"], pf.PF_METHOD_ELEMENTWISE_ATOMIC | pf.PF_EW_PRECOMPUTED, d["vm"], d["va"],
                                   d["p"], d["q"], d["j"], stream=st)
         ev_pre, _ = timed(ca_pre, K, W)
-        extra["ew_copy_add_atomic_sj"] = {"evals_per_s": K / wall, "avg_eval_us": ev / K * 1e6,
+        extra["ew_copy_add_atomic_sj"] = {"evals_per_s": K / ev, "avg_eval_us": ev / K * 1e6,
                                           "achieved_GBs": abytes / (ev / K) / 1e9, "launches_per_eval": 3,
                                           "fused_speedup": (ev / K) / avg_launch,
                                           "precomputed_constants_us": ev_pre / K * 1e6}
@@ -493,7 +516,7 @@ def main():
                                   d["j"], stream=st)
         ev, wall = timed(ew_csc, K, W)
         cb = abytes + 32 * g.nl  # + the opposite end's coupling, 16 B per branch end (lane table)
-        extra["ew_sj_csc"] = {"evals_per_s": K / wall, "avg_launch_us": ev / K * 1e6,
+        extra["ew_sj_csc"] = {"evals_per_s": K / ev, "avg_launch_us": ev / K * 1e6,
                               "achieved_GBs": abytes / (ev / K) / 1e9, "over_csr_time": (ev / K) / avg_launch,
                               "kernel": f"k_ew_csc<{tile}, false, true>", "bytes_read_extra": cb - abytes}
         log(f"element-wise S+J, CSC order: {ev / K * 1e6:.2f} us/launch")
@@ -506,7 +529,7 @@ def main():
             pf.pf_jacobian_values(d["G"], pf.PF_METHOD_YBUS | pf.PF_JAC_CSC, d["vm"], d["va"], d["p"], d["q"], d["j"],
                                   stream=st)
         ev, wall = timed(yb_csc, K, W)
-        extra["ybus_sj_csc"] = {"evals_per_s": K / wall, "avg_launch_us": ev / K * 1e6,
+        extra["ybus_sj_csc"] = {"evals_per_s": K / ev, "avg_launch_us": ev / K * 1e6,
                                 "kernel": f"k_ybus_csc<{tile}, true>"}
         log(f"Ybus S+J, CSC order: {ev / K * 1e6:.2f} us/launch")
 
@@ -557,7 +580,7 @@ def main():
             pf.pf_branch_flows(d["G"], d["vm"], d["va"], *d["fl"], d["fj"], stream=st)
         ev, wall = timed(flows, K, W)
         fb = 48 * g.nl + 16 * g.nb + (32 + 128) * g.nl  # branch data + state in, flows + partials out
-        extra["branch_flows_jac"] = {"evals_per_s": K / wall, "avg_launch_us": ev / K * 1e6,
+        extra["branch_flows_jac"] = {"evals_per_s": K / ev, "avg_launch_us": ev / K * 1e6,
                                      "achieved_GBs": fb / (ev / K) / 1e9, "algorithmic_bytes": fb}
         for d in reps:
             del d["fl"], d["fj"]
@@ -626,7 +649,7 @@ def main():
             d = reps[0]
             pf.pf_jacobian_values(d["G"], pf.PF_METHOD_ELEMENTWISE, d["vm"], d["va"], d["p"], d["q"], d["j"], stream=st)
         ev, wall = timed(ew_warm, K, W)
-        extra["ew_sj_warm_cache"] = {"evals_per_s": K / wall, "avg_launch_us": ev / K * 1e6}
+        extra["ew_sj_warm_cache"] = {"evals_per_s": K / ev, "avg_launch_us": ev / K * 1e6}
         wall = eager_timed(ew_sj, K, W)
         extra["ew_sj_eager_python_calls"] = {"evals_per_s": K / wall, "us_per_call": wall / K * 1e6,
                                              "note": "one binding call per step; bound by host time"}
@@ -641,14 +664,14 @@ def main():
             d = reps[k % R]
             pf.pf_injections_elementwise(d["G"], d["vm"], d["va"], d["p"], d["q"], stream=st)
         ev, wall = timed(ew_s, K, W)
-        extra["ew_s_only"] = {"evals_per_s": K / wall, "avg_launch_us": ev / K * 1e6,
+        extra["ew_s_only"] = {"evals_per_s": K / ev, "avg_launch_us": ev / K * 1e6,
                               "achieved_GBs": algorithmic_bytes(g.nb, g.nl, nnz_y, 1, with_j=False) / (ev / K) / 1e9}
         if "ybus_sj" in extra:
             def yb_s(k, st):
                 d = reps[k % R]
                 pf.pf_injections_ybus(d["G"], d["vm"], d["va"], d["p"], d["q"], stream=st)
             ev, wall = timed(yb_s, K, W)
-            extra["ybus_s_only"] = {"evals_per_s": K / wall, "avg_launch_us": ev / K * 1e6}
+            extra["ybus_s_only"] = {"evals_per_s": K / ev, "avg_launch_us": ev / K * 1e6}
         log("warm/S-only done")
 
     if want("phasor"):
@@ -717,7 +740,7 @@ def main():
             tuned["batched"] = autotune.tune(G2, "jacobian_ew", B, cache=tune_cache, save=False)
         ev, wall = timed(b_sj, steps, 5, period=10)
         bb = algorithmic_bytes(g2.nb, g2.nl, G2.nnz_y, B)
-        extra["batched_20k_x512"] = {"state_evals_per_s": B * steps / wall, "avg_launch_us": ev / steps * 1e6,
+        extra["batched_20k_x512"] = {"state_evals_per_s": B * steps / ev, "avg_launch_us": ev / steps * 1e6,
                                      "achieved_GBs": bb / (ev / steps) / 1e9,
                                      "frac_hbm": bb / (ev / steps) / 1e9 / HBM_PEAK_GBS,
                                      "algorithmic_bytes": bb, "schedule": G2.schedule(),
@@ -782,7 +805,7 @@ def main():
             tuned["multigrid"] = autotune.tune(G3, "jacobian_ew", 4, cache=tune_cache, cands=cands, save=False)
         ev, wall = timed(m_sj, steps, 5, period=10)
         mb = algorithmic_bytes(big.nb, big.nl, G3.nnz_y, 4)
-        extra["multigrid_64x4"] = {"grid_state_evals_per_s": 256 * steps / wall, "avg_launch_us": ev / steps * 1e6,
+        extra["multigrid_64x4"] = {"grid_state_evals_per_s": 256 * steps / ev, "avg_launch_us": ev / steps * 1e6,
                                    "achieved_GBs": mb / (ev / steps) / 1e9,
                                    "frac_hbm": mb / (ev / steps) / 1e9 / HBM_PEAK_GBS, "algorithmic_bytes": mb,
                                    "buses": big.nb, "branches": big.nl, "schedule": G3.schedule()}
@@ -837,7 +860,7 @@ def main():
         ev_j, wall_j = timed(lambda k, st: pf.pf_jacobian_values(G4, pf.PF_METHOD_ELEMENTWISE, vm4d, va4d, p4, q4, j4,
                                                                  stream=st), steps, 5, period=10)
         jb = algorithmic_bytes(g.nb, g.nl, G4.nnz_y, B)
-        extra["ew_sj_100k_x32"] = {"state_evals_per_s": B * steps / wall_j, "avg_launch_us": ev_j / steps * 1e6,
+        extra["ew_sj_100k_x32"] = {"state_evals_per_s": B * steps / ev_j, "avg_launch_us": ev_j / steps * 1e6,
                                    "achieved_GBs": jb / (ev_j / steps) / 1e9,
                                    "frac_hbm": jb / (ev_j / steps) / 1e9 / HBM_PEAK_GBS, "algorithmic_bytes": jb,
                                    "schedule": G4.schedule()}
@@ -871,6 +894,9 @@ def main():
         log(f"newton: {res.iterations} iterations, eval {extra['newton_5k']['eval_ms_per_iter']:.3f} ms/iter, "
             f"solve {extra['newton_5k']['solve_ms_per_iter']:.2f} ms/iter")
         del G5
+
+    if want("sweep"):
+        extra["sweep"] = size_sweep(torch, gridgen, pf, timer, log)
 
     if tuned:
         extra["autotuner"] ={k: {"schedule": v["schedule"], "us": v["us"], "tried": v["tried"]}
