@@ -895,6 +895,38 @@ def main():
             f"solve {extra['newton_5k']['solve_ms_per_iter']:.2f} ms/iter")
         del G5
 
+    if want("hubs"):
+        # long rows: 32 hub buses of 200-2000 branches each on a 20k-bus grid, against the
+        # same grid without the hub lines; one state, warm (the tables fit the caches)
+        res_h = {}
+        for tag, gh in (("with_hubs", gridgen.grid_hubs()), ("without_hubs", gridgen.make_grid(20_000, 27_000, 0.15,
+                                                                                               case=6))):
+            Gh = pf.Grid.from_grid(gh)
+            pf.pf_ybus(Gh)
+            vmh, vah = gridgen.states(gh.nb, 1, case=6)
+            vh, ah = torch.as_tensor(vmh, device=dev), torch.as_tensor(vah, device=dev)
+            ph, qh = torch.empty_like(vh), torch.empty_like(vh)
+            jh = torch.empty(1, Gh.nnz_j, dtype=torch.float64, device=dev)
+            n = 100
+            row = {"branches": gh.nl}
+            for mname, fn in (("ew_s", lambda k, st: pf.pf_injections_elementwise(Gh, vh, ah, ph, qh, stream=st)),
+                              ("ew_sj", lambda k, st: pf.pf_jacobian_values(Gh, pf.PF_METHOD_ELEMENTWISE, vh, ah, ph,
+                                                                            qh, jh, stream=st)),
+                              ("ybus_s", lambda k, st: pf.pf_injections_ybus(Gh, vh, ah, ph, qh, stream=st)),
+                              ("ybus_sj", lambda k, st: pf.pf_jacobian_values(Gh, pf.PF_METHOD_YBUS, vh, ah, ph, qh,
+                                                                              jh, stream=st))):
+                ev, _ = timed(fn, n, 3, period=n)
+                row[mname + "_us"] = ev / n * 1e6
+            res_h[tag] = row
+            del Gh, vh, ah, ph, qh, jh
+        res_h["hub_degrees"] = {"count": 32, "min": 200, "max": 2000, "total_hub_branches":
+                                res_h["with_hubs"]["branches"] - res_h["without_hubs"]["branches"]}
+        extra["hubs_20k"] = res_h
+        log("hubs: " + ", ".join(f"{k} {v:.2f} us" for k, v in res_h["with_hubs"].items() if k.endswith("_us")) +
+            " (without hubs: " + ", ".join(f"{v:.2f}" for k, v in res_h["without_hubs"].items() if k.endswith("_us"))
+            + ")")
+        torch.cuda.empty_cache()
+
     if want("sweep"):
         extra["sweep"] = size_sweep(torch, gridgen, pf, timer, log)
 

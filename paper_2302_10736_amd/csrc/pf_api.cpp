@@ -121,6 +121,10 @@ void build_tiles(pf_grid *g, int NT) {
             d.ne = d.n - (z - a);  // one shunt record per row
             d.s0 = g->yrow[a];
             d.ns = g->yrow[z] - d.s0;
+            d.sh = 0;
+            if (z == a + 1)  // one row: where its bus-shunt record sits among its records
+                for (int32_t e = g->irow[a]; e < g->irow[z]; ++e)
+                    if (g->item_br[e] < 0) d.sh = e - d.i0;
             // Grid gi's J values start at 4 y_off[gi]; its P rows hold
             // 2 nnz_y(gi) values, so row i's P part starts at
             // 2 y_off[gi] + 2 yrow[i] and its Q part at 2 y_off[gi+1] + 2 yrow[i].

@@ -17,8 +17,11 @@ struct TileDesc {
     int32_t i0, n;      // first record, number of records (shunt records included)
     int32_t ne;         // branch-end records (n - nrows)
     int32_t s0, ns;     // first Ybus slot, number of slots
+    int32_t sh;         // one-row tiles: position of the bus-shunt record in the row (else 0)
     int64_t jp, jq;     // offsets of the tile's P rows and Q rows in one state's J values
 };
+
+static_assert(sizeof(TileDesc) == 48, "tile descriptors are uploaded as raw bytes");
 
 // Ybus slots an element-wise tile may hold (its LDS copy of the J rows),
 // for NT branch ends per tile: rows carry ~1.4 slots per branch end.

@@ -152,11 +152,17 @@ __device__ __forceinline__ int ew_o12(int v) { return (v >> 11) & 0x7ff; }
 __device__ __forceinline__ int ew_row(int v) { return (int)((unsigned)v >> 22); }
 
 // Walk states [sb, se) (never empty) with the per-state inputs of each state
-// loaded one state ahead; `ra` holds state sb's inputs on entry.  Two register sets alternate (states are taken in pairs), so
-// the loop never copies registers that are still being loaded: a copy would
-// make the wave wait for every outstanding memory operation, including the
-// previous state's stores.  `proc(s, parity, in)` gets parity = (s - sb) & 1
-// for the double-buffered LDS.
+// loaded one state ahead; `ra` holds state sb's inputs on entry.  Two
+// register sets alternate (states are taken in pairs), so the loop never
+// copies registers that are still being loaded: a copy would make the wave
+// wait for every outstanding memory operation, including the previous
+// state's stores.  The loop body has no branch: the memory counter counts
+// loads and stores in issue order, and a load or store behind a branch makes
+// the compiler wait for every outstanding operation where the paths join,
+// prefetch included.  So every pair runs both of its states; when the count
+// is odd, the last pair evaluates the last state twice and writes the same
+// values to the same places again.  `proc(s, parity, in)` gets the parity of
+// the state's position for the double-buffered LDS.
 template <class In, bool ONE, class Load, class Proc>
 __device__ __forceinline__ void pipelined_states(int sb, int se, In &ra, Load &&load, Proc &&proc) {
     if constexpr (ONE) {  // one state per workgroup: nothing to overlap, half the registers
@@ -165,10 +171,11 @@ __device__ __forceinline__ void pipelined_states(int sb, int se, In &ra, Load &&
     }
     In rb{};
     for (int s = sb; s < se; s += 2) {
-        if (s + 1 < se) load(s + 1, rb);
+        const int s1 = min(s + 1, se - 1);
+        load(s1, rb);
         proc(s, 0, ra);
-        if (s + 2 < se) load(s + 2, ra);
-        if (s + 1 < se) proc(s + 1, 1, rb);
+        load(min(s + 2, se - 1), ra);
+        proc(s1, 1, rb);
     }
 }
 
@@ -204,12 +211,57 @@ __device__ __forceinline__ void row_sum2_acc(const double *x, const double *y, i
     }
 }
 
-// The same sums started from zero.
+// Bus sums in an order set by the pattern alone: a row's terms (its branch
+// ends, or its Ybus nonzeros) are taken in consecutive chunks of kSumChunk
+// from the start of the row, each chunk is summed left to right from zero,
+// and the chunk sums are added left to right (the first one taken as it
+// is).  Rows of at most kSumChunk terms, nearly all of them, are a plain
+// left-to-right sum.  Rows longer than a tile sum their chunks in parallel
+// (chunk_sums, fold_chunks) and still produce the bits of the packed path,
+// whatever the tile size.
+constexpr int kSumChunk = 32;
+
 __device__ __forceinline__ void row_sum2(const double *x, const double *y, int a, int z, double &sx, double &sy) {
     double u = 0.0, v = 0.0;
-    row_sum2_acc(x, y, a, z, u, v);
+    const int e = min(z, a + kSumChunk);
+    row_sum2_acc(x, y, a, e, u, v);
+    for (int c = e; c < z; c += kSumChunk) {  // rows longer than one chunk
+        double cu = 0.0, cv = 0.0;
+        row_sum2_acc(x, y, c, min(z, c + kSumChunk), cu, cv);
+        u += cu;
+        v += cv;
+    }
     sx = u;
     sy = v;
+}
+
+// Long rows, one piece of m <= NT terms starting at a multiple of kSumChunk
+// in the row: thread q sums chunk q of the piece into csx[q], csy[q].
+__device__ __forceinline__ void chunk_sums(const double *x, const double *y, int m, double *csx, double *csy) {
+    const int q = threadIdx.x;
+    if (q * kSumChunk < m) {
+        double u = 0.0, v = 0.0;
+        row_sum2_acc(x, y, q * kSumChunk, min(m, (q + 1) * kSumChunk), u, v);
+        csx[q] = u;
+        csy[q] = v;
+    }
+}
+
+// Long rows, one thread: adds the piece's chunk sums in order to the running
+// row sums (the row's first chunk is taken as it is).
+__device__ __forceinline__ void fold_chunks(const double *csx, const double *csy, int m, bool first_piece, double &u,
+                                            double &v) {
+    const int nc = (m + kSumChunk - 1) / kSumChunk;
+    int q = 0;
+    if (first_piece && nc > 0) {
+        u = csx[0];
+        v = csy[0];
+        q = 1;
+    }
+    for (; q < nc; ++q) {
+        u += csx[q];
+        v += csy[q];
+    }
 }
 
 // One element-wise record (see the file header): its row-sum terms and the
@@ -293,9 +345,8 @@ __device__ __forceinline__ void ew_eval(const DevGrid &g, int nstate, int spb, i
     constexpr int NR = (WITH_J && PAR) ? NT : 1;  // remote partials kept for slot sums
     constexpr int NBUF = ONE ? 1 : 2;             // LDS buffers alternate between states
     constexpr int NS = kEwSlots(NT);              // Ybus slots per tile
-    __shared__ int s_ls[NT];   // long rows: local slot of each record of a chunk
-    __shared__ int s_dslot[1];  // long rows: local diagonal slot
-    __shared__ int s_cls[2];    // long rows: slot carried into the next chunk (-1: none), by chunk parity
+    __shared__ int s_ls[NT];   // long rows: local slot of each branch end of a piece
+    __shared__ int s_cls[2];    // long rows: slot carried into the next piece (-1: none), by piece parity
     __shared__ double s_carry[8];  // long rows: its partial sums, written [4, 8), read [0, 4)
     __shared__ double s_ab[NBUF][2][NT];
     __shared__ __align__(16) double s_J[NBUF][WITH_J ? kJStage<NS> : 2];
@@ -319,31 +370,35 @@ __device__ __forceinline__ void ew_eval(const DevGrid &g, int nstate, int spb, i
     const size_t nb = (size_t)g.nb;
 
     if (c.ne > NT) {
-        // ---- one row with more than NT branch ends, walked in chunks of NT
-        // records.  Each thread evaluates one record of the chunk; the first
-        // record of each Ybus slot in the chunk sums its slot's records in
-        // order and writes the slot's four J values (a slot that the chunk end
-        // cuts hands its partial sums to the next chunk through LDS, so every
-        // slot sum runs in record order); thread 0 carries the row sums, in
-        // record order.  The diagonal slot holds only the bus-shunt record;
-        // thread 0 writes it last, from the row sums.
+        // ---- one row with more than NT branch ends, walked in pieces of NT
+        // branch ends (position p of the row's branch ends is record
+        // i0 + p, one further from the bus-shunt record on, c.sh).  Each
+        // thread evaluates one branch end of the piece; threads q < NT /
+        // kSumChunk sum the piece's chunks and thread 0 folds them into the
+        // row sums (the order of row_sum2); the first branch end of each
+        // Ybus slot in the piece sums its slot's records in order and writes
+        // the slot's four J values (a slot that the piece end cuts hands its
+        // partial sums to the next piece through LDS, so every slot sum runs
+        // in record order).  Thread 0 writes the diagonal slot last, from the
+        // row sums.
+        __shared__ double s_cs[2][NT / kSumChunk];
         const int i = c.r0;
         const int d = c.ns;  // slots in the row
         const double dA = g.dA[i], dC = g.dC[i];
+        auto rec = [&](int p) { return c.i0 + p + (p >= c.sh ? 1 : 0); };
         for (int s = sb; s < se; ++s) {
             const double *vms = vm + (size_t)s * nb;
             const double *vas = va + (size_t)s * nb;
             double *Js = WITH_J ? J + (size_t)s * (size_t)g.nnz_j : nullptr;
             const double vi = vms[i], ti = vas[i];
             double as = 0.0, bs = 0.0;
-            if (WITH_J && k == 0) s_cls[1] = -1;  // nothing carried into the first chunk
-            for (int base = 0, chunk = 0; base < c.n; base += NT, ++chunk) {
-                const int m = min(NT, c.n - base);
+            if (WITH_J && k == 0) s_cls[1] = -1;  // nothing carried into the first piece
+            for (int base = 0, piece = 0; base < c.ne; base += NT, ++piece) {
+                const int m = min(NT, c.ne - base);
                 int ls = -1;
-                bool shunt = false;
-                if (WITH_J && k == 0) s_cls[chunk & 1] = -1;  // read last in the previous chunk
+                if (WITH_J && k == 0) s_cls[piece & 1] = -1;  // read last in the previous piece
                 if (k < m) {
-                    const int e = c.i0 + base + k;
+                    const int e = rec(base + k);
                     const int je = g.nbr[e];
                     EwRec r;
                     if constexpr (CSC)
@@ -359,17 +414,15 @@ __device__ __forceinline__ void ew_eval(const DevGrid &g, int nstate, int spb, i
                         s_J[0][3 * NT + k] = r.o[3];
                         ls = (PAR ? g.slot[e] : e) - c.s0;
                         s_ls[k] = ls;
-                        shunt = je == i;
-                        if (shunt) s_dslot[0] = ls;
                     }
                 }
                 __syncthreads();
-                if (k == 0) row_sum2_acc(s_ab[0][0], s_ab[0][1], 0, m, as, bs);
+                chunk_sums(s_ab[0][0], s_ab[0][1], m, s_cs[0], s_cs[1]);
                 if constexpr (WITH_J) {
-                    const int prev_cls = s_cls[(chunk + 1) & 1];  // slot carried in from the previous chunk
+                    const int prev_cls = s_cls[(piece + 1) & 1];  // slot carried in from the previous piece
                     const bool cont = k == 0 && ls == prev_cls;
                     const bool head = k < m && (k == 0 || ls != s_ls[k - 1]);
-                    if (head && !shunt) {
+                    if (head) {
                         double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
                         if (cont) {
                             a0 = s_carry[0];
@@ -384,13 +437,13 @@ __device__ __forceinline__ void ew_eval(const DevGrid &g, int nstate, int spb, i
                             a2 += s_J[0][2 * NT + q];
                             a3 += s_J[0][3 * NT + q];
                         }
-                        const int en = c.i0 + base + m;  // first record of the next chunk
-                        if (q == m && base + m < c.n && (PAR ? g.slot[en] : en) - c.s0 == ls) {
-                            s_carry[4] = a0;  // the slot goes on in the next chunk
+                        const int pn = base + m;  // first branch end of the next piece
+                        if (q == m && pn < c.ne && (PAR ? g.slot[rec(pn)] : rec(pn)) - c.s0 == ls) {
+                            s_carry[4] = a0;  // the slot goes on in the next piece
                             s_carry[5] = a1;
                             s_carry[6] = a2;
                             s_carry[7] = a3;
-                            s_cls[chunk & 1] = ls;
+                            s_cls[piece & 1] = ls;
                         } else {
                             st_out(Js + c.jp + ls, a0);
                             st_out(Js + c.jp + d + ls, a1);
@@ -400,12 +453,15 @@ __device__ __forceinline__ void ew_eval(const DevGrid &g, int nstate, int spb, i
                     }
                 }
                 __syncthreads();
-                if constexpr (WITH_J) {  // the carried partial sums move to the slots read by the next chunk
-                    if (k == 0 && s_cls[chunk & 1] >= 0) {
-                        s_carry[0] = s_carry[4];
-                        s_carry[1] = s_carry[5];
-                        s_carry[2] = s_carry[6];
-                        s_carry[3] = s_carry[7];
+                if (k == 0) {
+                    fold_chunks(s_cs[0], s_cs[1], m, piece == 0, as, bs);
+                    if constexpr (WITH_J) {  // the carried partial sums move to the slots read by the next piece
+                        if (s_cls[piece & 1] >= 0) {
+                            s_carry[0] = s_carry[4];
+                            s_carry[1] = s_carry[5];
+                            s_carry[2] = s_carry[6];
+                            s_carry[3] = s_carry[7];
+                        }
                     }
                 }
             }
@@ -416,7 +472,8 @@ __device__ __forceinline__ void ew_eval(const DevGrid &g, int nstate, int spb, i
                     st_out(Q + (size_t)s * nb + i, o.q);
                 }
                 if constexpr (WITH_J) {
-                    const int ld = s_dslot[0];
+                    const int sh = c.i0 + c.sh;  // the bus-shunt record: the diagonal slot
+                    const int ld = (PAR ? g.slot[sh] : sh) - c.s0;
                     st_out(Js + c.jp + ld, o.j11);
                     st_out(Js + c.jp + d + ld, CSC ? o.j21 : o.j12);
                     st_out(Js + c.jq + ld, CSC ? o.j12 : o.j21);
@@ -665,8 +722,9 @@ __device__ __forceinline__ void yb_eval(const DevGrid &g, int nstate, int spb, i
     const size_t nb = (size_t)g.nb;
 
     if (c.ns > NT) {
-        // ---- one long row: pass 1 sums I_i in chunks (thread 0, in slot order, four terms per LDS
-        // round trip), pass 2 writes J.
+        // ---- one long row: pass 1 sums I_i in pieces of NT nonzeros (chunk sums in parallel,
+        // folded by thread 0 in row_sum2's order), pass 2 writes J.
+        __shared__ double s_cs[2][NT / kSumChunk];
         const int i = c.r0;
         const int d = c.ns;
         const size_t n = (size_t)nstate * nb;
@@ -674,7 +732,8 @@ __device__ __forceinline__ void yb_eval(const DevGrid &g, int nstate, int spb, i
             const size_t so = (size_t)s * nb;
             Cx I = {0.0, 0.0};
             for (int base = 0; base < d; base += NT) {
-                if (base + k < d) {
+                const int m = min(NT, d - base);
+                if (k < m) {
                     const int p = c.s0 + base + k;
                     const int jc = g.ycol[p];
                     YbIn x;
@@ -686,13 +745,15 @@ __device__ __forceinline__ void yb_eval(const DevGrid &g, int nstate, int spb, i
                     s_yv[0][1][k] = yv.im;
                 }
                 __syncthreads();
+                chunk_sums(s_yv[0][0], s_yv[0][1], m, s_cs[0], s_cs[1]);
+                __syncthreads();
                 if (k == 0) {
-                    row_sum2_acc(s_yv[0][0], s_yv[0][1], 0, min(NT, d - base), I.re, I.im);
+                    fold_chunks(s_cs[0], s_cs[1], m, base == 0, I.re, I.im);
                     s_vu[0][0][0] = I.re;
                     s_vu[0][1][0] = I.im;
                 }
-                __syncthreads();
             }
+            __syncthreads();
             YbIn xi;
             yb_load<PH, true>(vm, va, ph, n, so + i, xi);
             Cx Vi, Ui;
@@ -923,22 +984,29 @@ __global__ void __launch_bounds__(NT)
     };
 
     if (c.ne > NT) {
+        // one row with more than NT branch ends, in pieces of NT branch ends
+        // (the bus-shunt record, position c.sh, contributes nothing and is
+        // skipped); chunk sums in parallel, folded by thread 0 in row_sum2's order
+        __shared__ double s_cs[2][NT / kSumChunk];
         const int i = c.r0;
         const double dA = g.dA[i], dC = g.dC[i];
         for (int s = sb; s < se; ++s) {
             const size_t so = (size_t)s * nb;
             double acc_a = 0.0, acc_v = 0.0;
-            for (int base = 0; base < c.n; base += NT) {
-                if (base + k < c.n) {
-                    const int e = c.i0 + base + k;
+            for (int base = 0; base < c.ne; base += NT) {
+                const int m = min(NT, c.ne - base);
+                if (k < m) {
+                    const int pos = base + k;
+                    const int e = c.i0 + pos + (pos >= c.sh ? 1 : 0);
                     double ga, gv;
                     vjp_record(fetch(so, i, g.nbr[e]), g.G[e], g.B[e], g.Gr[e], g.Br[e], ga, gv);
                     s_val[0][0][k] = ga;
                     s_val[0][1][k] = gv;
                 }
                 __syncthreads();
-                if (k == 0) row_sum2_acc(s_val[0][0], s_val[0][1], 0, min(NT, c.n - base), acc_a, acc_v);
+                chunk_sums(s_val[0][0], s_val[0][1], m, s_cs[0], s_cs[1]);
                 __syncthreads();
+                if (k == 0) fold_chunks(s_cs[0], s_cs[1], m, base == 0, acc_a, acc_v);
             }
             if (k == 0) {
                 const double vi = vm[so + i];

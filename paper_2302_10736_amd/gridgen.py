@@ -217,6 +217,42 @@ def grids_uneven_64(ngrid: int = 64) -> list[Grid]:
     return [make_grid(nb, nl, 0.15, case=3, grid=k + 1) for k, (nb, nl) in enumerate(uneven_sizes(ngrid))]
 
 
+def grid_hubs(nb: int = 20_000, nl: int = 27_000, nhub: int = 32, deg_lo: int = 200, deg_hi: int = 2_000,
+              case: int = 6) -> Grid:
+    """A generator grid (15 % transformers) plus ``nhub`` hub buses, each
+    joined to a log-uniform number of distinct other buses in [deg_lo,
+    deg_hi] by extra lines of the same parameter distributions (the long-row
+    timing case: hub rows exceed every tile size)."""
+    base = make_grid(nb, nl, 0.15, case=case)
+    g = rng(case, 0, 5)
+    hubs = g.choice(nb, size=nhub, replace=False)
+    deg = np.rint(np.exp(g.uniform(math.log(deg_lo), math.log(deg_hi), nhub))).astype(np.int64)
+    existing = set(zip(np.minimum(base.fbus, base.tbus).tolist(), np.maximum(base.fbus, base.tbus).tolist()))
+    pairs = []
+    for h, d in zip(hubs.tolist(), deg.tolist()):
+        cand = g.permutation(nb)
+        got = 0
+        for c in cand.tolist():
+            key = (min(h, c), max(h, c))
+            if c == h or key in existing:
+                continue
+            existing.add(key)
+            pairs.append((h, c))
+            got += 1
+            if got == d:
+                break
+    pairs = np.asarray(pairs, dtype=np.int64)
+    m = len(pairs)
+    flip = g.random(m) < 0.5
+    fb = np.where(flip, pairs[:, 1], pairs[:, 0]).astype(np.int32)
+    tb = np.where(flip, pairs[:, 0], pairs[:, 1]).astype(np.int32)
+    cat = lambda a, b: np.concatenate([a, b])
+    return Grid(nb, nl + m, cat(base.fbus, fb), cat(base.tbus, tb), cat(base.r, g.uniform(0.001, 0.05, m)),
+                cat(base.x, g.uniform(0.01, 0.3, m)), cat(base.b, g.uniform(0.0, 0.1, m)), cat(base.tap, np.ones(m)),
+                cat(base.shift, np.zeros(m)), base.gs.copy(), base.bs.copy(),
+                meta={"case": case, "hubs": hubs.tolist(), "hub_degrees": deg.tolist()})
+
+
 def concat(grids: list[Grid]) -> tuple[Grid, np.ndarray, np.ndarray]:
     """Concatenate grids for one multi-grid handle.
 

@@ -160,6 +160,35 @@ def test_determinism_across_runs_and_schedules():
                     assert np.array_equal(ref[k], other[k]), (k, tile, spb, order)
 
 
+@pytest.mark.parametrize("n_leaf,parallel", [(40, 0), (100, 3), (333, 0), (700, 25)])
+def test_hub_rows_bitwise_across_schedules(n_leaf, parallel):
+    """Bus sums run in chunks of 32 terms fixed by the row alone, so a hub row
+    gives the same bits whether its tile packs it (tile size above its branch
+    ends) or walks it in pieces of the tile size (the long-row path), for
+    every tile size and states per workgroup; every run matches the oracle.
+    The hub sits mid-numbering, so its bus-shunt record lies inside its row."""
+    g = star_grid(n_leaf, seed=n_leaf, parallel=parallel)
+    perm = np.arange(g.nb)
+    perm[0], perm[g.nb // 2] = g.nb // 2, 0
+    g = gridgen.renumber(g, perm)
+    rng = np.random.default_rng(n_leaf)
+    ns = 3
+    vm = rng.uniform(0.9, 1.1, (ns, g.nb))
+    va = rng.normal(0, 0.3, (ns, g.nb))
+    lp, lq = rng.normal(size=vm.shape), rng.normal(size=vm.shape)
+    G = pf.Grid.from_grid(g)
+    ref = gpu_all(G, vm, va, lp, lq)
+    for s in range(ns):
+        compare_grid(ref, oracle_all(g, vm[s], va[s], lp[s], lq[s]), s, slice(None), slice(None), slice(None))
+    fixed = [k for k in ref if not k.endswith("_ca")]
+    for tile in (64, 128, 512):
+        for spb in (1, 2):
+            G.set_schedule(tile, spb, pf.PF_ORDER_AUTO)
+            other = gpu_all(G, vm, va, lp, lq)
+            for k in fixed:
+                assert np.array_equal(ref[k], other[k]), (k, tile, spb)
+
+
 def test_graph_replays_match_eager_calls():
     """A recorded [injections, Jacobian (both methods), VJP, Jacobian in CSC order] sequence, replayed
     several times with eager work and input changes in between; every replay
