@@ -306,7 +306,9 @@ int pf_jacobian_scatter(const pf_grid *g, int32_t nstate, const double *jval, co
  *                     one tile are adjacent), PF_ORDER_STATE_MAJOR (the tiles
  *                     of one state chunk are adjacent, so concurrent
  *                     workgroups write neighbouring parts of J) or
- *                     PF_ORDER_AUTO (= state-major)
+ *                     PF_ORDER_AUTO (state-major for Jacobian launches,
+ *                     tile-major for injections and the adjoint, whose state
+ *                     chunks of one tile then share an L2)
  * The initial schedule is tile_items 256 (with several grids per handle:
  * the smallest of 64, 128, 256 that holds the mean branch ends per grid,
  * since tiles never span grids), states_per_block 0, PF_ORDER_AUTO.
@@ -356,6 +358,31 @@ typedef struct {
 int pf_graph_create(const pf_grid *g, const pf_op *ops, int32_t nops, pf_graph **out);
 int pf_graph_launch(const pf_graph *gr, void *stream);
 void pf_graph_free(pf_graph *gr);
+
+/* Schedule autotuner.  Times candidate launch schedules (pf_set_schedule)
+ * for one operation and leaves the fastest set on the handle; results never
+ * depend on the schedule, so tuning changes speed only.
+ *   op      the operation, as for pf_graph_create, on the caller's DEVICE
+ *           buffers (its outputs are overwritten); nstate >= 1
+ *   ncand, cand  int32[3 ncand] host array of (tile_items, states_per_block,
+ *           order) triples, or ncand = 0 for the default set: tile_items in
+ *           {64, 128, 256, 512} x states_per_block in {0, 1, 2, 4, 8, 16, 32,
+ *           64} up to nstate x both work orders (one state: the four tile
+ *           sizes, one state per workgroup)
+ *   reps    calls per timing in [1, 1000]: each candidate records `reps`
+ *           copies of the op in a graph, replays it untimed for 10 ms, then
+ *           takes the median of three replays timed by HIP events on a
+ *           private stream
+ *   best    int32[3] out: the chosen triple; best_us (may be NULL): its
+ *           device time per call in microseconds; tried (may be NULL): the
+ *           number of candidates timed
+ * Synchronises with its private stream; not for use while other work on
+ * the handle is in flight (it changes the schedule, so graphs recorded
+ * before must be recorded again).  On an error the handle keeps the
+ * schedule it had.  Errors: those of pf_set_schedule and pf_graph_create,
+ * PF_EINVAL for bad arguments, PF_ESTATE on a host-only handle. */
+int pf_autotune(pf_grid *g, const pf_op *op, int32_t ncand, const int32_t *cand, int32_t reps, int32_t *best,
+                double *best_us, int32_t *tried);
 
 /* Description of the last error on the calling thread ("" if none).  The
  * string stays valid until the next pf_* call on that thread. */

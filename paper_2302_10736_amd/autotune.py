@@ -19,7 +19,6 @@ import hashlib
 import json
 import os
 import tempfile
-import time
 from typing import Callable, Iterable, Optional, Sequence, Tuple
 
 from . import pf
@@ -113,14 +112,20 @@ def _device_name() -> str:
     return f"{p.name}|{getattr(p, 'gcnArchName', '')}"
 
 
-def device_timer(grid: "pf.Grid", op: str, nstate: int, reps: int = 5, seed: int = 0,
-                 warm_s: float = 0.01, samples: int = 3) -> Callable[[Schedule], float]:
-    """Seconds per call of ``op`` on synthetic states under a given schedule,
-    measured with HIP events around a replayed graph of ``reps`` calls (so
-    the host cost of a call does not hide differences): the median of
-    ``samples`` timed replays, after untimed replays for ``warm_s`` seconds
-    (a tile-size change rebuilds the tables on the host, and the device runs
-    slower for the first milliseconds after idling)."""
+# (op name) -> (pf_op op, method)
+_OP = {"injections_ew": (pf.PF_OP_INJECTIONS, pf.PF_METHOD_ELEMENTWISE),
+       "injections_ybus": (pf.PF_OP_INJECTIONS, pf.PF_METHOD_YBUS),
+       "jacobian_ew": (pf.PF_OP_JACOBIAN, pf.PF_METHOD_ELEMENTWISE),
+       "jacobian_ybus": (pf.PF_OP_JACOBIAN, pf.PF_METHOD_YBUS),
+       "jacobian_ew_csc": (pf.PF_OP_JACOBIAN, pf.PF_METHOD_ELEMENTWISE | pf.PF_JAC_CSC),
+       "jacobian_ybus_csc": (pf.PF_OP_JACOBIAN, pf.PF_METHOD_YBUS | pf.PF_JAC_CSC),
+       "vjp": (pf.PF_OP_VJP, pf.PF_METHOD_ELEMENTWISE)}
+
+
+def synthetic_op(grid: "pf.Grid", op: str, nstate: int, seed: int = 0) -> dict:
+    """``op`` on seeded synthetic device buffers (states v ~ 1 + U(-0.025,
+    0.025), theta ~ N(0, 0.2), adjoint seeds ~ N(0, 1)), as a dict for
+    pf_graph_create / pf_autotune."""
     import torch
     if op not in OPS:
         raise ValueError(f"unknown op {op!r}")
@@ -129,66 +134,24 @@ def device_timer(grid: "pf.Grid", op: str, nstate: int, reps: int = 5, seed: int
     shape = (nstate, grid.nb)
     vm = (1.0 + 0.05 * (torch.rand(shape, generator=g, dtype=torch.float64) - 0.5)).to(dev)
     va = (0.2 * torch.randn(shape, generator=g, dtype=torch.float64)).to(dev)
-    lp = torch.randn(shape, generator=g, dtype=torch.float64).to(dev)
-    lq = torch.randn(shape, generator=g, dtype=torch.float64).to(dev)
-    a, b = torch.empty_like(vm), torch.empty_like(vm)
-    j = torch.empty((nstate, grid.nnz_j), dtype=torch.float64, device=dev) if op.startswith("jacobian") else None
-    side = torch.cuda.Stream()
-
-    def call(st):
-        if op == "injections_ew":
-            pf.pf_injections_elementwise(grid, vm, va, a, b, stream=st)
-        elif op == "injections_ybus":
-            pf.pf_injections_ybus(grid, vm, va, a, b, stream=st)
-        elif op == "jacobian_ew":
-            pf.pf_jacobian_values(grid, pf.PF_METHOD_ELEMENTWISE, vm, va, a, b, j, stream=st)
-        elif op == "jacobian_ybus":
-            pf.pf_jacobian_values(grid, pf.PF_METHOD_YBUS, vm, va, a, b, j, stream=st)
-        elif op == "jacobian_ew_csc":
-            pf.pf_jacobian_values(grid, pf.PF_METHOD_ELEMENTWISE | pf.PF_JAC_CSC, vm, va, a, b, j, stream=st)
-        elif op == "jacobian_ybus_csc":
-            pf.pf_jacobian_values(grid, pf.PF_METHOD_YBUS | pf.PF_JAC_CSC, vm, va, a, b, j, stream=st)
-        else:
-            pf.pf_injections_vjp(grid, vm, va, lp, lq, a, b, stream=st)
-
-    def measure(sched: Schedule) -> float:
-        grid.set_schedule(*sched)
-        with torch.cuda.stream(side):
-            call(side)
-        torch.cuda.synchronize()
-        gr = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(gr, stream=side):
-            for _ in range(reps):
-                call(side)
-        torch.cuda.synchronize()
-        tw = time.perf_counter()
-        while True:
-            with torch.cuda.stream(side):
-                gr.replay()
-            torch.cuda.synchronize()
-            if time.perf_counter() - tw >= warm_s:
-                break
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        ts = []
-        for _ in range(max(1, samples)):
-            with torch.cuda.stream(side):
-                e0.record(side)
-                gr.replay()
-                e1.record(side)
-            torch.cuda.synchronize()
-            ts.append(e0.elapsed_time(e1) / 1e3 / reps)
-        return sorted(ts)[len(ts) // 2]
-
-    return measure
+    o, m = _OP[op]
+    d = dict(op=o, method=m, vm=vm, va=va, out_a=torch.empty_like(vm), out_b=torch.empty_like(vm))
+    if o == pf.PF_OP_VJP:
+        d["lam_p"] = torch.randn(shape, generator=g, dtype=torch.float64).to(dev)
+        d["lam_q"] = torch.randn(shape, generator=g, dtype=torch.float64).to(dev)
+    if o == pf.PF_OP_JACOBIAN:
+        d["jval"] = torch.empty((nstate, grid.nnz_j), dtype=torch.float64, device=dev)
+    return d
 
 
 def tune(grid: "pf.Grid", op: str, nstate: int, *, cache: Optional[ScheduleCache] = None,
          measure: Optional[Callable[[Schedule], float]] = None, cands: Optional[Iterable[Schedule]] = None,
          device: Optional[str] = None, lib: Optional[str] = None, save: bool = True) -> dict:
     """Time every candidate schedule, keep the fastest on ``grid`` and record
-    it in the cache.  Returns {"schedule", "us", "tried", "key"}.
-    ``measure(schedule) -> seconds`` defaults to :func:`device_timer`."""
+    it in the cache.  Returns {"schedule", "us", "tried", "key"}.  By default
+    the library's native tuner (pf_autotune) times the candidates on seeded
+    synthetic states (:func:`synthetic_op`); ``measure(schedule) -> seconds``
+    replaces it (host-side tests)."""
     cache = cache if cache is not None else ScheduleCache()
     device = device if device is not None else _device_name()
     lib = lib if lib is not None else library_id()
@@ -196,17 +159,20 @@ def tune(grid: "pf.Grid", op: str, nstate: int, *, cache: Optional[ScheduleCache
     cands = list(cands) if cands is not None else candidates(nstate)
     if not cands:
         raise ValueError("no candidate schedules")
-    measure = measure if measure is not None else device_timer(grid, op, nstate)
-    best, best_t = None, float("inf")
-    for c in cands:
-        t = measure(c)
-        if t < best_t:
-            best, best_t = c, t
-    grid.set_schedule(*best)
-    cache.put(key, best, best_t * 1e6, len(cands))
+    if measure is None:
+        best, best_us, tried = pf.pf_autotune(grid, synthetic_op(grid, op, nstate), cands)
+    else:
+        best, best_t = None, float("inf")
+        for c in cands:
+            t = measure(c)
+            if t < best_t:
+                best, best_t = c, t
+        grid.set_schedule(*best)
+        best_us, tried = best_t * 1e6, len(cands)
+    cache.put(key, best, best_us, tried)
     if save:
         cache.save()
-    return {"schedule": best, "us": best_t * 1e6, "tried": len(cands), "key": key}
+    return {"schedule": tuple(best), "us": best_us, "tried": tried, "key": key}
 
 
 def apply(grid: "pf.Grid", op: str, nstate: int, *, cache: Optional[ScheduleCache] = None,

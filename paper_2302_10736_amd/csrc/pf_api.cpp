@@ -10,6 +10,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -957,7 +958,13 @@ int run(const pf_grid *g, pf::Launch &L, void *stream) {
     L.tile_items = g->tile_items;
     L.has_parallel = g->has_parallel;
     L.states_per_block = auto_states_per_block(g, L.kind, L.nstate);
-    L.state_major = g->order != PF_ORDER_TILE_MAJOR;  // automatic = state-major (one state's J written together)
+    // Automatic order: state-major for Jacobian launches (the tiles of one
+    // state write neighbouring parts of J together), tile-major for
+    // injections and the adjoint (the state chunks of one tile run on one
+    // XCD, so its tables come from that XCD's L2 after the first chunk).
+    const bool with_j = L.kind == pf::K_EW_SJ || L.kind == pf::K_YB_SJ || L.kind == pf::K_EW_SJ_CSC ||
+                        L.kind == pf::K_YB_SJ_CSC;
+    L.state_major = g->order == PF_ORDER_AUTO ? with_j : g->order == PF_ORDER_STATE_MAJOR;
     if (L.nstate == 0) return PF_OK;
     int cur = -1;
     hipError_t e = hipGetDevice(&cur);
@@ -1330,6 +1337,118 @@ void pf_graph_free(pf_graph *gr) {
     if (gr->exec) (void)hipGraphExecDestroy(gr->exec);
     if (gr->graph) (void)hipGraphDestroy(gr->graph);
     delete gr;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- autotuner
+
+namespace {
+
+// Time per call (microseconds) of `op` under the handle's current schedule:
+// a graph of `reps` copies of the op replayed untimed for warm_ms, then the
+// median over `samples` replays timed by HIP events on stream `st`.
+int time_op(const pf_grid *g, const pf_op &op, int32_t reps, hipStream_t st, hipEvent_t e0, hipEvent_t e1,
+            double *us) {
+    std::vector<pf_op> ops(reps, op);
+    pf_graph *gr = nullptr;
+    int rc = pf_graph_create(g, ops.data(), reps, &gr);
+    if (rc) return rc;
+    constexpr double warm_ms = 10.0;
+    constexpr int samples = 3;
+    const auto t0 = std::chrono::steady_clock::now();
+    hipError_t e = hipSuccess;
+    do {
+        rc = pf_graph_launch(gr, st);
+        if (rc) break;
+        e = hipStreamSynchronize(st);
+        if (e != hipSuccess) break;
+    } while (std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count() < warm_ms);
+    double t[samples];
+    for (int k = 0; k < samples && !rc && e == hipSuccess; ++k) {
+        e = hipEventRecord(e0, st);
+        if (e == hipSuccess) rc = pf_graph_launch(gr, st);
+        if (!rc && e == hipSuccess) e = hipEventRecord(e1, st);
+        if (!rc && e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (!rc && e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        t[k] = 1e3 * (double)ms / reps;
+    }
+    pf_graph_free(gr);
+    if (rc) return rc;
+    if (e != hipSuccess) return hip_fail(e, "autotuner timing");
+    std::sort(t, t + samples);
+    *us = t[samples / 2];
+    return PF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pf_autotune(pf_grid *g, const pf_op *op, int32_t ncand, const int32_t *cand, int32_t reps, int32_t *best,
+                double *best_us, int32_t *tried) {
+    g_err.clear();
+    if (!g || !op || !best) return fail(PF_EINVAL, "NULL handle, op or output");
+    if (g->host_only) return fail(PF_ESTATE, "handle was built with PF_BUILD_HOST_ONLY");
+    if (ncand < 0 || (ncand > 0 && !cand)) return fail(PF_EINVAL, "ncand < 0, or candidates missing");
+    if (reps < 1 || reps > 1000) return fail(PF_EINVAL, "reps must lie in [1, 1000]");
+    if (op->nstate < 1) return fail(PF_EINVAL, "the op needs at least one state");
+    std::vector<int32_t> c;
+    try {
+        if (ncand > 0) {
+            c.assign(cand, cand + 3 * (size_t)ncand);
+        } else {
+            const int32_t tiles[4] = {64, 128, 256, 512};
+            const int32_t spbs[8] = {0, 1, 2, 4, 8, 16, 32, 64};
+            for (int32_t t : tiles) {
+                if (op->nstate == 1) {
+                    c.insert(c.end(), {t, 1, PF_ORDER_TILE_MAJOR});
+                    continue;
+                }
+                for (int32_t s : spbs)
+                    if (s <= op->nstate)
+                        for (int32_t o : {PF_ORDER_TILE_MAJOR, PF_ORDER_STATE_MAJOR}) c.insert(c.end(), {t, s, o});
+            }
+        }
+    } catch (const std::bad_alloc &) {
+        return fail(PF_ENOMEM, "host allocation failed");
+    }
+    const int32_t n = (int32_t)(c.size() / 3);
+    const int32_t orig[3] = {g->tile_items, g->states_per_block, g->order};
+    hipStream_t st = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    int rc = e == hipSuccess ? PF_OK : hip_fail(e, "autotuner stream or events");
+    int32_t bi = -1;
+    double bt = 0.0;
+    for (int32_t k = 0; k < n && rc == PF_OK; ++k) {
+        rc = pf_set_schedule(g, c[3 * k], c[3 * k + 1], c[3 * k + 2]);
+        double us = 0.0;
+        if (rc == PF_OK) rc = time_op(g, *op, reps, st, e0, e1, &us);
+        if (rc == PF_OK && (bi < 0 || us < bt)) {
+            bi = k;
+            bt = us;
+        }
+    }
+    std::string err = g_err;
+    if (e1) (void)hipEventDestroy(e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (st) (void)hipStreamDestroy(st);
+    if (rc != PF_OK || bi < 0) {
+        (void)pf_set_schedule(g, orig[0], orig[1], orig[2]);  // back to where the handle started
+        return rc != PF_OK ? fail(rc, err) : fail(PF_EINVAL, "no candidate schedules");
+    }
+    rc = pf_set_schedule(g, c[3 * bi], c[3 * bi + 1], c[3 * bi + 2]);
+    if (rc) return rc;
+    best[0] = c[3 * bi];
+    best[1] = c[3 * bi + 1];
+    best[2] = c[3 * bi + 2];
+    if (best_us) *best_us = bt;
+    if (tried) *tried = n;
+    return PF_OK;
 }
 
 }  // extern "C"

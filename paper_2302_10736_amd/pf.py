@@ -30,7 +30,7 @@ EXPORTS = (
     "pf_build_pattern", "pf_grid_free", "pf_grid_sizes", "pf_pattern_sizes", "pf_grid_offsets",
     "pf_pattern_export", "pf_ybus", "pf_injections_elementwise", "pf_injections_ybus", "pf_jacobian_values",
     "pf_injections_vjp", "pf_jacobian_two_phase_static", "pf_branch_flows", "pf_phasors", "pf_ybus_from_phasors", "pf_jacobian_map", "pf_jacobian_scatter", "pf_set_schedule", "pf_get_schedule", "pf_graph_create", "pf_graph_launch",
-    "pf_graph_free", "pf_stream_copy", "pf_debug_fail_allocs", "pf_last_error", "pf_version",
+    "pf_graph_free", "pf_autotune", "pf_stream_copy", "pf_debug_fail_allocs", "pf_last_error", "pf_version",
 )
 PF_OP_INJECTIONS, PF_OP_JACOBIAN, PF_OP_VJP = 0, 1, 2
 
@@ -86,6 +86,7 @@ def lib() -> C.CDLL:
         L.pf_graph_launch.argtypes = [P, P]
         L.pf_graph_free.argtypes = [P]
         L.pf_graph_free.restype = None
+        L.pf_autotune.argtypes = [P, P, i32, P, i32, P, P, P]
         L.pf_get_schedule.argtypes = [P, P, P, P, P]
         L.pf_last_error.restype = C.c_char_p
         L.pf_last_error.argtypes = []
@@ -396,6 +397,40 @@ def pf_version() -> str:
     return lib().pf_version().decode()
 
 
+def _pf_op(grid: "Grid", o: dict):
+    """A ``pf_op`` structure from a dict (keys of :class:`Graph`'s ops) and the
+    tensors it refers to."""
+    vm = o["vm"]
+    ns = _nstate(vm, grid.nb)
+    shp = tuple(vm.shape)
+    jshp = (grid.nnz_j,) if vm.dim() == 1 else (ns, grid.nnz_j)
+    r = PfOp()
+    r.op = int(o["op"])
+    r.method = int(o.get("method", PF_METHOD_ELEMENTWISE))
+    r.nstate = ns
+    r.vm = _dev(vm, shp, "vm")
+    r.va = _dev(o["va"], shp, "va")
+    for name in ("lam_p", "lam_q", "out_a", "out_b"):
+        setattr(r, name, _dev(o.get(name), shp, name))
+    r.jval = _dev(o.get("jval"), jshp, "jval")
+    return r, [v for v in o.values() if not isinstance(v, int)]
+
+
+def pf_autotune(grid: "Grid", op: dict, cands=None, reps: int = 5):
+    """Native schedule autotuner: times candidate schedules of ``op`` (a dict
+    as in :class:`Graph`; its outputs are overwritten) and leaves the fastest
+    on ``grid``.  ``cands``: (tile_items, states_per_block, order) triples or
+    None for the library's default set.  Returns (schedule, us, tried)."""
+    r, keep = _pf_op(grid, op)
+    c = None if not cands else np.ascontiguousarray(np.asarray(cands, dtype=np.int32).reshape(-1, 3))
+    best = np.zeros(3, np.int32)
+    us, tried = C.c_double(), C.c_int32()
+    check(lib().pf_autotune(grid.handle, C.byref(r), 0 if c is None else len(c), _hp(c), int(reps), _hp(best),
+                            C.byref(us), C.byref(tried)))
+    del keep
+    return (int(best[0]), int(best[1]), int(best[2])), us.value, tried.value
+
+
 class Graph:
     """Owner of a ``pf_graph`` (pf_graph_create / pf_graph_launch / pf_graph_free).
 
@@ -410,19 +445,8 @@ class Graph:
         arr = (PfOp * len(ops))()
         keep = [grid]
         for k, o in enumerate(ops):
-            vm = o["vm"]
-            ns = _nstate(vm, grid.nb)
-            shp = tuple(vm.shape)
-            jshp = (grid.nnz_j,) if vm.dim() == 1 else (ns, grid.nnz_j)
-            arr[k].op = int(o["op"])
-            arr[k].method = int(o.get("method", PF_METHOD_ELEMENTWISE))
-            arr[k].nstate = ns
-            arr[k].vm = _dev(vm, shp, "vm")
-            arr[k].va = _dev(o["va"], shp, "va")
-            for name in ("lam_p", "lam_q", "out_a", "out_b"):
-                setattr(arr[k], name, _dev(o.get(name), shp, name))
-            arr[k].jval = _dev(o.get("jval"), jshp, "jval")
-            keep += [v for v in o.values() if not isinstance(v, int)]
+            arr[k], kp = _pf_op(grid, o)
+            keep += kp
         self._h = C.c_void_p()
         check(lib().pf_graph_create(grid.handle, arr, len(ops), C.byref(self._h)))
         self._keep = keep

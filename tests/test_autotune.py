@@ -77,3 +77,47 @@ def test_tune_on_device_keeps_results(tmp_path):
     pf.pf_jacobian_values(G, pf.PF_METHOD_ELEMENTWISE, vm, va, p1, q1, j1)
     torch.cuda.synchronize()
     assert torch.equal(j0, j1) and torch.equal(p0, p1) and torch.equal(q0, q1)
+
+
+def test_native_tuner_argument_checks():
+    """pf_autotune rejects bad arguments on the host (CPU, host-only handle)."""
+    import ctypes as C
+    G = pf.Grid.from_grid(_grids.random_small(10, 12, 1), host_only=True)
+    L = pf.lib()
+    best = (C.c_int32 * 3)()
+    op = pf.PfOp()
+    op.op, op.method, op.nstate = pf.PF_OP_JACOBIAN, pf.PF_METHOD_ELEMENTWISE, 1
+    assert L.pf_autotune(None, C.byref(op), 0, None, 5, best, None, None) == pf.PF_EINVAL
+    assert L.pf_autotune(G.handle, None, 0, None, 5, best, None, None) == pf.PF_EINVAL
+    assert L.pf_autotune(G.handle, C.byref(op), 0, None, 5, best, None, None) == pf.PF_ESTATE
+
+
+@pytest.mark.gpu
+def test_native_tuner_default_and_given_candidates():
+    """pf_autotune through the C ABI: it times the default candidate set (one
+    state) and a caller's list (several states), leaves the best schedule on
+    the handle, and the results stay bit for bit what they were."""
+    import torch
+    from tests._gpu import to_dev
+    g = gridgen.grid_500()
+    G = pf.Grid.from_grid(g)
+    rng = np.random.default_rng(9)
+    for ns, cands in ((1, None), (5, [(128, 2, pf.PF_ORDER_TILE_MAJOR), (256, 0, pf.PF_ORDER_STATE_MAJOR),
+                                      (64, 5, pf.PF_ORDER_TILE_MAJOR)])):
+        vm, va = to_dev(rng.uniform(0.95, 1.05, (ns, g.nb))), to_dev(rng.normal(0, 0.2, (ns, g.nb)))
+        z = lambda *s: torch.zeros(*s, dtype=torch.float64, device="cuda:0")
+        p0, q0, j0 = z(ns, g.nb), z(ns, g.nb), z(ns, G.nnz_j)
+        pf.pf_jacobian_values(G, pf.PF_METHOD_ELEMENTWISE, vm, va, p0, q0, j0)
+        torch.cuda.synchronize()
+        a, b, j = z(ns, g.nb), z(ns, g.nb), z(ns, G.nnz_j)
+        op = dict(op=pf.PF_OP_JACOBIAN, method=pf.PF_METHOD_ELEMENTWISE, vm=vm, va=va, out_a=a, out_b=b, jval=j)
+        best, us, tried = pf.pf_autotune(G, op, cands, reps=3)
+        assert tried == (len(autotune.TILES) if cands is None else len(cands)) and us > 0
+        assert G.schedule()[:3] == best
+        if cands is not None:
+            assert best in cands
+        assert torch.equal(j, j0) and torch.equal(a, p0) and torch.equal(b, q0)
+        p1, q1, j1 = z(ns, g.nb), z(ns, g.nb), z(ns, G.nnz_j)
+        pf.pf_jacobian_values(G, pf.PF_METHOD_ELEMENTWISE, vm, va, p1, q1, j1)
+        torch.cuda.synchronize()
+        assert torch.equal(j1, j0) and torch.equal(p1, p0)
