@@ -453,6 +453,9 @@ def main():
         q = np.percentile(rep_us, [10, 50, 90])
         extra["headline_repeats"] = {"repeats": 20, "launches_each": 10 * R, "p10_us": q[0], "median_us": q[1],
                                      "p90_us": q[2]}
+        # the same launch over long replay windows, beside the timed steps' figure
+        out["roofline"]["median_launch_us"] = q[1]
+        out["roofline"]["frac_at_median"] = abytes / (q[1] * 1e-6) / 1e9 / HBM_PEAK_GBS
         log(f"headline repeats: p10 {q[0]:.2f} median {q[1]:.2f} p90 {q[2]:.2f} us")
 
     if want("ybus"):

@@ -84,3 +84,35 @@ def test_static_scratch_limits_and_arguments():
     j2 = torch.empty(1, G2.nnz_j, dtype=torch.float64, device="cuda:0")
     assert _static_call(G2, pf.PF_METHOD_ELEMENTWISE, vm2, vm2, None, None, j2) == pf.PF_EINVAL
     assert _static_call(G2, pf.PF_METHOD_ELEMENTWISE_TWO_PHASE, vm2, vm2, vm2, None, j2) == pf.PF_EINVAL
+
+
+def test_static_scratch_under_graph_capture():
+    """The allocation-free entry point recorded in a captured HIP graph (torch
+    capture of the library's launches on the capturing stream) and replayed
+    several times with eager work and input changes in between: every replay
+    equals the eager call bit for bit."""
+    import torch
+    g = gridgen.grid_500()
+    G = pf.Grid.from_grid(g)
+    vm_h, va_h = gridgen.states(g.nb, 3, case=0)
+    vm, va = to_dev(vm_h), to_dev(va_h)
+    p, q = torch.empty_like(vm), torch.empty_like(vm)
+    j = torch.empty(3, G.nnz_j, dtype=torch.float64, device="cuda:0")
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        pf.pf_jacobian_two_phase_static(G, pf.PF_METHOD_ELEMENTWISE_TWO_PHASE, vm, va, p, q, j, stream=side)
+    torch.cuda.synchronize()
+    gr = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(gr, stream=side):
+        pf.pf_jacobian_two_phase_static(G, pf.PF_METHOD_ELEMENTWISE_TWO_PHASE, vm, va, p, q, j, stream=side)
+    for rep in range(3):
+        j.fill_(float("nan"))
+        with torch.cuda.stream(side):
+            gr.replay()
+        torch.cuda.synchronize()
+        p2, q2, j2 = torch.empty_like(p), torch.empty_like(q), torch.empty_like(j)
+        pf.pf_jacobian_values(G, pf.PF_METHOD_ELEMENTWISE_TWO_PHASE, vm, va, p2, q2, j2)
+        torch.cuda.synchronize()
+        assert torch.equal(j, j2) and torch.equal(p, p2) and torch.equal(q, q2), rep
+        vm.mul_(1.01)
+        va.add_(0.02)
