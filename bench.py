@@ -49,7 +49,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 WARM_S = 0.05  # untimed replays before every timed region, seconds
 # sources that decide the headline kernel's memory traffic (kernels and lane-table layout)
-KERNEL_SRCS = [os.path.join(ROOT, "paper_2302_10736_amd", "csrc", f) for f in ("pf_kernels.hip", "pf_api.cpp")]
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2302_10736_amd", "csrc", f)
+               for f in ("pf_kernels.hip", "pf_math.h", "pf_internal.h", "pf_api.cpp")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_ew_100k_1state_traffic.json")
 HEADLINE_KERNEL = "k_ew<256, false, true, true>"  # element-wise S+J, one state per workgroup
 COPY_PROBE_DOUBLES = 4 * 1024 * 1024  # 32 MiB read + 32 MiB written by the calibration copy

@@ -71,7 +71,17 @@ namespace {
 
 constexpr int kXcds = 8;
 
-__device__ __forceinline__ void sincos_dev(double x, double *s, double *c) { sincos_rad(x, s, c, g_sincos); }
+// sincos_rad, with its reduction and quadrant fix-up skipped when every lane
+// of the wave has quadrant count 0 (angle differences within about pi/4, the
+// usual case in power-flow states).  Same bits either way (pf_math.h), so a
+// record's result does not depend on which lanes share its wave.
+__device__ __forceinline__ void sincos_dev(double x, double *s, double *c) {
+    if (__builtin_amdgcn_ballot_w64(sincos_quadrant(x) != 0.0) == 0) {
+        sincos_series(x, s, c, g_sincos);
+        return;
+    }
+    sincos_rad(x, s, c, g_sincos);
+}
 
 // Workgroups are dispatched round-robin over the 8 XCDs.  Give each XCD a
 // contiguous range of work items so that neighbouring tiles, and all state

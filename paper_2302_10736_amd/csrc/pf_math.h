@@ -46,8 +46,30 @@ inline constexpr SinCosCoef kSinCosTaylor = {
      -4.1666666666666666667e-02,    // -1/4!
      5.0000000000000000000e-01}};   // 1/2!
 
+// Quadrant count of the reduction: x * 2/pi rounded to the nearest integer.
+__host__ __device__ inline double sincos_quadrant(double x) {
+    constexpr double kTwoOverPi = 0.63661977236758134308;  // 2/pi
+    return rint(x * kTwoOverPi);
+}
+
+// The two series on a reduced argument r (|r| <= pi/4 + a rounding error).
+__host__ __device__ inline void sincos_series(double r, double *s, double *c, const SinCosCoef &k) {
+    const double z = r * r;
+    double ps = k.s[0];
+    for (int q = 1; q < 8; ++q) ps = fma(ps, z, k.s[q]);
+    *s = fma(ps * z, r, r);
+    double pc = k.c[0];
+    for (int q = 1; q < 9; ++q) pc = fma(pc, z, k.c[q]);
+    *c = fma(-pc, z, 1.0);
+}
+
 // `k` is kSinCosTaylor itself on the host; device code passes a copy held in
 // constant memory, so the coefficients are scalar operands of the FMAs.
+//
+// With quadrant count n = 0 the reduction leaves x unchanged (a zero becomes
+// +0, and the series maps either zero to sine +0 and cosine 1) and the
+// fix-up below is the identity, so sincos_rad(x) has the bits of
+// sincos_series(x) there; the kernels take that shortcut for whole waves.
 __host__ __device__ inline void sincos_rad(double x, double *s, double *c, const SinCosCoef &k) {
     const double ax = fabs(x);
     if (!(ax < 131072.0)) {  // also catches NaN and infinities
@@ -55,19 +77,13 @@ __host__ __device__ inline void sincos_rad(double x, double *s, double *c, const
         *c = ::cos(x);
         return;
     }
-    constexpr double kTwoOverPi = 0.63661977236758134308;   // 2/pi
-    constexpr double kPio2Hi = 1.5707963267948966192;       // pi/2 rounded to double
-    constexpr double kPio2Lo = 6.123233995736766036e-17;    // pi/2 - kPio2Hi
-    const double n = rint(x * kTwoOverPi);
+    constexpr double kPio2Hi = 1.5707963267948966192;     // pi/2 rounded to double
+    constexpr double kPio2Lo = 6.123233995736766036e-17;  // pi/2 - kPio2Hi
+    const double n = sincos_quadrant(x);
     double r = fma(-n, kPio2Hi, x);
     r = fma(-n, kPio2Lo, r);
-    const double z = r * r;
-    double ps = k.s[0];
-    for (int q = 1; q < 8; ++q) ps = fma(ps, z, k.s[q]);
-    const double sr = fma(ps * z, r, r);
-    double pc = k.c[0];
-    for (int q = 1; q < 9; ++q) pc = fma(pc, z, k.c[q]);
-    const double cr = fma(-pc, z, 1.0);
+    double sr, cr;
+    sincos_series(r, &sr, &cr, k);
     const int qd = static_cast<int>(n) & 3;  // |n| < 2^17 here, so the conversion is exact
     const double so = (qd & 1) ? cr : sr;
     const double co = (qd & 1) ? sr : cr;

@@ -140,11 +140,19 @@ def test_determinism_across_runs_and_schedules():
     g = _grids.random_small(900, 1600, 33, parallel=12, isolated=5)
     vm, va = _grids.random_state(g.nb, 6)
     rng = np.random.default_rng(2)
-    vm = np.stack([vm, rng.uniform(0.9, 1.1, g.nb), rng.uniform(0.9, 1.1, g.nb)])
-    va = np.stack([va, rng.normal(0, 0.3, g.nb), rng.normal(0, 0.3, g.nb)])
+    # the last two states keep every angle difference within pi/4 (whole
+    # waves take the sine/cosine shortcut) except at 1 % of the buses, so a
+    # record's wave takes the shortcut under some tile sizes and not others
+    small = rng.normal(0, 0.01, (2, g.nb))
+    small[1, rng.choice(g.nb, g.nb // 100, replace=False)] = rng.uniform(1.0, 3.0, g.nb // 100)
+    vm = np.stack([vm, rng.uniform(0.9, 1.1, g.nb), rng.uniform(0.9, 1.1, g.nb), rng.uniform(0.95, 1.05, g.nb),
+                   rng.uniform(0.95, 1.05, g.nb)])
+    va = np.stack([va, rng.normal(0, 0.3, g.nb), rng.normal(0, 0.3, g.nb), small[0], small[1]])
     lp, lq = rng.normal(size=vm.shape), rng.normal(size=vm.shape)
     G = pf.Grid.from_grid(g)
     ref = gpu_all(G, vm, va, lp, lq)
+    for s in range(vm.shape[0]):
+        compare_grid(ref, oracle_all(g, vm[s], va[s], lp[s], lq[s]), s, slice(None), slice(None), slice(None))
     # every method but copy-add (atomic adds in no fixed order) is bitwise reproducible
     fixed = [k for k in ref if not k.endswith("_ca")]
     for _ in range(3):

@@ -1,5 +1,7 @@
 """The kernels' sine/cosine (pf_math.h), compiled for the host from the same
-source, against 80-bit sinl/cosl over many argument ranges."""
+source, against 80-bit sinl/cosl over many argument ranges; and the kernels'
+wave-wide shortcut for quadrant count 0 (the series alone on x),
+which must reproduce the full function's bits."""
 import os
 import subprocess
 
@@ -17,6 +19,9 @@ def test_sincos_accuracy(tmp_path):
                     "-o", str(exe)], check=True, capture_output=True)
     out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
     max_abs, max_ulp, n = float(out[0]), float(out[1]), int(out[2])
+    n0, n0_diff = int(out[3]), int(out[4])
     assert n > 2_000_000
+    assert n0 > 400_000, n0
+    assert n0_diff == 0, n0_diff
     assert max_abs <= 3.0e-16, max_abs   # absolute, results in [-1, 1]
     assert max_ulp <= 2.5, max_ulp       # relative where |result| >= 2^-10
