@@ -168,13 +168,15 @@ def test_determinism_across_runs_and_schedules():
                     assert np.array_equal(ref[k], other[k]), (k, tile, spb, order)
 
 
-@pytest.mark.parametrize("n_leaf,parallel", [(40, 0), (100, 3), (333, 0), (700, 25)])
+@pytest.mark.parametrize("n_leaf,parallel", [(40, 0), (100, 3), (256, 0), (250, 6), (333, 0), (700, 25)])
 def test_hub_rows_bitwise_across_schedules(n_leaf, parallel):
     """Bus sums run in chunks of 32 terms fixed by the row alone, so a hub row
     gives the same bits whether its tile packs it (tile size above its branch
     ends) or walks it in pieces of the tile size (the long-row path), for
     every tile size and states per workgroup; every run matches the oracle.
-    The hub sits mid-numbering, so its bus-shunt record lies inside its row."""
+    The hub sits mid-numbering, so its bus-shunt record lies inside its row.
+    256 branch ends (with and without parallel branches) fill whole pieces of
+    64 and 128 exactly."""
     g = star_grid(n_leaf, seed=n_leaf, parallel=parallel)
     perm = np.arange(g.nb)
     perm[0], perm[g.nb // 2] = g.nb // 2, 0
