@@ -1035,16 +1035,23 @@ __global__ void __launch_bounds__(NT)
     struct In {
         double vj, tj, lpj, lqj, vr, tr, lpr, lqr;
     };
+    // Only waves that hold a row load the row values (uniform per wave, so
+    // the other waves skip four loads per state; their values are unused).
+    const bool anyrow = (k & ~63) < c.nrows;
     auto load = [&](int s, In &in) {
         const size_t so = (size_t)s * nb;
         in.vj = vm[so + j];
         in.tj = va[so + j];
         in.lpj = lp[so + j];
         in.lqj = lq[so + j];
-        in.vr = vm[so + ir];
-        in.tr = va[so + ir];
-        in.lpr = lp[so + ir];
-        in.lqr = lq[so + ir];
+        if (anyrow) {
+            in.vr = vm[so + ir];
+            in.tr = va[so + ir];
+            in.lpr = lp[so + ir];
+            in.lqr = lq[so + ir];
+        } else {
+            in.vr = in.tr = in.lpr = in.lqr = 0.0;
+        }
     };
     In first;
     load(sb, first);
