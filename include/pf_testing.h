@@ -14,8 +14,10 @@ extern "C" {
 #endif
 
 /* A streaming device copy of n doubles from src to dst (DEVICE buffers,
- * 16-byte aligned, not overlapping), 16-byte loads and streaming stores over
- * a grid-stride loop.  A copy moves its bytes with no dependent loads, so at
+ * 16-byte aligned, not overlapping): 16-byte loads, then 16-byte streaming
+ * stores, two pairs of doubles per thread up to 8M pairs and one above (the
+ * faster pattern at each size), one workgroup per chunk of the buffers.  A
+ * copy moves its bytes with no dependent loads, so at
  * a given byte count it is the practical bandwidth ceiling for a kernel that
  * reads half and writes half of those bytes; the benchmark times it beside
  * the evaluation kernels.  One launch on `stream`.  Errors: PF_EINVAL

@@ -309,9 +309,10 @@ def test_variants_grid_100k_full_size():
         assert np.array_equal(r["j1"], r["j0"]) and np.array_equal(r["p2"], r["ps"])
 
 
-@pytest.mark.parametrize("n", [1, 2, 3, 1001, (1 << 20) + 1, 5_000_000])
+@pytest.mark.parametrize("n", [1, 2, 3, 1001, (1 << 20) + 1, 5_000_000, (16 << 20) + 5])
 def test_stream_copy(n):
-    """The bandwidth probe copies every element, odd lengths included."""
+    """The bandwidth probe copies every element, odd lengths included, with
+    two pairs of doubles per thread and (past 8M pairs) one."""
     import torch
     src = torch.randn(n + 2, dtype=torch.float64, device="cuda:0")[:n]  # the first n of a larger buffer
     dst = torch.full((n + 2,), float("nan"), dtype=torch.float64, device="cuda:0")
