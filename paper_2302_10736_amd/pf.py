@@ -5,7 +5,7 @@ Every function mirrors the C entry point of the same name in
 Device arrays are ``torch`` float64 CUDA tensors (PyTorch provides device
 memory and streams only); ``stream=None`` means torch's current stream.
 The library must be built (``python -m paper_2302_10736_amd.build``):
-importing this module without it raises, there is no fallback.
+without it the first call raises ImportError; there is no fallback.
 """
 from __future__ import annotations
 
