@@ -110,6 +110,19 @@ def traffic_from_csv(fetch_csv, write_csv):
     return res
 
 
+def recorded_traffic(path=TRAFFIC_FILE):
+    """Counter-measured HBM bytes per launch of the headline kernel from the
+    file `--traffic` wrote, or None when there is none or it was taken for
+    other kernel sources (its hash differs from kernel_hash())."""
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("kernel_sha256_16") != kernel_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
 def algorithmic_bytes(nb, nl, nnz_y, nstate, with_j=True, method="ew", vjp=False):
     """Bytes the method must move: state in/out, problem data once, outputs.
 
@@ -409,11 +422,7 @@ def main():
         f"wall {wall_s / K * 1e6:.2f} us/step")
 
     # traffic measured by rocprofv3 counters for this exact kernel source, if recorded
-    traffic = None
-    if os.path.exists(TRAFFIC_FILE):
-        t = json.load(open(TRAFFIC_FILE))
-        if t.get("kernel_sha256_16") == kernel_hash():
-            traffic = t.get("bytes_per_launch")
+    traffic = recorded_traffic()
 
     out = {
         "metric": "S+Jacobian evals/s at 100k buses, % HBM peak; batched & adjoint vs plain",

@@ -59,6 +59,17 @@ def test_traffic_from_counter_files(tmp_path):
     assert r["kernel_sha256_16"] == bench.kernel_hash()
 
 
+def test_recorded_traffic_needs_the_same_kernel_sources(tmp_path):
+    import json
+    good = tmp_path / "t.json"
+    good.write_text(json.dumps({"kernel_sha256_16": bench.kernel_hash(), "bytes_per_launch": 123.0}))
+    assert bench.recorded_traffic(str(good)) == 123.0
+    stale = tmp_path / "s.json"
+    stale.write_text(json.dumps({"kernel_sha256_16": "0" * 16, "bytes_per_launch": 123.0}))
+    assert bench.recorded_traffic(str(stale)) is None
+    assert bench.recorded_traffic(str(tmp_path / "missing.json")) is None
+
+
 def test_more_than_one_gpu_is_refused():
     p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=120)
