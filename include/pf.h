@@ -305,17 +305,23 @@ int pf_jacobian_scatter(const pf_grid *g, int32_t nstate, const double *jval, co
  *                     workgroups: PF_ORDER_TILE_MAJOR (the state chunks of
  *                     one tile are adjacent), PF_ORDER_STATE_MAJOR (the tiles
  *                     of one state chunk are adjacent, so concurrent
- *                     workgroups write neighbouring parts of J) or
- *                     PF_ORDER_AUTO (state-major for Jacobian launches,
- *                     tile-major for injections and the adjoint, whose state
- *                     chunks of one tile then share an L2)
+ *                     workgroups write neighbouring parts of J),
+ *                     PF_ORDER_GROUPED (each of the 8 XCDs owns an eighth
+ *                     of the tiles and walks them chunk by chunk: the tiles'
+ *                     tables stay in its L2 while neighbouring workgroups
+ *                     write neighbouring parts of J) or PF_ORDER_AUTO
+ *                     (Jacobian launches: state-major while the tile tables
+ *                     fit in 2 MB, which then stay in every XCD's L2,
+ *                     grouped above that; injections and the adjoint:
+ *                     tile-major, so the state chunks of one tile share
+ *                     an L2)
  * The initial schedule is tile_items 256 (with several grids per handle:
  * the smallest of 64, 128, 256 that holds the mean branch ends per grid,
  * since tiles never span grids), states_per_block 0, PF_ORDER_AUTO.
  * Changing the schedule never changes results.  Rebuilds the tile list on
  * the host and device; not for use while work on the handle is in flight.
  * Graphs recorded before the call must be recorded again. */
-enum { PF_ORDER_AUTO = 0, PF_ORDER_TILE_MAJOR = 1, PF_ORDER_STATE_MAJOR = 2 };
+enum { PF_ORDER_AUTO = 0, PF_ORDER_TILE_MAJOR = 1, PF_ORDER_STATE_MAJOR = 2, PF_ORDER_GROUPED = 3 };
 int pf_set_schedule(pf_grid *g, int32_t tile_items, int32_t states_per_block, int32_t order);
 /* ntiles: element-wise work tiles of the current schedule. */
 int pf_get_schedule(const pf_grid *g, int32_t *tile_items, int32_t *states_per_block, int32_t *order,
@@ -367,7 +373,7 @@ void pf_graph_free(pf_graph *gr);
  *   ncand, cand  int32[3 ncand] host array of (tile_items, states_per_block,
  *           order) triples, or ncand = 0 for the default set: tile_items in
  *           {64, 128, 256, 512} x states_per_block in {0, 1, 2, 4, 8, 16, 32,
- *           64} up to nstate x both work orders (one state: the four tile
+ *           64} up to nstate x the three work orders (one state: the four tile
  *           sizes, one state per workgroup)
  *   reps    calls per timing in [1, 1000]: each candidate records `reps`
  *           copies of the op in a graph, replays it untimed for 10 ms, then

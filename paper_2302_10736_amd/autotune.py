@@ -36,11 +36,12 @@ def candidates(nstate: int, tiles: Sequence[int] = TILES) -> list:
 
     One state: one workgroup per tile, order irrelevant.  Several states:
     the automatic split (0) and explicit states per workgroup up to nstate,
-    each in both work orders."""
+    each in the three work orders."""
     if nstate <= 1:
         return [(t, 1, pf.PF_ORDER_TILE_MAJOR) for t in tiles]
     spbs = [0] + [s for s in STATES_PER_BLOCK if s <= nstate]
-    return [(t, s, o) for t in tiles for s in spbs for o in (pf.PF_ORDER_TILE_MAJOR, pf.PF_ORDER_STATE_MAJOR)]
+    orders = (pf.PF_ORDER_TILE_MAJOR, pf.PF_ORDER_STATE_MAJOR, pf.PF_ORDER_GROUPED)
+    return [(t, s, o) for t in tiles for s in spbs for o in orders]
 
 
 def default_cache_path() -> str:

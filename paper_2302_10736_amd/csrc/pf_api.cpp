@@ -848,7 +848,8 @@ int pf_set_schedule(pf_grid *g, int32_t tile_items, int32_t states_per_block, in
     if (tile_items != 64 && tile_items != 128 && tile_items != 256 && tile_items != 512)
         return fail(PF_EINVAL, "tile_items must be 64, 128, 256 or 512");
     if (states_per_block < 0) return fail(PF_EINVAL, "states_per_block must be >= 0");
-    if (order != PF_ORDER_AUTO && order != PF_ORDER_TILE_MAJOR && order != PF_ORDER_STATE_MAJOR)
+    if (order != PF_ORDER_AUTO && order != PF_ORDER_TILE_MAJOR && order != PF_ORDER_STATE_MAJOR &&
+        order != PF_ORDER_GROUPED)
         return fail(PF_EINVAL, "unknown order");
     if (tile_items != g->tile_items) {
         // new tiles on the host and device; on failure the old ones stay
@@ -904,22 +905,56 @@ int check_eval(const pf_grid *g, int32_t nstate) {
     return PF_OK;
 }
 
+bool is_jacobian(int kind) {
+    return kind == pf::K_EW_SJ || kind == pf::K_YB_SJ || kind == pf::K_EW_SJ_CSC || kind == pf::K_YB_SJ_CSC;
+}
+
+// Bytes of tile tables a launch walks per state: about 24 per lane and 24
+// per bus.
+int64_t table_bytes(const pf_grid *g, int kind) {
+    const bool yb = kind == pf::K_YB_S || kind == pf::K_YB_SJ || kind == pf::K_YB_SJ_CSC;
+    const int64_t nt = std::max<int64_t>(1, (int64_t)(yb ? g->ytiles : g->tiles).size());
+    return 24 * nt * (int64_t)g->tile_items + 24 * (int64_t)g->nb;
+}
+
+// Work order of a launch (pf::WO_*).  Automatic: for Jacobian launches
+// state-major while the tables fit in one XCD's L2 (2 MB of its 4 MB), so
+// the tiles of a state write neighbouring parts of J together, else grouped
+// (each XCD walks its own eighth of the tiles state by state: their tables
+// stay in its L2 while neighbouring workgroups still write neighbouring J
+// rows); tile-major for injections and the adjoint (the state chunks of one
+// tile run on one XCD, so its tables come from that XCD's L2 after the
+// first chunk).
+int work_order(const pf_grid *g, int kind) {
+    switch (g->order) {
+        case PF_ORDER_TILE_MAJOR:
+            return pf::WO_TILE;
+        case PF_ORDER_STATE_MAJOR:
+            return pf::WO_STATE;
+        case PF_ORDER_GROUPED:
+            return pf::WO_GROUPED;
+        default:
+            if (!is_jacobian(kind)) return pf::WO_TILE;
+            return table_bytes(g, kind) <= ((int64_t)2 << 20) ? pf::WO_STATE : pf::WO_GROUPED;
+    }
+}
+
 // States per workgroup.  A workgroup keeps its tile's record constants in
 // registers and walks its states one after another, so fewer, longer
 // workgroups read the constants fewer times, while more, shorter workgroups
 // keep more of every state's output stream in flight.  The automatic choice
 // takes at most 2 states per workgroup for Jacobian launches (their time is
 // the J stream: 8 nnzJ bytes per state against a few bytes of constants),
-// 1 when the tables are small enough to stay in L2 between states, and at
-// most 8 for injections and the adjoint (small per-state outputs, so reusing
-// the constants pays); fewer when the tiles alone would leave part of one
-// round of resident workgroups empty (it then splits each tile's states into
-// about resident capacity / tiles chunks).
+// 1 when the tables a workgroup's XCD walks stay in its 4 MB L2 between
+// states (an eighth of them in the grouped order, all otherwise), and at
+// most 8 for injections and the adjoint (small
+// per-state outputs, so reusing the constants pays); fewer when the tiles
+// alone would leave part of one round of resident workgroups empty (it then
+// splits each tile's states into about resident capacity / tiles chunks).
 int auto_states_per_block(const pf_grid *g, int kind, int32_t nstate) {
     if (g->states_per_block > 0) return std::min<int32_t>(g->states_per_block, std::max(nstate, 1));
     if (nstate <= 1) return 1;
     const bool yb = kind == pf::K_YB_S || kind == pf::K_YB_SJ || kind == pf::K_YB_SJ_CSC;
-    const bool with_j = kind == pf::K_EW_SJ || kind == pf::K_YB_SJ || kind == pf::K_EW_SJ_CSC || kind == pf::K_YB_SJ_CSC;
     const int64_t nt = std::max<int64_t>(1, (int64_t)(yb ? g->ytiles : g->tiles).size());
     int per_cu = pf::resident_blocks_per_cu(kind, g->tile_items, g->has_parallel);
     if (per_cu <= 0) per_cu = 4;
@@ -927,13 +962,13 @@ int auto_states_per_block(const pf_grid *g, int kind, int32_t nstate) {
     int64_t chunks = std::max<int64_t>(1, capacity / nt);
     chunks = std::min<int64_t>(chunks, nstate);
     const int fill = (int)((nstate + chunks - 1) / chunks);
-    if (with_j) {
+    if (is_jacobian(kind)) {
         // One state per workgroup (the lean single-state kernel) when the
-        // tile tables a state walks (about 24 bytes per lane and per bus)
-        // stay in one XCD's 4 MB L2 across states; else two.
-        const int64_t lanes = nt * (int64_t)g->tile_items;
-        const int64_t table_bytes = 24 * lanes + 24 * (int64_t)g->nb;
-        return std::min(fill, table_bytes <= (int64_t)2 << 20 ? 1 : 2);
+        // tile tables an XCD walks stay in its L2 across states (an eighth
+        // of them in the grouped order); else two.
+        int64_t tb = table_bytes(g, kind);
+        if (work_order(g, kind) == pf::WO_GROUPED) tb /= 8;
+        return std::min(fill, tb <= ((int64_t)2 << 20) ? 1 : 2);
     }
     return std::min(fill, 8);
 }
@@ -958,13 +993,7 @@ int run(const pf_grid *g, pf::Launch &L, void *stream) {
     L.tile_items = g->tile_items;
     L.has_parallel = g->has_parallel;
     L.states_per_block = auto_states_per_block(g, L.kind, L.nstate);
-    // Automatic order: state-major for Jacobian launches (the tiles of one
-    // state write neighbouring parts of J together), tile-major for
-    // injections and the adjoint (the state chunks of one tile run on one
-    // XCD, so its tables come from that XCD's L2 after the first chunk).
-    const bool with_j = L.kind == pf::K_EW_SJ || L.kind == pf::K_YB_SJ || L.kind == pf::K_EW_SJ_CSC ||
-                        L.kind == pf::K_YB_SJ_CSC;
-    L.state_major = g->order == PF_ORDER_AUTO ? with_j : g->order == PF_ORDER_STATE_MAJOR;
+    L.order = work_order(g, L.kind);
     if (L.nstate == 0) return PF_OK;
     int cur = -1;
     hipError_t e = hipGetDevice(&cur);
@@ -1408,7 +1437,8 @@ int pf_autotune(pf_grid *g, const pf_op *op, int32_t ncand, const int32_t *cand,
                 }
                 for (int32_t s : spbs)
                     if (s <= op->nstate)
-                        for (int32_t o : {PF_ORDER_TILE_MAJOR, PF_ORDER_STATE_MAJOR}) c.insert(c.end(), {t, s, o});
+                        for (int32_t o : {PF_ORDER_TILE_MAJOR, PF_ORDER_STATE_MAJOR, PF_ORDER_GROUPED})
+                            c.insert(c.end(), {t, s, o});
             }
         }
     } catch (const std::bad_alloc &) {

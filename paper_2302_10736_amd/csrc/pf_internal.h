@@ -135,11 +135,15 @@ enum Kind { K_EW_S = 0, K_EW_SJ = 1, K_YB_S = 2, K_YB_SJ = 3, K_EW_VJP = 4, K_EW
 // PF_PHASOR_SPLIT and PF_PHASOR_INTERLEAVED).
 enum { PH_FLY = 0, PH_SPLIT = 1, PH_INTERLEAVED = 2 };
 
+// Order of the (tile, state chunk) work items over the workgroups (see
+// work_item in pf_kernels.hip).
+enum { WO_TILE = 0, WO_STATE = 1, WO_GROUPED = 2 };
+
 struct Launch {
     int kind;
     int tile_items;        // workgroup size = records per tile
     int states_per_block;
-    bool state_major;  // work items ordered state chunk first
+    int order;             // WO_*
     int nstate;
     bool has_parallel;
     const double *vm, *va, *lp, *lq;

@@ -92,6 +92,48 @@ __device__ __forceinline__ int work_index(int nblocks) {
     return (b % kXcds) * per + b / kXcds;
 }
 
+// Tiles per XCD in the grouped order.
+__host__ __device__ __forceinline__ int grouped_tiles(int ntiles) { return (ntiles + kXcds - 1) / kXcds; }
+
+// The work item of this workgroup: tile t and state chunk c, or false for a
+// workgroup past the end.
+//   WO_TILE:    item w (work_index), tile w / nchunk, chunk w % nchunk: the
+//               state chunks of a tile are adjacent, on one XCD.
+//   WO_STATE:   tile w % ntiles, chunk w / ntiles: the tiles of a chunk are
+//               adjacent.
+//   WO_GROUPED: XCD x owns tiles [x tx, x tx + tx), tx = ceil(ntiles / 8),
+//               and walks them chunk by chunk (all its tiles for chunk 0,
+//               then for chunk 1, ...): each tile's tables stay in that
+//               XCD's L2 across chunks while consecutive workgroups write
+//               neighbouring rows of one state's outputs.  The grid has
+//               8 tx nchunk workgroups.
+__device__ __forceinline__ bool work_item(int ntiles, int nchunk, int order, int &t, int &c) {
+    if (nchunk == 1) {  // one chunk: every order maps tile = work_index (and the grids agree)
+        t = work_index(gridDim.x);
+        c = 0;
+        return t < ntiles;
+    }
+    if (order == WO_GROUPED) {
+        const int tx = grouped_tiles(ntiles);
+        const int x = blockIdx.x % kXcds, i = blockIdx.x / kXcds;
+        const int ntx = min(tx, ntiles - x * tx);  // tiles of XCD x (<= 0: none)
+        if (ntx <= 0 || i >= ntx * nchunk) return false;
+        t = x * tx + i % ntx;
+        c = i / ntx;
+        return true;
+    }
+    const int w = work_index(gridDim.x);
+    if (w >= ntiles * nchunk) return false;
+    if (order == WO_STATE) {
+        t = w % ntiles;
+        c = w / ntiles;
+    } else {
+        t = w / nchunk;
+        c = w - t * nchunk;
+    }
+    return true;
+}
+
 // LDS-only workgroup barrier: orders LDS accesses across the barrier without
 // waiting for outstanding global loads (prefetches) or stores.
 __device__ __forceinline__ void lds_barrier() {
@@ -348,7 +390,7 @@ __device__ __forceinline__ EwRow ew_row(double vi, double dA, double dC, double 
 // record's slot filled by ew_record_csc and the diagonal entries
 // dQ_i/dtheta_i and dP_i/dv_i trading places.
 template <int NT, bool PAR, bool WITH_J, bool ONE, bool CSC>
-__device__ __forceinline__ void ew_eval(const DevGrid &g, int nstate, int spb, int nchunk, bool state_major,
+__device__ __forceinline__ void ew_eval(const DevGrid &g, int nstate, int spb, int nchunk, int order,
                                         const double *__restrict__ vm, const double *__restrict__ va,
                                         double *__restrict__ P, double *__restrict__ Q, double *__restrict__ J) {
     static_assert(WITH_J || !CSC, "the CSC order concerns J values");
@@ -362,11 +404,9 @@ __device__ __forceinline__ void ew_eval(const DevGrid &g, int nstate, int spb, i
     __shared__ __align__(16) double s_J[NBUF][WITH_J ? kJStage<NS> : 2];
     __shared__ double s_rem[NBUF][4][NR];
 
-    const int W = g.ntiles * nchunk;
-    const int w = work_index(gridDim.x);
-    if (w >= W) return;
-    const int t = state_major ? w % g.ntiles : w / nchunk;
-    const int sb = (state_major ? w / g.ntiles : w - t * nchunk) * spb;
+    int t, c0;
+    if (!work_item(g.ntiles, nchunk, order, t, c0)) return;
+    const int sb = c0 * spb;
     const int se = min(nstate, sb + spb);
     const int k = threadIdx.x;
     // lane table entries do not depend on the tile descriptor: both load at once
@@ -590,17 +630,17 @@ __device__ __forceinline__ void ew_eval(const DevGrid &g, int nstate, int spb, i
 
 template <int NT, bool PAR, bool WITH_J, bool ONE>
 __global__ void __launch_bounds__(NT)
-    k_ew(DevGrid g, int nstate, int spb, int nchunk, bool state_major, const double *__restrict__ vm, const double *__restrict__ va,
+    k_ew(DevGrid g, int nstate, int spb, int nchunk, int order, const double *__restrict__ vm, const double *__restrict__ va,
          double *__restrict__ P, double *__restrict__ Q, double *__restrict__ J) {
-    ew_eval<NT, PAR, WITH_J, ONE, false>(g, nstate, spb, nchunk, state_major, vm, va, P, Q, J);
+    ew_eval<NT, PAR, WITH_J, ONE, false>(g, nstate, spb, nchunk, order, vm, va, P, Q, J);
 }
 
 // Injections and J values in CSC order.
 template <int NT, bool PAR, bool ONE>
 __global__ void __launch_bounds__(NT)
-    k_ew_csc(DevGrid g, int nstate, int spb, int nchunk, bool state_major, const double *__restrict__ vm,
+    k_ew_csc(DevGrid g, int nstate, int spb, int nchunk, int order, const double *__restrict__ vm,
              const double *__restrict__ va, double *__restrict__ P, double *__restrict__ Q, double *__restrict__ J) {
-    ew_eval<NT, PAR, true, ONE, true>(g, nstate, spb, nchunk, state_major, vm, va, P, Q, J);
+    ew_eval<NT, PAR, true, ONE, true>(g, nstate, spb, nchunk, order, vm, va, P, Q, J);
 }
 
 // ===================================================================
@@ -704,7 +744,7 @@ __device__ __forceinline__ void yb_phasor(const YbIn &x, Cx &V, Cx &U) {
 // for bit), and the diagonal entries dQ_i/dtheta_i and dP_i/dv_i trade
 // places.
 template <int NT, bool WITH_J, bool ONE, int PH, bool CSC>
-__device__ __forceinline__ void yb_eval(const DevGrid &g, int nstate, int spb, int nchunk, bool state_major,
+__device__ __forceinline__ void yb_eval(const DevGrid &g, int nstate, int spb, int nchunk, int order,
                                         const double *__restrict__ vm, const double *__restrict__ va,
                                         const double *__restrict__ ph, double *__restrict__ P,
                                         double *__restrict__ Q, double *__restrict__ J) {
@@ -715,11 +755,9 @@ __device__ __forceinline__ void yb_eval(const DevGrid &g, int nstate, int spb, i
     __shared__ double s_yd[WITH_J ? 2 : 1][WITH_J ? NT : 1];  // per row: Y_ii (state-free, written once)
     __shared__ __align__(16) double s_J[NBUF][WITH_J ? kJStage<NT> : 2];
 
-    const int W = g.nytiles * nchunk;
-    const int w = work_index(gridDim.x);
-    if (w >= W) return;
-    const int t = state_major ? w % g.nytiles : w / nchunk;
-    const int sb = (state_major ? w / g.nytiles : w - t * nchunk) * spb;
+    int t, c0;
+    if (!work_item(g.nytiles, nchunk, order, t, c0)) return;
+    const int sb = c0 * spb;
     const int se = min(nstate, sb + spb);
     const int k = threadIdx.x;
     const size_t lane = (size_t)t * NT + k;
@@ -914,17 +952,17 @@ __device__ __forceinline__ void yb_eval(const DevGrid &g, int nstate, int spb, i
 
 template <int NT, bool WITH_J, bool ONE, int PH>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? 6 : 1, 8)))
-    k_ybus(DevGrid g, int nstate, int spb, int nchunk, bool state_major, const double *__restrict__ vm, const double *__restrict__ va,
+    k_ybus(DevGrid g, int nstate, int spb, int nchunk, int order, const double *__restrict__ vm, const double *__restrict__ va,
            const double *__restrict__ ph, double *__restrict__ P, double *__restrict__ Q, double *__restrict__ J) {
-    yb_eval<NT, WITH_J, ONE, PH, false>(g, nstate, spb, nchunk, state_major, vm, va, ph, P, Q, J);
+    yb_eval<NT, WITH_J, ONE, PH, false>(g, nstate, spb, nchunk, order, vm, va, ph, P, Q, J);
 }
 
 // Injections and J values in CSC order by the Ybus method.
 template <int NT, bool ONE>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? 6 : 1, 8)))
-    k_ybus_csc(DevGrid g, int nstate, int spb, int nchunk, bool state_major, const double *__restrict__ vm,
+    k_ybus_csc(DevGrid g, int nstate, int spb, int nchunk, int order, const double *__restrict__ vm,
                const double *__restrict__ va, double *__restrict__ P, double *__restrict__ Q, double *__restrict__ J) {
-    yb_eval<NT, true, ONE, PH_FLY, true>(g, nstate, spb, nchunk, state_major, vm, va, nullptr, P, Q, J);
+    yb_eval<NT, true, ONE, PH_FLY, true>(g, nstate, spb, nchunk, order, vm, va, nullptr, P, Q, J);
 }
 
 // ===================================================================
@@ -961,16 +999,14 @@ __device__ __forceinline__ double vjp_own(double sum, double vi, double lpi, dou
 
 template <int NT, bool ONE>
 __global__ void __launch_bounds__(NT)
-    k_ew_vjp(DevGrid g, int nstate, int spb, int nchunk, bool state_major, const double *__restrict__ vm,
+    k_ew_vjp(DevGrid g, int nstate, int spb, int nchunk, int order, const double *__restrict__ vm,
              const double *__restrict__ va, const double *__restrict__ lp, const double *__restrict__ lq,
              double *__restrict__ gvm, double *__restrict__ gva) {
     __shared__ double s_val[ONE ? 1 : 2][2][NT];
 
-    const int W = g.ntiles * nchunk;
-    const int w = work_index(gridDim.x);
-    if (w >= W) return;
-    const int t = state_major ? w % g.ntiles : w / nchunk;
-    const int sb = (state_major ? w / g.ntiles : w - t * nchunk) * spb;
+    int t, c0;
+    if (!work_item(g.ntiles, nchunk, order, t, c0)) return;
+    const int sb = c0 * spb;
     const int se = min(nstate, sb + spb);
     const int k = threadIdx.x;
     const size_t lane = (size_t)t * NT + k;
@@ -1479,15 +1515,15 @@ void launch_ybus_ph(const DevGrid &g, const Launch &L, dim3 grid, dim3 block, in
     double *J = WITH_J ? L.jval : nullptr;
     switch (L.phasor) {
         case PH_SPLIT:
-            hipLaunchKernelGGL((k_ybus<NT, WITH_J, ONE, PH_SPLIT>), grid, block, 0, st, g, L.nstate, spb, nchunk, L.state_major,
+            hipLaunchKernelGGL((k_ybus<NT, WITH_J, ONE, PH_SPLIT>), grid, block, 0, st, g, L.nstate, spb, nchunk, L.order,
                                L.vm, L.va, L.ph, L.p, L.q, J);
             break;
         case PH_INTERLEAVED:
             hipLaunchKernelGGL((k_ybus<NT, WITH_J, ONE, PH_INTERLEAVED>), grid, block, 0, st, g, L.nstate, spb, nchunk,
-                               L.state_major, L.vm, L.va, L.ph, L.p, L.q, J);
+                               L.order, L.vm, L.va, L.ph, L.p, L.q, J);
             break;
         default:
-            hipLaunchKernelGGL((k_ybus<NT, WITH_J, ONE, PH_FLY>), grid, block, 0, st, g, L.nstate, spb, nchunk, L.state_major,
+            hipLaunchKernelGGL((k_ybus<NT, WITH_J, ONE, PH_FLY>), grid, block, 0, st, g, L.nstate, spb, nchunk, L.order,
                                L.vm, L.va, L.ph, L.p, L.q, J);
             break;
     }
@@ -1498,7 +1534,7 @@ hipError_t launch_ybus(const DevGrid &g, const Launch &L, dim3 grid, dim3 block,
     if (L.phasor != PH_FLY && L.phasor != PH_SPLIT && L.phasor != PH_INTERLEAVED) return hipErrorInvalidValue;
     if (L.kind == K_YB_SJ_CSC) {
         if (L.phasor != PH_FLY) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_ybus_csc<NT, ONE>), grid, block, 0, st, g, L.nstate, spb, nchunk, L.state_major, L.vm, L.va,
+        hipLaunchKernelGGL((k_ybus_csc<NT, ONE>), grid, block, 0, st, g, L.nstate, spb, nchunk, L.order, L.vm, L.va,
                            L.p, L.q, L.jval);
     } else if (L.kind == K_YB_SJ)
         launch_ybus_ph<NT, ONE, true>(g, L, grid, block, spb, nchunk, st);
@@ -1512,33 +1548,34 @@ hipError_t launch_nt(const DevGrid &g, const Launch &L, hipStream_t st) {
     const int spb = L.states_per_block;
     const int nchunk = (L.nstate + spb - 1) / spb;
     const bool yb = L.kind == K_YB_S || L.kind == K_YB_SJ || L.kind == K_YB_SJ_CSC;
-    const int64_t work = (int64_t)(yb ? g.nytiles : g.ntiles) * nchunk;
-    const int64_t blocks = (work + kXcds - 1) / kXcds * kXcds;
+    const int64_t ntl = yb ? g.nytiles : g.ntiles;
+    const int64_t blocks = L.order == WO_GROUPED ? (int64_t)kXcds * grouped_tiles((int)ntl) * nchunk
+                                                 : (ntl * nchunk + kXcds - 1) / kXcds * kXcds;
     if (blocks > INT32_MAX) return hipErrorInvalidConfiguration;
     const dim3 grid((unsigned)blocks), block(NT);
     switch (L.kind) {
         case K_EW_S:
             if (L.has_parallel)
-                hipLaunchKernelGGL((k_ew<NT, true, false, ONE>), grid, block, 0, st, g, L.nstate, spb, nchunk, L.state_major, L.vm, L.va,
+                hipLaunchKernelGGL((k_ew<NT, true, false, ONE>), grid, block, 0, st, g, L.nstate, spb, nchunk, L.order, L.vm, L.va,
                                    L.p, L.q, nullptr);
             else
-                hipLaunchKernelGGL((k_ew<NT, false, false, ONE>), grid, block, 0, st, g, L.nstate, spb, nchunk, L.state_major, L.vm, L.va,
+                hipLaunchKernelGGL((k_ew<NT, false, false, ONE>), grid, block, 0, st, g, L.nstate, spb, nchunk, L.order, L.vm, L.va,
                                    L.p, L.q, nullptr);
             break;
         case K_EW_SJ:
             if (L.has_parallel)
-                hipLaunchKernelGGL((k_ew<NT, true, true, ONE>), grid, block, 0, st, g, L.nstate, spb, nchunk, L.state_major, L.vm, L.va,
+                hipLaunchKernelGGL((k_ew<NT, true, true, ONE>), grid, block, 0, st, g, L.nstate, spb, nchunk, L.order, L.vm, L.va,
                                    L.p, L.q, L.jval);
             else
-                hipLaunchKernelGGL((k_ew<NT, false, true, ONE>), grid, block, 0, st, g, L.nstate, spb, nchunk, L.state_major, L.vm, L.va,
+                hipLaunchKernelGGL((k_ew<NT, false, true, ONE>), grid, block, 0, st, g, L.nstate, spb, nchunk, L.order, L.vm, L.va,
                                    L.p, L.q, L.jval);
             break;
         case K_EW_SJ_CSC:
             if (L.has_parallel)
-                hipLaunchKernelGGL((k_ew_csc<NT, true, ONE>), grid, block, 0, st, g, L.nstate, spb, nchunk, L.state_major, L.vm,
+                hipLaunchKernelGGL((k_ew_csc<NT, true, ONE>), grid, block, 0, st, g, L.nstate, spb, nchunk, L.order, L.vm,
                                    L.va, L.p, L.q, L.jval);
             else
-                hipLaunchKernelGGL((k_ew_csc<NT, false, ONE>), grid, block, 0, st, g, L.nstate, spb, nchunk, L.state_major, L.vm,
+                hipLaunchKernelGGL((k_ew_csc<NT, false, ONE>), grid, block, 0, st, g, L.nstate, spb, nchunk, L.order, L.vm,
                                    L.va, L.p, L.q, L.jval);
             break;
         case K_YB_S:
@@ -1546,7 +1583,7 @@ hipError_t launch_nt(const DevGrid &g, const Launch &L, hipStream_t st) {
         case K_YB_SJ_CSC:
             return launch_ybus<NT, ONE>(g, L, grid, block, spb, nchunk, st);
         case K_EW_VJP:
-            hipLaunchKernelGGL((k_ew_vjp<NT, ONE>), grid, block, 0, st, g, L.nstate, spb, nchunk, L.state_major, L.vm, L.va, L.lp, L.lq,
+            hipLaunchKernelGGL((k_ew_vjp<NT, ONE>), grid, block, 0, st, g, L.nstate, spb, nchunk, L.order, L.vm, L.va, L.lp, L.lq,
                                L.gvm, L.gva);
             break;
         default:

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "libpf.so")
 PF_OK, PF_EINVAL, PF_ENOMEM, PF_EHIP, PF_ESTATE, PF_EUNSUP = range(6)
 PF_METHOD_ELEMENTWISE, PF_METHOD_YBUS, PF_METHOD_ELEMENTWISE_TWO_PHASE, PF_METHOD_ELEMENTWISE_ATOMIC = 0, 1, 2, 3
 PF_BUILD_HOST_ONLY = 1
-PF_ORDER_AUTO, PF_ORDER_TILE_MAJOR, PF_ORDER_STATE_MAJOR = 0, 1, 2
+PF_ORDER_AUTO, PF_ORDER_TILE_MAJOR, PF_ORDER_STATE_MAJOR, PF_ORDER_GROUPED = 0, 1, 2, 3
 PF_PHASOR_SPLIT, PF_PHASOR_INTERLEAVED = 1, 2
 PF_JAC_CSC = 0x100  # OR into the method of pf_jacobian_values: J values in CSC order
 PF_LAYOUT_CSR, PF_LAYOUT_CSC = 0, 1

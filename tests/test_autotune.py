@@ -15,8 +15,9 @@ def test_candidates():
     assert one == [(t, 1, pf.PF_ORDER_TILE_MAJOR) for t in autotune.TILES]
     many = autotune.candidates(12)
     assert (256, 0, pf.PF_ORDER_TILE_MAJOR) in many and (64, 8, pf.PF_ORDER_STATE_MAJOR) in many
+    assert (128, 1, pf.PF_ORDER_GROUPED) in many
     assert all(s <= 12 for _, s, _ in many)
-    assert len(many) == len(set(many)) == len(autotune.TILES) * 5 * 2  # spb in {0, 1, 2, 4, 8}
+    assert len(many) == len(set(many)) == len(autotune.TILES) * 5 * 3  # spb in {0, 1, 2, 4, 8}, three orders
 
 
 def test_tune_picks_fastest_and_caches(tmp_path):

@@ -226,8 +226,12 @@ def test_schedule_choices():
         G.set_schedule(256, -1)
     with pytest.raises(pf.PFError):
         G.set_schedule(256, 0, 7)
+    with pytest.raises(pf.PFError):
+        G.set_schedule(256, 0, 4)
     G.set_schedule(128, 3, pf.PF_ORDER_STATE_MAJOR)
     assert G.schedule()[:3] == (128, 3, pf.PF_ORDER_STATE_MAJOR)
+    G.set_schedule(64, 2, pf.PF_ORDER_GROUPED)
+    assert G.schedule()[:3] == (64, 2, pf.PF_ORDER_GROUPED)
 
 
 def test_binding_refuses_host_arrays():

@@ -95,7 +95,7 @@ def test_shunt_only_buses():
     assert np.allclose(gres["q_ew"][0], -(vm ** 2) * bs, rtol=1e-15, atol=0)
 
 
-@pytest.mark.parametrize("order", [pf.PF_ORDER_TILE_MAJOR, pf.PF_ORDER_STATE_MAJOR])
+@pytest.mark.parametrize("order", [pf.PF_ORDER_TILE_MAJOR, pf.PF_ORDER_STATE_MAJOR, pf.PF_ORDER_GROUPED])
 @pytest.mark.parametrize("spb", [0, 1, 3, 8, 64])
 def test_batched_states_ragged(spb, order):
     g = gridgen.grid_500()
@@ -161,7 +161,7 @@ def test_determinism_across_runs_and_schedules():
             assert np.array_equal(ref[k], again[k]), k
     for tile in (64, 128, 512):
         for spb in (1, 2):
-            for order in (pf.PF_ORDER_TILE_MAJOR, pf.PF_ORDER_STATE_MAJOR):
+            for order in (pf.PF_ORDER_TILE_MAJOR, pf.PF_ORDER_STATE_MAJOR, pf.PF_ORDER_GROUPED):
                 G.set_schedule(tile, spb, order)
                 other = gpu_all(G, vm, va, lp, lq)
                 for k in fixed:
@@ -547,6 +547,6 @@ def test_random_grids_and_schedules(seed):
     va = rng.normal(0, 0.25, (ns, g.nb))
     tile = int(rng.choice([64, 128, 256, 512]))
     spb = int(rng.choice([0, 1, 2, 3]))
-    order = int(rng.choice([pf.PF_ORDER_AUTO, pf.PF_ORDER_TILE_MAJOR, pf.PF_ORDER_STATE_MAJOR]))
+    order = int(rng.choice([pf.PF_ORDER_AUTO, pf.PF_ORDER_TILE_MAJOR, pf.PF_ORDER_STATE_MAJOR, pf.PF_ORDER_GROUPED]))
     print(f"seed {seed}: nb {g.nb} nl {g.nl} parallel {par} isolated {iso} states {ns} schedule {tile},{spb},{order}")
     check_single(g, vm, va, tile=tile, spb=spb, order=order, use_scale=g.nb <= 3)
