@@ -281,8 +281,9 @@ def main():
     ap.add_argument("--probe", action="store_true",
                     help="counter-run workload: headline launches, then one copy of known size; no timing")
     ap.add_argument("--probe-batched", action="store_true",
-                    help="counter-run workload: 3 batched S+J launches (20k buses x 512 states), 3 injection and "
-                         "3 adjoint launches (100k buses x 32 states), then one copy of known size; no timing")
+                    help="counter-run workload: 3 batched S+J launches (20k buses x 512 states), 3 injection, "
+                         "3 adjoint and 3 S+J launches (100k buses x 32 states), then one copy of known size; "
+                         "no timing")
     ap.add_argument("--traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the headline kernel's HBM traffic from two counter CSVs and exit")
     args = ap.parse_args()
@@ -334,12 +335,17 @@ def main():
             pf.pf_injections_elementwise(G4, v4, a4, o[0], o[1])
         for _ in range(3):
             pf.pf_injections_vjp(G4, v4, a4, l4p, l4q, o[2], o[3])
+        j4 = torch.empty(32, G4.nnz_j, dtype=torch.float64, device=dev)
+        for _ in range(3):
+            pf.pf_jacobian_values(G4, pf.PF_METHOD_ELEMENTWISE, v4, a4, o[0], o[1], j4)
+        torch.cuda.synchronize()
+        del j4
         a = torch.ones(COPY_PROBE_DOUBLES, dtype=torch.float64, device=dev)
         b = torch.empty_like(a)
         torch.cuda.synchronize()
         b.copy_(a)
         torch.cuda.synchronize()
-        log("probe done: 3 launches each of 20k x 512 S+J, 100k x 32 injections and adjoint; one copy of "
+        log("probe done: 3 launches each of 20k x 512 S+J, 100k x 32 injections, adjoint and S+J; one copy of "
             f"{8 * COPY_PROBE_DOUBLES} bytes")
         return
 
