@@ -425,112 +425,174 @@ __device__ __forceinline__ void ew_eval(const DevGrid &g, int nstate, int spb, i
         // i0 + p, one further from the bus-shunt record on, c.sh).  Each
         // thread evaluates one branch end of the piece; threads q < NT /
         // kSumChunk sum the piece's chunks and thread 0 folds them into the
-        // row sums (the order of row_sum2); the first branch end of each
-        // Ybus slot in the piece sums its slot's records in order and writes
-        // the slot's four J values (a slot that the piece end cuts hands its
-        // partial sums to the next piece through LDS, so every slot sum runs
-        // in record order).  Thread 0 writes the diagonal slot last, from the
-        // row sums.
+        // row sums (the order of row_sum2).  Without parallel branches every
+        // Ybus slot holds one record, whose lane writes the slot's four J
+        // values as they are; with them, the first branch end of each slot
+        // in the piece sums its slot's records in order and writes the four
+        // values (a slot that the piece end cuts hands its partial sums to
+        // the next piece through LDS, so every slot sum runs in record
+        // order).  Thread 0 writes the diagonal slot last, from the row sums,
+        // and keeps its running sums in LDS, off the registers of the packed
+        // path.  The (state, piece) items are walked with their loads two
+        // stages ahead: while an item is summed, the remote states of the
+        // next item and the records of the one after it are in flight.
         __shared__ double s_cs[2][NT / kSumChunk];
+        __shared__ double s_rs[4];  // thread 0: the running row sums of the current state; dA, dC of the row
         const int i = c.r0;
         const int d = c.ns;  // slots in the row
-        const double dA = g.dA[i], dC = g.dC[i];
+        const int npc = (c.ne + NT - 1) / NT;  // pieces per state
+        const int nit = (se - sb) * npc;
+        const int sh = c.i0 + c.sh;  // the bus-shunt record: the diagonal slot
+        const int ld = WITH_J ? (PAR ? g.slot[sh] : sh) - c.s0 : 0;
         auto rec = [&](int p) { return c.i0 + p + (p >= c.sh ? 1 : 0); };
-        for (int s = sb; s < se; ++s) {
-            const double *vms = vm + (size_t)s * nb;
-            const double *vas = va + (size_t)s * nb;
+        struct Rec {
+            int je;   // remote bus
+            int ls;   // the lane's slot, tile-relative
+            int nls;  // slot of the next piece's first record (-1: last piece)
+            double G, B, Gr, Br;
+        };
+        struct Gat {
+            double vi, ti, vj, tj;
+        };
+        // Every lane loads valid entries: lanes past the piece end repeat its
+        // last record (their values are never used).
+        auto load_rec = [&](int it, Rec &r) {
+            const int base = (it % npc) * NT;
+            const int m = min(NT, c.ne - base);
+            const int e = rec(base + min(k, m - 1));
+            r.je = g.nbr[e];
+            r.G = g.G[e];
+            r.B = g.B[e];
+            if constexpr (CSC) {
+                r.Gr = g.Gr[e];
+                r.Br = g.Br[e];
+            }
+            if constexpr (WITH_J) {
+                const int en = rec(min(base + m, c.ne - 1));
+                r.ls = (PAR ? g.slot[e] : e) - c.s0;
+                const int nls = (PAR ? g.slot[en] : en) - c.s0;
+                r.nls = base + m < c.ne ? nls : -1;
+            }
+        };
+        auto load_gat = [&](int it, int je, Gat &x) {
+            const size_t so = (size_t)(sb + it / npc) * nb;
+            x.vj = vm[so + je];
+            x.tj = va[so + je];
+            x.vi = vm[so + i];
+            x.ti = va[so + i];
+        };
+        Rec rc, rn;
+        Gat gt;
+        load_rec(0, rc);
+        load_rec(min(1, nit - 1), rn);
+        load_gat(0, rc.je, gt);
+        if (k == 0) {
+            s_rs[2] = g.dA[i];
+            s_rs[3] = g.dC[i];
+        }
+        for (int it = 0; it < nit; ++it) {
+            const int s = sb + it / npc, piece = it % npc, base = piece * NT;
+            const int m = min(NT, c.ne - base);
             double *Js = WITH_J ? J + (size_t)s * (size_t)g.nnz_j : nullptr;
-            const double vi = vms[i], ti = vas[i];
-            double as = 0.0, bs = 0.0;
-            if (WITH_J && k == 0) s_cls[1] = -1;  // nothing carried into the first piece
-            for (int base = 0, piece = 0; base < c.ne; base += NT, ++piece) {
-                const int m = min(NT, c.ne - base);
-                int ls = -1;
-                if (WITH_J && k == 0) s_cls[piece & 1] = -1;  // read last in the previous piece
-                if (k < m) {
-                    const int e = rec(base + k);
-                    const int je = g.nbr[e];
-                    EwRec r;
-                    if constexpr (CSC)
-                        r = ew_record_csc(vi, ti, vms[je], vas[je], g.G[e], g.B[e], g.Gr[e], g.Br[e]);
-                    else
-                        r = ew_record(vi, ti, vms[je], vas[je], g.G[e], g.B[e]);
-                    s_ab[0][0][k] = r.a;
-                    s_ab[0][1][k] = r.b;
-                    if constexpr (WITH_J) {
-                        s_J[0][0 * NT + k] = r.o[0];
-                        s_J[0][1 * NT + k] = r.o[1];
-                        s_J[0][2 * NT + k] = r.o[2];
-                        s_J[0][3 * NT + k] = r.o[3];
-                        ls = (PAR ? g.slot[e] : e) - c.s0;
-                        s_ls[k] = ls;
-                    }
+            if (WITH_J && k == 0 && piece == 0) s_cls[1] = -1;  // nothing carried into the first piece
+            int ls = -1;
+            if (WITH_J && k == 0) s_cls[piece & 1] = -1;  // read last in the previous piece
+            if (k < m) {
+                EwRec r;
+                if constexpr (CSC)
+                    r = ew_record_csc(gt.vi, gt.ti, gt.vj, gt.tj, rc.G, rc.B, rc.Gr, rc.Br);
+                else
+                    r = ew_record(gt.vi, gt.ti, gt.vj, gt.tj, rc.G, rc.B);
+                s_ab[0][0][k] = r.a;
+                s_ab[0][1][k] = r.b;
+                if constexpr (WITH_J && !PAR) {  // one record per slot: its J values as they are
+                    const int lsk = rc.ls;
+                    st_out(Js + c.jp + lsk, r.o[0]);
+                    st_out(Js + c.jp + d + lsk, r.o[1]);
+                    st_out(Js + c.jq + lsk, r.o[2]);
+                    st_out(Js + c.jq + d + lsk, r.o[3]);
                 }
-                __syncthreads();
-                chunk_sums(s_ab[0][0], s_ab[0][1], m, s_cs[0], s_cs[1]);
-                if constexpr (WITH_J) {
-                    const int prev_cls = s_cls[(piece + 1) & 1];  // slot carried in from the previous piece
-                    const bool cont = k == 0 && ls == prev_cls;
-                    const bool head = k < m && (k == 0 || ls != s_ls[k - 1]);
-                    if (head) {
-                        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-                        if (cont) {
-                            a0 = s_carry[0];
-                            a1 = s_carry[1];
-                            a2 = s_carry[2];
-                            a3 = s_carry[3];
-                        }
-                        int q = k;
-                        for (; q < m && s_ls[q] == ls; ++q) {
-                            a0 += s_J[0][0 * NT + q];
-                            a1 += s_J[0][1 * NT + q];
-                            a2 += s_J[0][2 * NT + q];
-                            a3 += s_J[0][3 * NT + q];
-                        }
-                        const int pn = base + m;  // first branch end of the next piece
-                        if (q == m && pn < c.ne && (PAR ? g.slot[rec(pn)] : rec(pn)) - c.s0 == ls) {
-                            s_carry[4] = a0;  // the slot goes on in the next piece
-                            s_carry[5] = a1;
-                            s_carry[6] = a2;
-                            s_carry[7] = a3;
-                            s_cls[piece & 1] = ls;
-                        } else {
-                            st_out(Js + c.jp + ls, a0);
-                            st_out(Js + c.jp + d + ls, a1);
-                            st_out(Js + c.jq + ls, a2);
-                            st_out(Js + c.jq + d + ls, a3);
-                        }
-                    }
+                if constexpr (WITH_J && PAR) {
+                    s_J[0][0 * NT + k] = r.o[0];
+                    s_J[0][1 * NT + k] = r.o[1];
+                    s_J[0][2 * NT + k] = r.o[2];
+                    s_J[0][3 * NT + k] = r.o[3];
+                    ls = rc.ls;
+                    s_ls[k] = ls;
                 }
-                __syncthreads();
-                if (k == 0) {
-                    fold_chunks(s_cs[0], s_cs[1], m, piece == 0, as, bs);
-                    if constexpr (WITH_J) {  // the carried partial sums move to the slots read by the next piece
-                        if (s_cls[piece & 1] >= 0) {
-                            s_carry[0] = s_carry[4];
-                            s_carry[1] = s_carry[5];
-                            s_carry[2] = s_carry[6];
-                            s_carry[3] = s_carry[7];
-                        }
+            }
+            const int nls = rc.nls;
+            const double vi = gt.vi;
+            // the next item's remote states, then the records of the one after
+            load_gat(min(it + 1, nit - 1), rn.je, gt);
+            rc = rn;
+            load_rec(min(it + 2, nit - 1), rn);
+            lds_barrier();
+            chunk_sums(s_ab[0][0], s_ab[0][1], m, s_cs[0], s_cs[1]);
+            if constexpr (WITH_J && PAR) {
+                const int prev_cls = s_cls[(piece + 1) & 1];  // slot carried in from the previous piece
+                const bool cont = k == 0 && ls == prev_cls;
+                const bool head = k < m && (k == 0 || ls != s_ls[k - 1]);
+                if (head) {
+                    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+                    if (cont) {
+                        a0 = s_carry[0];
+                        a1 = s_carry[1];
+                        a2 = s_carry[2];
+                        a3 = s_carry[3];
+                    }
+                    int q = k;
+                    for (; q < m && s_ls[q] == ls; ++q) {
+                        a0 += s_J[0][0 * NT + q];
+                        a1 += s_J[0][1 * NT + q];
+                        a2 += s_J[0][2 * NT + q];
+                        a3 += s_J[0][3 * NT + q];
+                    }
+                    if (q == m && nls == ls) {
+                        s_carry[4] = a0;  // the slot goes on in the next piece
+                        s_carry[5] = a1;
+                        s_carry[6] = a2;
+                        s_carry[7] = a3;
+                        s_cls[piece & 1] = ls;
+                    } else {
+                        st_out(Js + c.jp + ls, a0);
+                        st_out(Js + c.jp + d + ls, a1);
+                        st_out(Js + c.jq + ls, a2);
+                        st_out(Js + c.jq + d + ls, a3);
                     }
                 }
             }
+            lds_barrier();
             if (k == 0) {
-                const EwRow o = ew_row(vi, dA, dC, as, bs);
-                if (P) {
-                    st_out(P + (size_t)s * nb + i, o.p);
-                    st_out(Q + (size_t)s * nb + i, o.q);
-                }
-                if constexpr (WITH_J) {
-                    const int sh = c.i0 + c.sh;  // the bus-shunt record: the diagonal slot
-                    const int ld = (PAR ? g.slot[sh] : sh) - c.s0;
-                    st_out(Js + c.jp + ld, o.j11);
-                    st_out(Js + c.jp + d + ld, CSC ? o.j21 : o.j12);
-                    st_out(Js + c.jq + ld, CSC ? o.j12 : o.j21);
-                    st_out(Js + c.jq + d + ld, o.j22);
+                double as = s_rs[0], bs = s_rs[1];
+                fold_chunks(s_cs[0], s_cs[1], m, piece == 0, as, bs);
+                s_rs[0] = as;
+                s_rs[1] = bs;
+                if constexpr (WITH_J && PAR) {  // the carried partial sums move to the slots read by the next piece
+                    if (s_cls[piece & 1] >= 0) {
+                        s_carry[0] = s_carry[4];
+                        s_carry[1] = s_carry[5];
+                        s_carry[2] = s_carry[6];
+                        s_carry[3] = s_carry[7];
+                    }
                 }
             }
-            __syncthreads();
+            if (piece == npc - 1) {  // the state's last piece: its row results
+                if (k == 0) {
+                    const EwRow o = ew_row(vi, s_rs[2], s_rs[3], s_rs[0], s_rs[1]);
+                    if (P) {
+                        st_out(P + (size_t)s * nb + i, o.p);
+                        st_out(Q + (size_t)s * nb + i, o.q);
+                    }
+                    if constexpr (WITH_J) {
+                        st_out(Js + c.jp + ld, o.j11);
+                        st_out(Js + c.jp + d + ld, CSC ? o.j21 : o.j12);
+                        st_out(Js + c.jq + ld, CSC ? o.j12 : o.j21);
+                        st_out(Js + c.jq + d + ld, o.j22);
+                    }
+                }
+                lds_barrier();
+            }
         }
         return;
     }
@@ -792,16 +854,16 @@ __device__ __forceinline__ void yb_eval(const DevGrid &g, int nstate, int spb, i
                     s_yv[0][0][k] = yv.re;
                     s_yv[0][1][k] = yv.im;
                 }
-                __syncthreads();
+                lds_barrier();
                 chunk_sums(s_yv[0][0], s_yv[0][1], m, s_cs[0], s_cs[1]);
-                __syncthreads();
+                lds_barrier();
                 if (k == 0) {
                     fold_chunks(s_cs[0], s_cs[1], m, base == 0, I.re, I.im);
                     s_vu[0][0][0] = I.re;
                     s_vu[0][1][0] = I.im;
                 }
             }
-            __syncthreads();
+            lds_barrier();
             YbIn xi;
             yb_load<PH, true>(vm, va, ph, n, so + i, xi);
             Cx Vi, Ui;
@@ -853,7 +915,7 @@ __device__ __forceinline__ void yb_eval(const DevGrid &g, int nstate, int spb, i
                     }
                 }
             }
-            __syncthreads();
+            lds_barrier();
         }
         return;
     }
@@ -1032,32 +1094,51 @@ __global__ void __launch_bounds__(NT)
     if (c.ne > NT) {
         // one row with more than NT branch ends, in pieces of NT branch ends
         // (the bus-shunt record, position c.sh, contributes nothing and is
-        // skipped); chunk sums in parallel, folded by thread 0 in row_sum2's order
+        // skipped); chunk sums in parallel, folded by thread 0 in row_sum2's
+        // order.  The remote bus of the next (state, piece) item is loaded
+        // one item ahead, so each item's gathers go out at once.
         __shared__ double s_cs[2][NT / kSumChunk];
+        __shared__ double s_rs[4];  // thread 0: the running sums of the current state; dA, dC of the row
         const int i = c.r0;
-        const double dA = g.dA[i], dC = g.dC[i];
-        for (int s = sb; s < se; ++s) {
-            const size_t so = (size_t)s * nb;
-            double acc_a = 0.0, acc_v = 0.0;
-            for (int base = 0; base < c.ne; base += NT) {
-                const int m = min(NT, c.ne - base);
-                if (k < m) {
-                    const int pos = base + k;
-                    const int e = c.i0 + pos + (pos >= c.sh ? 1 : 0);
-                    double ga, gv;
-                    vjp_record(fetch(so, i, g.nbr[e]), g.G[e], g.B[e], g.Gr[e], g.Br[e], ga, gv);
-                    s_val[0][0][k] = ga;
-                    s_val[0][1][k] = gv;
-                }
-                __syncthreads();
-                chunk_sums(s_val[0][0], s_val[0][1], m, s_cs[0], s_cs[1]);
-                __syncthreads();
-                if (k == 0) fold_chunks(s_cs[0], s_cs[1], m, base == 0, acc_a, acc_v);
+        const int npc = (c.ne + NT - 1) / NT;  // pieces per state
+        const int nit = (se - sb) * npc;
+        // lanes past the piece end repeat its last record (values unused)
+        auto rec_of = [&](int it) {
+            const int base = (it % npc) * NT;
+            const int pos = base + min(k, min(NT, c.ne - base) - 1);
+            return c.i0 + pos + (pos >= c.sh ? 1 : 0);
+        };
+        int jn = g.nbr[rec_of(0)];
+        if (k == 0) {
+            s_rs[2] = g.dA[i];
+            s_rs[3] = g.dC[i];
+        }
+        for (int it = 0; it < nit; ++it) {
+            const int s = sb + it / npc, piece = it % npc;
+            const int m = min(NT, c.ne - piece * NT);
+            const int e = rec_of(it);
+            const VjpIn x = fetch((size_t)s * nb, i, jn);
+            const double G = g.G[e], B = g.B[e], Gr = g.Gr[e], Br = g.Br[e];
+            jn = g.nbr[rec_of(min(it + 1, nit - 1))];
+            if (k < m) {
+                double ga, gv;
+                vjp_record(x, G, B, Gr, Br, ga, gv);
+                s_val[0][0][k] = ga;
+                s_val[0][1][k] = gv;
             }
+            lds_barrier();
+            chunk_sums(s_val[0][0], s_val[0][1], m, s_cs[0], s_cs[1]);
+            lds_barrier();
             if (k == 0) {
-                const double vi = vm[so + i];
-                st_out(gva + so + i, acc_a);
-                st_out(gvm + so + i, vjp_own(acc_v, vi, lp[so + i], lq[so + i], dA, dC));
+                double acc_a = s_rs[0], acc_v = s_rs[1];
+                fold_chunks(s_cs[0], s_cs[1], m, piece == 0, acc_a, acc_v);
+                s_rs[0] = acc_a;
+                s_rs[1] = acc_v;
+                if (piece == npc - 1) {  // the state's last piece: the row's gradients
+                    const size_t so = (size_t)s * nb;
+                    st_out(gva + so + i, acc_a);
+                    st_out(gvm + so + i, vjp_own(acc_v, x.vi, x.lpi, x.lqi, s_rs[2], s_rs[3]));
+                }
             }
         }
         return;
