@@ -299,8 +299,10 @@ int pf_jacobian_scatter(const pf_grid *g, int32_t nstate, const double *jval, co
  *   states_per_block  voltage states one workgroup evaluates in turn, with
  *                     the tile's constants held in registers (>= 1; 0 =
  *                     automatic: at most 2 for Jacobian launches, at most 8
- *                     for injections and the adjoint, fewer when the tiles
- *                     alone do not fill the GPU)
+ *                     for injections, fewer when the tiles alone do not
+ *                     fill the GPU; the adjoint splits each tile's states
+ *                     into as many chunks as fill one round of resident
+ *                     workgroups)
  *   order             order of the (tile, state chunk) work items over the
  *                     workgroups: PF_ORDER_TILE_MAJOR (the state chunks of
  *                     one tile are adjacent), PF_ORDER_STATE_MAJOR (the tiles

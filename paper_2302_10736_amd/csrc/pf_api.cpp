@@ -947,10 +947,13 @@ int work_order(const pf_grid *g, int kind) {
 // the J stream: 8 nnzJ bytes per state against a few bytes of constants),
 // 1 when the tables a workgroup's XCD walks stay in its 4 MB L2 between
 // states (an eighth of them in the grouped order, all otherwise), and at
-// most 8 for injections and the adjoint (small
-// per-state outputs, so reusing the constants pays); fewer when the tiles
-// alone would leave part of one round of resident workgroups empty (it then
-// splits each tile's states into about resident capacity / tiles chunks).
+// most 8 for injections (small per-state outputs, so reusing the constants
+// pays); fewer when the tiles alone would leave part of one round of
+// resident workgroups empty (it then splits each tile's states into about
+// resident capacity / tiles chunks).  The adjoint takes exactly that split,
+// however many states it gives a workgroup: its record constants (both
+// ends' couplings) are the heaviest, and one round of workgroups that each
+// walk their share of the states measured fastest.
 int auto_states_per_block(const pf_grid *g, int kind, int32_t nstate) {
     if (g->states_per_block > 0) return std::min<int32_t>(g->states_per_block, std::max(nstate, 1));
     if (nstate <= 1) return 1;
@@ -970,6 +973,7 @@ int auto_states_per_block(const pf_grid *g, int kind, int32_t nstate) {
         if (work_order(g, kind) == pf::WO_GROUPED) tb /= 8;
         return std::min(fill, tb <= ((int64_t)2 << 20) ? 1 : 2);
     }
+    if (kind == pf::K_EW_VJP) return fill;
     return std::min(fill, 8);
 }
 
