@@ -1001,6 +1001,46 @@ def main():
                          "sample": f"{ns_cpu} of the 512 states of the 20k-bus batched workload, element-wise S+J, "
                                    f"{threads} threads ({el2:.2f} s)"}
             out.setdefault("extra", {})["cpu_oracle_batched_20k"] = extra_cpu
+
+            # the 100k x 32 adjoint workload: forward injections, then J^T lambda (J, then its transpose
+            # product), one state per task
+            vm4, va4 = gridgen.states(g.nb, 32, case=4)
+            lp4, lq4 = gridgen.adjoint_seeds(g.nb, 32, case=4)
+
+            def fwd(s_):
+                oracle.inject_ew(g, vm4[s_], va4[s_])
+
+            def adj(s_):
+                oracle.vjp(g.nb, pat, oracle.jac_ew(g, vm4[s_], va4[s_], pat), lp4[s_], lq4[s_])
+            with ThreadPoolExecutor(max_workers=threads) as ex:
+                t0 = time.perf_counter()
+                list(ex.map(fwd, range(32)))
+                el_f = time.perf_counter() - t0
+                t0 = time.perf_counter()
+                list(ex.map(adj, range(32)))
+                el_b = time.perf_counter() - t0
+            out["extra"]["cpu_oracle_adjoint_100k_x32"] = {
+                "forward_state_evals_per_s": 32 / el_f, "vjp_state_evals_per_s": 32 / el_b, "cores": threads,
+                "kind": "oracle", "sample": f"the 32 states of the 100k x 32 adjoint workload, {threads} threads "
+                                            f"(forward {el_f:.2f} s, adjoint {el_b:.2f} s)"}
+
+            # the 64 uneven grids x 4 states, element-wise S+J, one (grid, state) per task
+            grids = gridgen.grids_uneven_64()
+            pats = [oracle.jac_pattern(oracle.ybus(gr)) for gr in grids]
+            st3 = [gridgen.states(gr.nb, 4, case=3, grid=k + 1) for k, gr in enumerate(grids)]
+
+            def mg(task):
+                k, s_ = divmod(task, 4)
+                oracle.inject_ew(grids[k], st3[k][0][s_], st3[k][1][s_])
+                oracle.jac_ew(grids[k], st3[k][0][s_], st3[k][1][s_], pats[k])
+            with ThreadPoolExecutor(max_workers=threads) as ex:
+                t0 = time.perf_counter()
+                list(ex.map(mg, range(4 * len(grids))))
+                el_m = time.perf_counter() - t0
+            out["extra"]["cpu_oracle_multigrid_64x4"] = {
+                "value": 4 * len(grids) / el_m, "unit": "grid-state-evals/s", "cores": threads, "kind": "oracle",
+                "sample": f"all {4 * len(grids)} grid-states of the 64-grid workload, element-wise S+J, {threads} "
+                          f"threads ({el_m:.2f} s)"}
     print(json.dumps(out), flush=True)
 
 
