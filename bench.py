@@ -1012,17 +1012,22 @@ def main():
 
             def adj(s_):
                 oracle.vjp(g.nb, pat, oracle.jac_ew(g, vm4[s_], va4[s_], pat), lp4[s_], lq4[s_])
+            def passes(fn, ntask, ex):  # whole passes over the tasks until at least one second has passed
+                n_, t0_ = 0, time.perf_counter()
+                while True:
+                    list(ex.map(fn, range(ntask)))
+                    n_ += 1
+                    el_ = time.perf_counter() - t0_
+                    if el_ >= 1.0:
+                        return n_, el_
             with ThreadPoolExecutor(max_workers=threads) as ex:
-                t0 = time.perf_counter()
-                list(ex.map(fwd, range(32)))
-                el_f = time.perf_counter() - t0
-                t0 = time.perf_counter()
-                list(ex.map(adj, range(32)))
-                el_b = time.perf_counter() - t0
+                nf, el_f = passes(fwd, 32, ex)
+                nbk, el_b = passes(adj, 32, ex)
             out["extra"]["cpu_oracle_adjoint_100k_x32"] = {
-                "forward_state_evals_per_s": 32 / el_f, "vjp_state_evals_per_s": 32 / el_b, "cores": threads,
-                "kind": "oracle", "sample": f"the 32 states of the 100k x 32 adjoint workload, {threads} threads "
-                                            f"(forward {el_f:.2f} s, adjoint {el_b:.2f} s)"}
+                "forward_state_evals_per_s": 32 * nf / el_f, "vjp_state_evals_per_s": 32 * nbk / el_b,
+                "cores": threads, "kind": "oracle",
+                "sample": f"the 32 states of the 100k x 32 adjoint workload, {threads} threads (forward {nf} "
+                          f"passes in {el_f:.2f} s, adjoint {nbk} passes in {el_b:.2f} s)"}
 
             # the 64 uneven grids x 4 states, element-wise S+J, one (grid, state) per task
             grids = gridgen.grids_uneven_64()
@@ -1034,13 +1039,12 @@ def main():
                 oracle.inject_ew(grids[k], st3[k][0][s_], st3[k][1][s_])
                 oracle.jac_ew(grids[k], st3[k][0][s_], st3[k][1][s_], pats[k])
             with ThreadPoolExecutor(max_workers=threads) as ex:
-                t0 = time.perf_counter()
-                list(ex.map(mg, range(4 * len(grids))))
-                el_m = time.perf_counter() - t0
+                nm, el_m = passes(mg, 4 * len(grids), ex)
             out["extra"]["cpu_oracle_multigrid_64x4"] = {
-                "value": 4 * len(grids) / el_m, "unit": "grid-state-evals/s", "cores": threads, "kind": "oracle",
+                "value": 4 * len(grids) * nm / el_m, "unit": "grid-state-evals/s", "cores": threads,
+                "kind": "oracle",
                 "sample": f"all {4 * len(grids)} grid-states of the 64-grid workload, element-wise S+J, {threads} "
-                          f"threads ({el_m:.2f} s)"}
+                          f"threads ({nm} passes in {el_m:.2f} s)"}
     print(json.dumps(out), flush=True)
 
 
