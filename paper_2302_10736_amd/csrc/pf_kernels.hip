@@ -22,8 +22,12 @@
 // not depend on the tile size or on the states per workgroup.  LDS buffers
 // alternate between consecutive states (two barriers per state), and the
 // gathers of the next state are issued before the current one is reduced.
-// A row with more than NT records is a tile of its own, walked in chunks by
-// one thread's sequential sums in the same order.  The baselines further
+// A row with more than NT records is a tile of its own, walked in pieces of
+// NT records: the piece's 32-term chunks are summed in parallel and folded
+// in order by one thread, so its sums keep the packed path's order.  The
+// work items (tile, chunk of states) map to workgroups XCD by XCD in one of
+// three orders (tile-major, state-major, grouped; see work_item).  The
+// baselines further
 // down (the two-phase and copy-add methods, branch flows) use one thread
 // per branch instead.
 //
