@@ -428,20 +428,23 @@ __device__ __forceinline__ void ew_eval(const DevGrid &g, int nstate, int spb, i
         // branch ends (position p of the row's branch ends is record
         // i0 + p, one further from the bus-shunt record on, c.sh).  Each
         // thread evaluates one branch end of the piece; threads q < NT /
-        // kSumChunk sum the piece's chunks and thread 0 folds them into the
-        // row sums (the order of row_sum2).  Without parallel branches every
+        // kSumChunk sum the piece's chunks and one thread (in the second wave
+        // when there is one) folds them into the row sums in the order of
+        // row_sum2, each piece's fold running beside the next piece's chunk
+        // sums (two buffers of chunk sums).  Without parallel branches every
         // Ybus slot holds one record, whose lane writes the slot's four J
         // values as they are; with them, the first branch end of each slot
         // in the piece sums its slot's records in order and writes the four
         // values (a slot that the piece end cuts hands its partial sums to
         // the next piece through LDS, so every slot sum runs in record
-        // order).  Thread 0 writes the diagonal slot last, from the row sums,
-        // and keeps its running sums in LDS, off the registers of the packed
-        // path.  The (state, piece) items are walked with their loads two
+        // order).  The folding thread writes the diagonal slot last, from the
+        // row sums, and keeps its running sums in LDS, off the registers of
+        // the packed path.  The (state, piece) items are walked with their loads two
         // stages ahead: while an item is summed, the remote states of the
         // next item and the records of the one after it are in flight.
-        __shared__ double s_cs[2][NT / kSumChunk];
-        __shared__ double s_rs[4];  // thread 0: the running row sums of the current state; dA, dC of the row
+        __shared__ double s_cs[2][2][NT / kSumChunk];  // chunk sums of the last two pieces, by piece parity
+        constexpr int FT = NT >= 128 ? 64 : 0;  // the folding thread, off wave 0 when the tile has two waves
+        __shared__ double s_rs[4];  // the folding thread's running row sums of the current state; dA, dC of the row
         const int i = c.r0;
         const int d = c.ns;  // slots in the row
         const int npc = (c.ne + NT - 1) / NT;  // pieces per state
@@ -532,7 +535,13 @@ __device__ __forceinline__ void ew_eval(const DevGrid &g, int nstate, int spb, i
             rc = rn;
             load_rec(min(it + 2, nit - 1), rn);
             lds_barrier();
-            chunk_sums(s_ab[0][0], s_ab[0][1], m, s_cs[0], s_cs[1]);
+            chunk_sums(s_ab[0][0], s_ab[0][1], m, s_cs[piece & 1][0], s_cs[piece & 1][1]);
+            if (k == FT && piece > 0) {  // the previous (full) piece's chunk sums, while this piece's are summed
+                double as = s_rs[0], bs = s_rs[1];
+                fold_chunks(s_cs[(piece + 1) & 1][0], s_cs[(piece + 1) & 1][1], NT, piece == 1, as, bs);
+                s_rs[0] = as;
+                s_rs[1] = bs;
+            }
             if constexpr (WITH_J && PAR) {
                 const int prev_cls = s_cls[(piece + 1) & 1];  // slot carried in from the previous piece
                 const bool cont = k == 0 && ls == prev_cls;
@@ -568,10 +577,6 @@ __device__ __forceinline__ void ew_eval(const DevGrid &g, int nstate, int spb, i
             }
             lds_barrier();
             if (k == 0) {
-                double as = s_rs[0], bs = s_rs[1];
-                fold_chunks(s_cs[0], s_cs[1], m, piece == 0, as, bs);
-                s_rs[0] = as;
-                s_rs[1] = bs;
                 if constexpr (WITH_J && PAR) {  // the carried partial sums move to the slots read by the next piece
                     if (s_cls[piece & 1] >= 0) {
                         s_carry[0] = s_carry[4];
@@ -581,9 +586,11 @@ __device__ __forceinline__ void ew_eval(const DevGrid &g, int nstate, int spb, i
                     }
                 }
             }
-            if (piece == npc - 1) {  // the state's last piece: its row results
-                if (k == 0) {
-                    const EwRow o = ew_row(vi, s_rs[2], s_rs[3], s_rs[0], s_rs[1]);
+            if (piece == npc - 1) {  // the state's last piece: its own chunk sums, then the row results
+                if (k == FT) {
+                    double as = s_rs[0], bs = s_rs[1];
+                    fold_chunks(s_cs[piece & 1][0], s_cs[piece & 1][1], m, false, as, bs);
+                    const EwRow o = ew_row(vi, s_rs[2], s_rs[3], as, bs);
                     if (P) {
                         st_out(P + (size_t)s * nb + i, o.p);
                         st_out(Q + (size_t)s * nb + i, o.q);
@@ -837,8 +844,10 @@ __device__ __forceinline__ void yb_eval(const DevGrid &g, int nstate, int spb, i
 
     if (c.ns > NT) {
         // ---- one long row: pass 1 sums I_i in pieces of NT nonzeros (chunk sums in parallel,
-        // folded by thread 0 in row_sum2's order), pass 2 writes J.
-        __shared__ double s_cs[2][NT / kSumChunk];
+        // folded in row_sum2's order by one thread, each piece's fold overlapping the next piece's
+        // chunk sums), pass 2 writes J.
+        __shared__ double s_cs[2][2][NT / kSumChunk];  // chunk sums of the last two pieces, by piece parity
+        constexpr int FT = NT >= 128 ? 64 : 0;  // the folding thread, off wave 0 when the tile has two waves
         const int i = c.r0;
         const int d = c.ns;
         const size_t n = (size_t)nstate * nb;
@@ -858,11 +867,14 @@ __device__ __forceinline__ void yb_eval(const DevGrid &g, int nstate, int spb, i
                     s_yv[0][0][k] = yv.re;
                     s_yv[0][1][k] = yv.im;
                 }
+                const int pc = base / NT;  // piece
                 lds_barrier();
-                chunk_sums(s_yv[0][0], s_yv[0][1], m, s_cs[0], s_cs[1]);
+                chunk_sums(s_yv[0][0], s_yv[0][1], m, s_cs[pc & 1][0], s_cs[pc & 1][1]);
+                if (k == FT && pc > 0)  // the previous (full) piece's chunk sums, while this piece's are summed
+                    fold_chunks(s_cs[(pc + 1) & 1][0], s_cs[(pc + 1) & 1][1], NT, pc == 1, I.re, I.im);
                 lds_barrier();
-                if (k == 0) {
-                    fold_chunks(s_cs[0], s_cs[1], m, base == 0, I.re, I.im);
+                if (k == FT && base + NT >= d) {  // the last piece: its own chunk sums, then I_i for every thread
+                    fold_chunks(s_cs[pc & 1][0], s_cs[pc & 1][1], m, false, I.re, I.im);
                     s_vu[0][0][0] = I.re;
                     s_vu[0][1][0] = I.im;
                 }
@@ -1098,11 +1110,13 @@ __global__ void __launch_bounds__(NT)
     if (c.ne > NT) {
         // one row with more than NT branch ends, in pieces of NT branch ends
         // (the bus-shunt record, position c.sh, contributes nothing and is
-        // skipped); chunk sums in parallel, folded by thread 0 in row_sum2's
-        // order.  The remote bus of the next (state, piece) item is loaded
-        // one item ahead, so each item's gathers go out at once.
-        __shared__ double s_cs[2][NT / kSumChunk];
-        __shared__ double s_rs[4];  // thread 0: the running sums of the current state; dA, dC of the row
+        // skipped); chunk sums in parallel, folded in row_sum2's order by one
+        // thread, each piece's fold beside the next piece's chunk sums.  The
+        // remote bus of the next (state, piece) item is loaded one item
+        // ahead, so each item's gathers go out at once.
+        __shared__ double s_cs[2][2][NT / kSumChunk];  // chunk sums of the last two pieces, by piece parity
+        constexpr int FT = NT >= 128 ? 64 : 0;  // the folding thread, off wave 0 when the tile has two waves
+        __shared__ double s_rs[4];  // the folding thread's running sums of the current state; dA, dC of the row
         const int i = c.r0;
         const int npc = (c.ne + NT - 1) / NT;  // pieces per state
         const int nit = (se - sb) * npc;
@@ -1131,14 +1145,18 @@ __global__ void __launch_bounds__(NT)
                 s_val[0][1][k] = gv;
             }
             lds_barrier();
-            chunk_sums(s_val[0][0], s_val[0][1], m, s_cs[0], s_cs[1]);
-            lds_barrier();
-            if (k == 0) {
+            chunk_sums(s_val[0][0], s_val[0][1], m, s_cs[piece & 1][0], s_cs[piece & 1][1]);
+            if (k == FT && piece > 0) {  // the previous (full) piece's chunk sums, while this piece's are summed
                 double acc_a = s_rs[0], acc_v = s_rs[1];
-                fold_chunks(s_cs[0], s_cs[1], m, piece == 0, acc_a, acc_v);
+                fold_chunks(s_cs[(piece + 1) & 1][0], s_cs[(piece + 1) & 1][1], NT, piece == 1, acc_a, acc_v);
                 s_rs[0] = acc_a;
                 s_rs[1] = acc_v;
-                if (piece == npc - 1) {  // the state's last piece: the row's gradients
+            }
+            lds_barrier();
+            if (k == FT && piece == npc - 1) {  // the state's last piece: its own chunk sums, then the gradients
+                double acc_a = s_rs[0], acc_v = s_rs[1];
+                fold_chunks(s_cs[piece & 1][0], s_cs[piece & 1][1], m, false, acc_a, acc_v);
+                {
                     const size_t so = (size_t)s * nb;
                     st_out(gva + so + i, acc_a);
                     st_out(gvm + so + i, vjp_own(acc_v, x.vi, x.lpi, x.lqi, s_rs[2], s_rs[3]));
