@@ -820,7 +820,7 @@ def main():
             pf.pf_jacobian_values(G3, pf.PF_METHOD_ELEMENTWISE, vm3d, va3d, p3, q3, j3, stream=st)
         steps = max(20, K // 40)
         if not args.no_tune:
-            cands = [(t, s, o) for t in (128, 256, 512) for s in (0, 1, 4) for o in (1, 2)]
+            cands = [(t, s, o) for t in (128, 256, 512) for s in (0, 1, 4) for o in (1, 2, 3)]
             tuned["multigrid"] = autotune.tune(G3, "jacobian_ew", 4, cache=tune_cache, cands=cands, save=False)
         ev, wall = timed(m_sj, steps, 5, period=10)
         mb = algorithmic_bytes(big.nb, big.nl, G3.nnz_y, 4)
