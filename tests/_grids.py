@@ -62,6 +62,32 @@ def random_small(nb: int, nl: int, seed: int, parallel: int = 0, isolated: int =
     return Grid(nb, n, fb, tb, r, x, b, tap, shift, gs, bs)
 
 
+def random_hubs(nb: int, nhub: int, deg_lo: int, deg_hi: int, parallel: int, seed: int) -> Grid:
+    """A random tree on nb buses plus nhub hub buses joined to deg_lo..deg_hi random other buses each
+    (rows longer than any tile), and `parallel` duplicated branches drawn from all of them."""
+    rng = np.random.default_rng(seed)
+    f = [int(rng.integers(0, i)) for i in range(1, nb)]
+    t = list(range(1, nb))
+    for h in rng.choice(nb, size=nhub, replace=False):
+        deg = int(rng.integers(deg_lo, deg_hi + 1))
+        for o in rng.choice(nb, size=min(deg, nb - 1), replace=False):
+            if o != h:
+                f.append(int(h))
+                t.append(int(o))
+    for _ in range(parallel):
+        k = int(rng.integers(0, len(f)))
+        f.append(f[k])
+        t.append(t[k])
+    n = len(f)
+    flip = rng.random(n) < 0.5
+    fb = np.where(flip, t, f).astype(np.int32)
+    tb = np.where(flip, f, t).astype(np.int32)
+    tap = np.where(rng.random(n) < 0.3, rng.uniform(0.9, 1.1, n), 1.0)
+    shift = np.where(tap != 1.0, rng.uniform(-0.1, 0.1, n), 0.0)
+    return Grid(nb, n, fb, tb, rng.uniform(0.001, 0.05, n), rng.uniform(0.01, 0.3, n), rng.uniform(0, 0.1, n),
+                tap, shift, rng.uniform(0, 0.02, nb), rng.uniform(-0.1, 0.1, nb))
+
+
 def random_state(nb: int, seed: int, sigma: float = 0.2):
     g = np.random.default_rng(seed + 7919)
     return g.uniform(0.9, 1.1, nb), g.normal(0.0, sigma, nb)

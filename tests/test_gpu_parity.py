@@ -529,6 +529,34 @@ def test_bound_calls_match_plain_calls():
     assert torch.equal(p1, p2) and torch.equal(q1, q2)
 
 
+@pytest.mark.parametrize("seed", range(12))
+def test_random_hub_grids_and_schedules(seed):
+    """Randomised long rows: hub buses of 65 to 1,500 branches (walked in pieces, with the chunk
+    sums of one piece folded beside the next piece's), parallel branches among them, random
+    schedule and batch size; every call against the oracle, and bitwise against the initial
+    schedule."""
+    rng = np.random.default_rng(7000 + seed)
+    g = _grids.random_hubs(int(rng.integers(300, 3000)), int(rng.integers(1, 6)), 65,
+                           int(rng.integers(100, 1500)), int(rng.integers(0, 30)), 7100 + seed)
+    ns = int(rng.integers(1, 6))
+    vm = rng.uniform(0.9, 1.1, (ns, g.nb))
+    va = rng.normal(0, 0.3, (ns, g.nb))
+    lp, lq = rng.normal(size=vm.shape), rng.normal(size=vm.shape)
+    tile = int(rng.choice([64, 128, 256, 512]))
+    spb = int(rng.choice([0, 1, 2, 3, 5]))
+    order = int(rng.choice([pf.PF_ORDER_AUTO, pf.PF_ORDER_TILE_MAJOR, pf.PF_ORDER_STATE_MAJOR, pf.PF_ORDER_GROUPED]))
+    print(f"seed {seed}: nb {g.nb} nl {g.nl} states {ns} schedule {tile},{spb},{order}")
+    G = pf.Grid.from_grid(g)
+    ref = gpu_all(G, vm, va, lp, lq)
+    G.set_schedule(tile, spb, order)
+    got = gpu_all(G, vm, va, lp, lq)
+    for k in ref:
+        if not k.endswith("_ca"):  # copy-add: atomic adds in no fixed order
+            assert np.array_equal(ref[k], got[k]), k
+    for s in range(ns):
+        compare_grid(got, oracle_all(g, vm[s], va[s], lp[s], lq[s]), s, slice(None), slice(None), slice(None))
+
+
 @pytest.mark.parametrize("seed", range(40))
 def test_random_grids_and_schedules(seed):
     """Randomised sweep: grid size and shape (parallel branches, isolated
