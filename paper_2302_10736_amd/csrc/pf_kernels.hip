@@ -23,7 +23,7 @@
 // alternate between consecutive states (two barriers per state), and the
 // gathers of the next state are issued before the current one is reduced.
 // A row with more than NT records is a tile of its own, walked in pieces of
-// NT records: the piece's 32-term chunks are summed in parallel and folded
+// NT records: the piece's 16-term chunks are summed in parallel and folded
 // in order by one thread, so its sums keep the packed path's order.  The
 // work items (tile, chunk of states) map to workgroups XCD by XCD in one of
 // three orders (tile-major, state-major, grouped; see work_item).  The
@@ -275,7 +275,7 @@ __device__ __forceinline__ void row_sum2_acc(const double *x, const double *y, i
 // left-to-right sum.  Rows longer than a tile sum their chunks in parallel
 // (chunk_sums, fold_chunks) and still produce the bits of the packed path,
 // whatever the tile size.
-constexpr int kSumChunk = 32;
+constexpr int kSumChunk = 16;
 
 __device__ __forceinline__ void row_sum2(const double *x, const double *y, int a, int z, double &sx, double &sy) {
     double u = 0.0, v = 0.0;
@@ -314,10 +314,7 @@ __device__ __forceinline__ void fold_chunks(const double *csx, const double *csy
         v = csy[0];
         q = 1;
     }
-    for (; q < nc; ++q) {
-        u += csx[q];
-        v += csy[q];
-    }
+    row_sum2_acc(csx, csy, q, nc, u, v);  // left to right, four chunk sums per LDS round trip
 }
 
 // One element-wise record (see the file header): its row-sum terms and the

@@ -170,7 +170,7 @@ def test_determinism_across_runs_and_schedules():
 
 @pytest.mark.parametrize("n_leaf,parallel", [(40, 0), (100, 3), (256, 0), (250, 6), (333, 0), (700, 25)])
 def test_hub_rows_bitwise_across_schedules(n_leaf, parallel):
-    """Bus sums run in chunks of 32 terms fixed by the row alone, so a hub row
+    """Bus sums run in chunks of 16 terms fixed by the row alone, so a hub row
     gives the same bits whether its tile packs it (tile size above its branch
     ends) or walks it in pieces of the tile size (the long-row path), for
     every tile size and states per workgroup; every run matches the oracle.
