@@ -184,6 +184,22 @@ typedef double dvec2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ void st_out(double *p, double v) { __builtin_nontemporal_store(v, p); }
 __device__ __forceinline__ void st_out2(dvec2 *p, dvec2 v) { __builtin_nontemporal_store(v, p); }
 
+// A row output (P, Q or an adjoint gradient) of the packed tiles: a plain
+// store with PLAIN, else a streaming one.  The row ranges of neighbouring
+// tiles share the 128-byte lines at their ends.  When a launch has few
+// state chunks per tile, those tiles write the shared lines at about the
+// same time: plain stores let L2 join the two parts of each line before it
+// goes to memory, where streaming stores write two partial lines.  With
+// many chunks per tile the lines would wait in L2 too long, and streaming
+// stores are faster.
+template <bool PLAIN>
+__device__ __forceinline__ void st_row(double *p, double v) {
+    if constexpr (PLAIN)
+        *p = v;
+    else
+        __builtin_nontemporal_store(v, p);
+}
+
 // Copy a staged tile of J rows (LDS, slot capacity NS) to global memory
 // with 16-byte stores.
 template <int NT, int NS>
@@ -390,7 +406,7 @@ __device__ __forceinline__ EwRow ew_row(double vi, double dA, double dC, double 
 // column-major order (WITH_J only) with the same tiles and staging, each
 // record's slot filled by ew_record_csc and the diagonal entries
 // dQ_i/dtheta_i and dP_i/dv_i trading places.
-template <int NT, bool PAR, bool WITH_J, bool ONE, bool CSC>
+template <int NT, bool PAR, bool WITH_J, bool ONE, bool CSC, bool PLAIN>
 __device__ __forceinline__ void ew_eval(const DevGrid &g, int nstate, int spb, int nchunk, int order,
                                         const double *__restrict__ vm, const double *__restrict__ va,
                                         double *__restrict__ P, double *__restrict__ Q, double *__restrict__ J) {
@@ -687,8 +703,8 @@ __device__ __forceinline__ void ew_eval(const DevGrid &g, int nstate, int spb, i
             }
         }
         if (P && rowt) {
-            st_out(P + (size_t)s * nb + ir, o.p);
-            st_out(Q + (size_t)s * nb + ir, o.q);
+            st_row<PLAIN>(P + (size_t)s * nb + ir, o.p);
+            st_row<PLAIN>(Q + (size_t)s * nb + ir, o.q);
         }
         if constexpr (WITH_J) {
             lds_barrier();
@@ -698,11 +714,12 @@ __device__ __forceinline__ void ew_eval(const DevGrid &g, int nstate, int spb, i
     pipelined_states<In, ONE>(sb, se, first, load, proc);
 }
 
-template <int NT, bool PAR, bool WITH_J, bool ONE>
+// PLAIN: plain stores for the rows of P and Q (see st_row).
+template <int NT, bool PAR, bool WITH_J, bool ONE, bool PLAIN = false>
 __global__ void __launch_bounds__(NT)
     k_ew(DevGrid g, int nstate, int spb, int nchunk, int order, const double *__restrict__ vm, const double *__restrict__ va,
          double *__restrict__ P, double *__restrict__ Q, double *__restrict__ J) {
-    ew_eval<NT, PAR, WITH_J, ONE, false>(g, nstate, spb, nchunk, order, vm, va, P, Q, J);
+    ew_eval<NT, PAR, WITH_J, ONE, false, PLAIN>(g, nstate, spb, nchunk, order, vm, va, P, Q, J);
 }
 
 // Injections and J values in CSC order.
@@ -710,7 +727,7 @@ template <int NT, bool PAR, bool ONE>
 __global__ void __launch_bounds__(NT)
     k_ew_csc(DevGrid g, int nstate, int spb, int nchunk, int order, const double *__restrict__ vm,
              const double *__restrict__ va, double *__restrict__ P, double *__restrict__ Q, double *__restrict__ J) {
-    ew_eval<NT, PAR, true, ONE, true>(g, nstate, spb, nchunk, order, vm, va, P, Q, J);
+    ew_eval<NT, PAR, true, ONE, true, false>(g, nstate, spb, nchunk, order, vm, va, P, Q, J);
 }
 
 // ===================================================================
@@ -1072,7 +1089,8 @@ __device__ __forceinline__ double vjp_own(double sum, double vi, double lpi, dou
     return fma(2.0 * vi, fma(lpi, dA, -(lqi * dC)), sum);
 }
 
-template <int NT, bool ONE>
+// PLAIN: plain stores for the gradient rows (see st_row).
+template <int NT, bool ONE, bool PLAIN = false>
 __global__ void __launch_bounds__(NT)
     k_ew_vjp(DevGrid g, int nstate, int spb, int nchunk, int order, const double *__restrict__ vm,
              const double *__restrict__ va, const double *__restrict__ lp, const double *__restrict__ lq,
@@ -1222,8 +1240,8 @@ __global__ void __launch_bounds__(NT)
         const double gm = vjp_own(v, in.vr, in.lpr, in.lqr, dA, dC);
         if (rowt) {
             const size_t so = (size_t)s * nb;
-            st_out(gva + so + ir, a);
-            st_out(gvm + so + ir, gm);
+            st_row<PLAIN>(gva + so + ir, a);
+            st_row<PLAIN>(gvm + so + ir, gm);
         }
     };
     pipelined_states<In, ONE>(sb, se, first, load, proc);
@@ -1653,11 +1671,20 @@ hipError_t launch_nt(const DevGrid &g, const Launch &L, hipStream_t st) {
                                                  : (ntl * nchunk + kXcds - 1) / kXcds * kXcds;
     if (blocks > INT32_MAX) return hipErrorInvalidConfiguration;
     const dim3 grid((unsigned)blocks), block(NT);
+    // Plain row stores for the injections and the adjoint when a tile has at
+    // most eight state chunks (see st_row).
+    const bool plain = !ONE && nchunk <= 8;
     switch (L.kind) {
         case K_EW_S:
-            if (L.has_parallel)
+            if (L.has_parallel && plain)
+                hipLaunchKernelGGL((k_ew<NT, true, false, ONE, !ONE>), grid, block, 0, st, g, L.nstate, spb, nchunk, L.order,
+                                   L.vm, L.va, L.p, L.q, nullptr);
+            else if (L.has_parallel)
                 hipLaunchKernelGGL((k_ew<NT, true, false, ONE>), grid, block, 0, st, g, L.nstate, spb, nchunk, L.order, L.vm, L.va,
                                    L.p, L.q, nullptr);
+            else if (plain)
+                hipLaunchKernelGGL((k_ew<NT, false, false, ONE, !ONE>), grid, block, 0, st, g, L.nstate, spb, nchunk, L.order,
+                                   L.vm, L.va, L.p, L.q, nullptr);
             else
                 hipLaunchKernelGGL((k_ew<NT, false, false, ONE>), grid, block, 0, st, g, L.nstate, spb, nchunk, L.order, L.vm, L.va,
                                    L.p, L.q, nullptr);
@@ -1683,8 +1710,12 @@ hipError_t launch_nt(const DevGrid &g, const Launch &L, hipStream_t st) {
         case K_YB_SJ_CSC:
             return launch_ybus<NT, ONE>(g, L, grid, block, spb, nchunk, st);
         case K_EW_VJP:
-            hipLaunchKernelGGL((k_ew_vjp<NT, ONE>), grid, block, 0, st, g, L.nstate, spb, nchunk, L.order, L.vm, L.va, L.lp, L.lq,
-                               L.gvm, L.gva);
+            if (plain)
+                hipLaunchKernelGGL((k_ew_vjp<NT, ONE, !ONE>), grid, block, 0, st, g, L.nstate, spb, nchunk, L.order, L.vm, L.va,
+                                   L.lp, L.lq, L.gvm, L.gva);
+            else
+                hipLaunchKernelGGL((k_ew_vjp<NT, ONE>), grid, block, 0, st, g, L.nstate, spb, nchunk, L.order, L.vm, L.va, L.lp,
+                                   L.lq, L.gvm, L.gva);
             break;
         default:
             return hipErrorInvalidValue;
