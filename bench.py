@@ -52,7 +52,7 @@ WARM_S = 0.05  # untimed replays before every timed region, seconds
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2302_10736_amd", "csrc", f)
                for f in ("pf_kernels.hip", "pf_math.h", "pf_internal.h", "pf_api.cpp")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_ew_100k_1state_traffic.json")
-HEADLINE_KERNEL = "k_ew<256, false, true, true>"  # element-wise S+J, one state per workgroup
+HEADLINE_KERNEL = "k_ew<256, false, true, true, false>"  # element-wise S+J, one state per workgroup
 COPY_PROBE_DOUBLES = 4 * 1024 * 1024  # 32 MiB read + 32 MiB written by the calibration copy
 
 
@@ -90,7 +90,7 @@ def traffic_from_csv(fetch_csv, write_csv):
         vals = d[names[0]]
         return names[0], sum(vals) / len(vals), len(vals)
 
-    head = lambda n: "k_ew<256, false, true, true>" in n
+    head = lambda n: "k_ew<256, false, true, true, false>" in n
     copy = lambda n: "copy" in n.lower() and "k_ew" not in n
     res = {"kernel": HEADLINE_KERNEL, "kernel_sha256_16": kernel_hash(), "copy_bytes_each_way": 8 * COPY_PROBE_DOUBLES}
     total = 0.0
@@ -452,7 +452,7 @@ def main():
                    "wall_ms_per_step": wall_s / K * 1e3},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": f"k_ew<{tile}, false, true, true>", "algorithmic_bytes_per_launch": abytes,
+                     "kernel": f"k_ew<{tile}, false, true, true, false>", "algorithmic_bytes_per_launch": abytes,
                      "avg_launch_us": avg_launch * 1e6},
     }
 

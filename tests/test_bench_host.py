@@ -38,7 +38,7 @@ def _counter_csv(path, counter, rows):
 
 
 def test_traffic_from_counter_files(tmp_path):
-    head = "void pf::k_ew<256, false, true, true>(pf::DevGrid, int)"
+    head = "void pf::k_ew<256, false, true, true, false>(pf::DevGrid, int)"
     copy = "__amd_rocclr_copyBuffer"
     copy_kib = 8 * bench.COPY_PROBE_DOUBLES / 1024.0
     f = tmp_path / "f.csv"
