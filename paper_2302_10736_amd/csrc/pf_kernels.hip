@@ -1192,12 +1192,10 @@ __global__ void __launch_bounds__(NT)
     // Only waves that hold a row load the row values (uniform per wave, so
     // the other waves skip four loads per state; their values are unused).
     const bool anyrow = (k & ~63) < c.nrows;
+    // The row values go out first: waiting for them (before the barrier of
+    // the state ahead, below) then leaves the remote gathers in flight.
     auto load = [&](int s, In &in) {
         const size_t so = (size_t)s * nb;
-        in.vj = vm[so + j];
-        in.tj = va[so + j];
-        in.lpj = lp[so + j];
-        in.lqj = lq[so + j];
         if (anyrow) {
             in.vr = vm[so + ir];
             in.tr = va[so + ir];
@@ -1206,6 +1204,10 @@ __global__ void __launch_bounds__(NT)
         } else {
             in.vr = in.tr = in.lpr = in.lqr = 0.0;
         }
+        in.vj = vm[so + j];
+        in.tj = va[so + j];
+        in.lpj = lp[so + j];
+        in.lqj = lq[so + j];
     };
     In first;
     load(sb, first);
@@ -1213,14 +1215,20 @@ __global__ void __launch_bounds__(NT)
     const int2 rw = g.row_ew[irr];
     const double dA = g.dA[irr], dC = g.dC[irr];
     const int ra = lo16(rw.x), rz = hi16(rw.x);
-    auto proc = [&](int s, int p, const In &in) {
+    // A state's own-bus values reach its lanes through LDS buffer p (the
+    // state's parity).  With several states per workgroup the row threads
+    // write the next state's values into the other buffer before this
+    // state's barrier, so each state takes one barrier.  Buffer p of either
+    // array is rewritten only after the barrier that follows its last read.
+    auto put_own = [&](int p, const In &in) {
         if (rowt) {
             s_own[p][0][k] = in.vr;
             s_own[p][1][k] = in.tr;
             s_own[p][2][k] = in.lpr;
             s_own[p][3][k] = in.lqr;
         }
-        lds_barrier();
+    };
+    auto record = [&](int p, const In &in) {
         VjpIn x;
         x.vi = s_own[p][0][rowl];
         x.ti = s_own[p][1][rowl];
@@ -1234,7 +1242,8 @@ __global__ void __launch_bounds__(NT)
         vjp_record(x, gb.x, gb.y, grb.x, grb.y, ga, gv);
         s_val[p][0][k] = ga;
         s_val[p][1][k] = gv;
-        lds_barrier();
+    };
+    auto finish = [&](int s, int p, const In &in) {
         double a, v;
         row_sum2(s_val[p][0], s_val[p][1], ra, rz, a, v);
         const double gm = vjp_own(v, in.vr, in.lpr, in.lqr, dA, dC);
@@ -1244,7 +1253,30 @@ __global__ void __launch_bounds__(NT)
             st_row<PLAIN>(gvm + so + ir, gm);
         }
     };
-    pipelined_states<In, ONE>(sb, se, first, load, proc);
+    put_own(0, first);
+    lds_barrier();
+    if constexpr (ONE) {
+        record(0, first);
+        lds_barrier();
+        finish(sb, 0, first);
+    } else {
+        // two states per trip, the next state's loads in flight while a
+        // state is evaluated; an odd count repeats the last state
+        In rb{};
+        for (int s = sb; s < se; s += 2) {
+            const int s1 = min(s + 1, se - 1);
+            load(s1, rb);
+            record(0, first);
+            put_own(1, rb);
+            lds_barrier();
+            finish(s, 0, first);
+            load(min(s + 2, se - 1), first);
+            record(1, rb);
+            put_own(0, first);
+            lds_barrier();
+            finish(s1, 1, rb);
+        }
+    }
 }
 
 // ===================================================================
