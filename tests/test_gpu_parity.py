@@ -168,6 +168,39 @@ def test_determinism_across_runs_and_schedules():
                     assert np.array_equal(ref[k], other[k]), (k, tile, spb, order)
 
 
+def test_injections_and_adjoint_bitwise_across_state_chunks():
+    """The injection and adjoint launches write their row outputs with plain
+    stores when a tile has at most eight state chunks and with streaming
+    stores above that; the adjoint walks a workgroup's states two at a time
+    (an odd count repeats the last).  40 states in chunks of 1, 4, 5, 8 and
+    40 (40, 10, 8, 5 and 1 chunks per tile) give the same bits, on a grid
+    with parallel branches and on one without."""
+    import torch
+    for g in (gridgen.grid_500(), star_grid(120, seed=5, parallel=4)):
+        rng = np.random.default_rng(g.nb)
+        ns = 40
+        vm = rng.uniform(0.9, 1.1, (ns, g.nb))
+        va = rng.normal(0, 0.3, (ns, g.nb))
+        lp, lq = rng.normal(size=vm.shape), rng.normal(size=vm.shape)
+        G = pf.Grid.from_grid(g)
+        v, a, l1, l2 = (to_dev(x) for x in (vm, va, lp, lq))
+        outs = []
+        for spb in (1, 4, 5, 8, 40):
+            G.set_schedule(128, spb, pf.PF_ORDER_AUTO)
+            r = [torch.empty_like(v) for _ in range(4)]
+            pf.pf_injections_elementwise(G, v, a, r[0], r[1])
+            pf.pf_injections_vjp(G, v, a, l1, l2, r[2], r[3])
+            torch.cuda.synchronize()
+            outs.append([x.cpu().numpy() for x in r])
+        for s in (0, 17, 39):
+            o = oracle_all(g, vm[s], va[s], lp[s], lq[s])
+            for k, name in enumerate(("p_ew", "q_ew", "gvm", "gva")):
+                assert rel_err(outs[0][k][s], o[name]) < TOL, (g.nb, s, name)
+        for spb, other in zip((4, 5, 8, 40), outs[1:]):
+            for k in range(4):
+                assert np.array_equal(outs[0][k], other[k]), (g.nb, spb, k)
+
+
 @pytest.mark.parametrize("n_leaf,parallel", [(40, 0), (100, 3), (256, 0), (250, 6), (333, 0), (700, 25)])
 def test_hub_rows_bitwise_across_schedules(n_leaf, parallel):
     """Bus sums run in chunks of 16 terms fixed by the row alone, so a hub row
