@@ -714,9 +714,12 @@ __device__ __forceinline__ void ew_eval(const DevGrid &g, int nstate, int spb, i
     pipelined_states<In, ONE>(sb, se, first, load, proc);
 }
 
-// PLAIN: plain stores for the rows of P and Q (see st_row).
+// PLAIN: plain stores for the rows of P and Q (see st_row).  The
+// injections of several states per workgroup are held to 80 registers
+// (their natural count is a few above), so that six waves fit per SIMD
+// instead of five.
 template <int NT, bool PAR, bool WITH_J, bool ONE, bool PLAIN = false>
-__global__ void __launch_bounds__(NT)
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu((!ONE && !WITH_J) ? 6 : 1, 8)))
     k_ew(DevGrid g, int nstate, int spb, int nchunk, int order, const double *__restrict__ vm, const double *__restrict__ va,
          double *__restrict__ P, double *__restrict__ Q, double *__restrict__ J) {
     ew_eval<NT, PAR, WITH_J, ONE, false, PLAIN>(g, nstate, spb, nchunk, order, vm, va, P, Q, J);
