@@ -461,8 +461,10 @@ def test_uneven_grids_64x4():
 
 
 def test_adjoint_100k_x32_against_oracle_and_fd():
-    """100k buses x 32 states: VJP vs J^T lambda from the oracle Jacobian (sampled
-    states) and vs central differences (h = 1e-7) on 1000 sampled coordinates."""
+    """100k buses x 32 states, the batched workload's launch configuration
+    (automatic schedule): the injections and the VJP against the oracle on
+    sampled states (the VJP as J^T lambda of the oracle Jacobian), and the VJP
+    against central differences (h = 1e-7) on 1000 sampled coordinates."""
     import torch
     g = gridgen.grid_100k()
     B = 32
@@ -473,11 +475,17 @@ def test_adjoint_100k_x32_against_oracle_and_fd():
     gvm = torch.empty_like(vm_d)
     gva = torch.empty_like(vm_d)
     pf.pf_injections_vjp(G, vm_d, va_d, lp_d, lq_d, gvm, gva)
+    p_all, q_all = torch.empty_like(vm_d), torch.empty_like(vm_d)
+    pf.pf_injections_elementwise(G, vm_d, va_d, p_all, q_all)
     torch.cuda.synchronize()
     gvm_h, gva_h = gvm.cpu().numpy(), gva.cpu().numpy()
+    p_h, q_h = p_all.cpu().numpy(), q_all.cpu().numpy()
     yb = oracle.ybus(g)
     pat = oracle.jac_pattern(yb)
     for s in (0, 13, 31):
+        op, oq = oracle.inject_ew(g, vm[s], va[s])
+        assert rel_err(p_h[s], op) <= TOL
+        assert rel_err(q_h[s], oq) <= TOL
         jv = oracle.jac_ybus(yb, vm[s], va[s], pat)
         ovm, ova = oracle.vjp(g.nb, pat, jv, lp[s], lq[s])
         assert rel_err(gvm_h[s], ovm) <= TOL
