@@ -299,6 +299,54 @@ def test_graph_replays_match_eager_calls():
     assert e.value.code == pf.PF_ESTATE
 
 
+def test_graph_replays_several_states_per_workgroup():
+    """Injections, S+J and the VJP with 4 states per workgroup (the
+    multi-state kernels; the injections and the VJP with plain row stores),
+    recorded once and replayed several times with the inputs changed in
+    between; every replay equals the eager calls bit for bit."""
+    import torch
+    g = gridgen.grid_500()
+    rng = np.random.default_rng(11)
+    ns = 10
+    G = pf.Grid.from_grid(g)
+    G.set_schedule(128, 4, pf.PF_ORDER_AUTO)
+    vm = to_dev(rng.uniform(0.9, 1.1, (ns, g.nb)))
+    va = to_dev(rng.normal(0, 0.3, (ns, g.nb)))
+    lp, lq = to_dev(rng.normal(size=(ns, g.nb))), to_dev(rng.normal(size=(ns, g.nb)))
+    z = lambda *sh: torch.zeros(*sh, dtype=torch.float64, device="cuda:0")
+    out = {k: z(ns, g.nb) for k in ("p", "q", "p2", "q2", "gvm", "gva")}
+    jv = z(ns, G.nnz_j)
+    ops = [
+        dict(op=pf.PF_OP_INJECTIONS, method=pf.PF_METHOD_ELEMENTWISE, vm=vm, va=va, out_a=out["p"], out_b=out["q"]),
+        dict(op=pf.PF_OP_JACOBIAN, method=pf.PF_METHOD_ELEMENTWISE, vm=vm, va=va, out_a=out["p2"], out_b=out["q2"],
+             jval=jv),
+        dict(op=pf.PF_OP_VJP, vm=vm, va=va, lam_p=lp, lam_q=lq, out_a=out["gvm"], out_b=out["gva"]),
+    ]
+    gr = pf.Graph(G, ops)
+    for rep in range(4):
+        for t in list(out.values()) + [jv]:
+            t.fill_(float("nan"))
+        gr.launch()
+        torch.cuda.synchronize()
+        e = {k: z(ns, g.nb) for k in out}
+        je = z(ns, G.nnz_j)
+        pf.pf_injections_elementwise(G, vm, va, e["p"], e["q"])
+        pf.pf_jacobian_values(G, pf.PF_METHOD_ELEMENTWISE, vm, va, e["p2"], e["q2"], je)
+        pf.pf_injections_vjp(G, vm, va, lp, lq, e["gvm"], e["gva"])
+        torch.cuda.synchronize()
+        for k in out:
+            assert np.array_equal(out[k].cpu().numpy(), e[k].cpu().numpy()), (rep, k)
+        assert np.array_equal(jv.cpu().numpy(), je.cpu().numpy()), rep
+        vm.mul_(1.0 + 0.01 * (rep + 1))
+        va.add_(0.02)
+    o = oracle_all(g, vm[3].cpu().numpy(), va[3].cpu().numpy(), lp[3].cpu().numpy(), lq[3].cpu().numpy())
+    gr.launch()
+    torch.cuda.synchronize()
+    for k, name in (("p", "p_ew"), ("q", "q_ew"), ("gvm", "gvm"), ("gva", "gva")):
+        assert rel_err(out[k][3].cpu().numpy(), o[name]) <= TOL, k
+    gr.close()
+
+
 def test_graph_multigrid_and_baselines():
     """A recorded sequence on a freshly built multi-grid handle (no evaluation
     call before recording) with several states: fused element-wise and Ybus
